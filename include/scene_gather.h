@@ -1,0 +1,176 @@
+/*
+ * scene_gather.h -- C ABI of the MI355X (gfx950) scene-space gather + filter library.
+ *
+ * Method: Klose, Wang, Bazin, Magnor, Sorkine-Hornung, "Sampling Based
+ * Scene-Space Video Processing" (ACM TOG). For every output pixel p of frame f
+ * the library gathers a sample set S^f(p) of source pixels from the frames of a
+ * temporal window that observe the same scene point (Sec. 4), then reduces each
+ * set to an output colour with a weighted mean (Sec. 5, Eq. 3 / Eq. 4).
+ *
+ * Conventions used by every entry point:
+ *   - pixel (x, y): x = column, y = row, pixel centres at integer coordinates;
+ *     flat pixel index y * W + x; planes are row-major [frame][row][column];
+ *   - intrinsics K = [[fx, 0, cx], [0, fy, cy], [0, 0, 1]];
+ *   - camera frame x right, y down, z forward; depth is z-depth;
+ *   - cam_to_world[f] is the rigid 4x4 camera-to-world matrix C^f (row-major,
+ *     float64, last row 0 0 0 1);
+ *   - colour is on the 0-1 scale (the paper's 0-255 divided by 255);
+ *   - binary16 values are passed as their 16-bit patterns (uint16_t).
+ *
+ * Memory ownership: every device buffer is allocated by the caller and only
+ * borrowed for the duration of the work enqueued on `stream`. The library
+ * allocates no device memory. `stream` is a hipStream_t (NULL = the default
+ * stream); all GPU work is enqueued asynchronously on it.
+ *
+ * Errors: argument checks run on the host before any GPU work and return
+ * synchronously (SG_E_INVALID, SG_E_UNSUPPORTED). A failing HIP call returns
+ * SG_E_HIP. Conditions found by kernels (sample arena too small, count/scatter
+ * disagreement) are OR-ed into the caller's device status word as SG_FLAG_*
+ * bits; read it after synchronising the stream. No C++ exception crosses this
+ * interface.
+ */
+#ifndef SCENE_GATHER_H
+#define SCENE_GATHER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_VERSION 1
+
+/* Limits. Sample ids pack (J - f + w) into 10 bits and the source pixel index
+ * into 22 bits, so W * H <= 2^22 and 2w + 1 <= 1024. */
+#define SG_MAX_PIXELS_PER_FRAME (1 << 22)
+#define SG_MAX_WINDOW 511
+#define SG_MAX_RADIUS 3
+#define SG_ID_SHIFT 22
+
+/* Device status bits (OR-ed into sg_sample_sets.status). */
+#define SG_FLAG_CAPACITY 1u      /* a pixel's records would pass `capacity`; its records were not written */
+#define SG_FLAG_INCONSISTENT 2u  /* scatter found a different count than the count pass (planes changed?) */
+
+typedef enum sg_status {
+  SG_OK = 0,
+  SG_E_INVALID = 1,     /* null pointer, size out of range, non-finite parameter, workspace too small */
+  SG_E_CAPACITY = 2,    /* reserved for callers mapping SG_FLAG_CAPACITY to a status */
+  SG_E_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+  SG_E_UNSUPPORTED = 4  /* outside the limits above */
+} sg_status;
+
+/* A staged clip: the stored input planes of N frames of W x H pixels.
+ * rgbd : device [N][H][W][4] binary16 (r, g, b, z-depth); the 4th channel is the
+ *        same binary16 depth as `depth` (scene_stage writes both).
+ * depth: device [N][H][W] binary16 z-depth (read alone by the count pass).
+ * cam_to_world: device [N][4][4] float64.                                    */
+typedef struct sg_clip {
+  int32_t width;
+  int32_t height;
+  int32_t num_frames;
+  int32_t reserved;
+  const uint16_t* rgbd;
+  const uint16_t* depth;
+  const double* cam_to_world;
+  double fx, fy, cx, cy;
+} sg_clip;
+
+/* Gather parameters (Sec. 4).
+ * window: w >= 0; source frames J in [max(0, f - w), min(N - 1, f + w)], f included.
+ * radius: r in [0, SG_MAX_RADIUS]; the l x l block with l = 2r + 1 (the paper uses l = 3).
+ * tol   : tau > 0; q is kept when |D^J(q) - z| <= tau * z, z the predicted depth in J.
+ * z_near: > 0; output pixels with depth <= z_near (or non-finite) get an empty set,
+ *         and frames where the point lies at z <= z_near are skipped (near plane, Sec. 4 Eq. 1). */
+typedef struct sg_gather_params {
+  int32_t window;
+  int32_t radius;
+  float tol;
+  float z_near;
+} sg_gather_params;
+
+/* Sample sets of the P = (f1 - f0) * H * W output pixels of frames [f0, f1), in CSR form.
+ * offsets : device [P + 1] int64; the set of output pixel i (i = (f - f0) * H * W + y * W + x)
+ *           is records [offsets[i], offsets[i + 1]); offsets[0] = 0, offsets[P] = total.
+ * ids     : device [capacity] uint32; id = ((J - f + w) << 22) | (q_y * W + q_x).
+ * crho    : device [capacity][4] binary16 (r, g, b, rho), rho = (D^J(q) - z) / z.
+ * Within a set, records are in ascending id (J ascending, block row-major).
+ * status  : device uint32 word; scene_gather_count clears it, kernels OR SG_FLAG_* bits. */
+typedef struct sg_sample_sets {
+  int64_t* offsets;
+  uint32_t* ids;
+  uint16_t* crho;
+  int64_t capacity;
+  uint32_t* status;
+} sg_sample_sets;
+
+/* Filter weights (Sec. 5.1 Eq. 4, diagonal Gaussian around the reference sample):
+ * w(s) = exp(-rho^2 / 2 sigma_d^2) * exp(-|c_s - c_ref|^2 / 2 sigma_c^2) * exp(-(J - f)^2 / 2 sigma_t^2),
+ * c_ref = I^f(p). A sigma of +INFINITY disables its term. */
+typedef struct sg_filter_params {
+  float sigma_d;
+  float sigma_c;
+  float sigma_t;
+  float reserved;
+} sg_filter_params;
+
+/* Library version (SG_VERSION). */
+int32_t sg_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* sg_status_string(int32_t status);
+
+/* Stage the stored input planes (Sec. 3: the colour of each pixel and its
+ * depth D^f(p) are the inputs of sampling).
+ * rgb_u8  : device [n_pixels][3] uint8 colour on the 0-255 scale.
+ * depth   : device [n_pixels] float32 z-depth.
+ * rgbd    : device [n_pixels][4] binary16 out: (c/255 rounded to nearest even, ..., depth).
+ * depth16 : device [n_pixels] binary16 out: depth rounded to nearest even (inf above 65504).
+ * n_pixels >= 0 (0 enqueues nothing). */
+sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int64_t n_pixels,
+                      uint16_t* rgbd, uint16_t* depth16, void* stream);
+
+/* Workspace bytes needed by scene_gather_count / scene_gather_scatter / scene_gather
+ * for output frames [f0, f1): relative camera maps for every (f, J) pair plus scan
+ * partials. Pure host computation. */
+sg_status scene_gather_workspace_size(const sg_clip* clip, int32_t f0, int32_t f1,
+                                      const sg_gather_params* params, size_t* bytes);
+
+/* Gather pass 1 (Sec. 4, parallel over output pixels): computes, in float64 on the
+ * device, T_{J<-f} = (C^J)^{-1} C^f for every (f, J) pair (exact identity for J = f),
+ * folds it with K into float32 maps M = K R K^{-1}, k = K t kept in `workspace`,
+ * counts each output pixel's members, and scans the counts into sets->offsets.
+ * Clears *sets->status. The total is sets->offsets[P] on the device; a caller may
+ * synchronise and read it to size the arena. ids/crho/capacity are not used. */
+sg_status scene_gather_count(const sg_clip* clip, int32_t f0, int32_t f1,
+                             const sg_gather_params* params, sg_sample_sets* sets,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gather pass 2: same traversal as pass 1 (same arithmetic, bit for bit), writing
+ * each member's record at its CSR slot. Needs the offsets and the workspace left by
+ * scene_gather_count with identical arguments. A pixel whose records would pass
+ * `capacity` writes none and sets SG_FLAG_CAPACITY. */
+sg_status scene_gather_scatter(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, sg_sample_sets* sets,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* scene_gather_count followed by scene_gather_scatter, enqueued without any host
+ * synchronisation (the caller sizes `capacity` in advance). */
+sg_status scene_gather(const sg_clip* clip, int32_t f0, int32_t f1,
+                       const sg_gather_params* params, sg_sample_sets* sets,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Filter (Sec. 5 Eq. 3 with the weight above): out_rgb device [P][3] float32 with
+ * O(p) = sum w(s) c_s / sum w(s) over the set of p, or I^f(p) (the stored colour of
+ * the output pixel) when the set is empty. `window` must be the w used to gather
+ * (it decodes J - f from the ids). Records are read only below sets->capacity: a
+ * pixel whose set did not fit the arena (SG_FLAG_CAPACITY) gets NaN. */
+sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                       const sg_sample_sets* sets, const sg_filter_params* params,
+                       float* out_rgb, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCENE_GATHER_H */

@@ -1,0 +1,233 @@
+"""Python binding of the MI355X scene-space gather + filter library.
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the gather and filter runs in the HIP
+kernels of libscenegather.so (see include/scene_gather.h for the contract).
+There is no CPU fallback: the library must be built, and every tensor passed
+in must live on the GPU.
+
+The functions carry the names of the C entry points they call.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to by soname)
+
+from . import _native
+
+_lib = _native.load()
+
+SG_ID_SHIFT = _native.SG_ID_SHIFT
+SG_FLAG_CAPACITY = _native.SG_FLAG_CAPACITY
+SG_FLAG_INCONSISTENT = _native.SG_FLAG_INCONSISTENT
+
+
+class SceneGatherError(RuntimeError):
+    pass
+
+
+def _check(status: int, what: str) -> None:
+    if status != _native.SG_OK:
+        msg = _lib.sg_status_string(int(status)).decode()
+        raise SceneGatherError(f"{what}: {msg} (status {status})")
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need_gpu(t: torch.Tensor, name: str, dtype=None) -> None:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise SceneGatherError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise SceneGatherError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise SceneGatherError(f"{name} must be contiguous")
+
+
+def version() -> int:
+    return int(_lib.sg_version())
+
+
+@dataclass
+class StagedClip:
+    """Stored input planes of a clip (all on the GPU)."""
+    rgbd: torch.Tensor          # [N, H, W, 4] float16: r, g, b (0-1), z-depth
+    depth: torch.Tensor         # [N, H, W] float16 z-depth
+    cam_to_world: torch.Tensor  # [N, 4, 4] float64
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    @property
+    def num_frames(self) -> int:
+        return self.rgbd.shape[0]
+
+    @property
+    def height(self) -> int:
+        return self.rgbd.shape[1]
+
+    @property
+    def width(self) -> int:
+        return self.rgbd.shape[2]
+
+    def c_struct(self) -> _native.SgClip:
+        return _native.SgClip(self.width, self.height, self.num_frames, 0,
+                              self.rgbd.data_ptr(), self.depth.data_ptr(), self.cam_to_world.data_ptr(),
+                              float(self.fx), float(self.fy), float(self.cx), float(self.cy))
+
+
+@dataclass
+class GatherParams:
+    window: int
+    radius: int = 1
+    tol: float = 0.01
+    z_near: float = 0.01
+
+    def c_struct(self) -> _native.SgGatherParams:
+        return _native.SgGatherParams(int(self.window), int(self.radius), float(self.tol), float(self.z_near))
+
+
+@dataclass
+class SampleSets:
+    """CSR sample sets of output frames [f0, f1) (device tensors)."""
+    f0: int
+    f1: int
+    window: int
+    offsets: torch.Tensor   # [P + 1] int64
+    ids: torch.Tensor       # [capacity] int32 (bit pattern of the uint32 ids)
+    crho: torch.Tensor      # [capacity, 4] float16: r, g, b, rho
+    status: torch.Tensor    # [1] int32 (bit pattern of the uint32 status word)
+
+    @property
+    def capacity(self) -> int:
+        return self.ids.shape[0]
+
+    def c_struct(self) -> _native.SgSampleSets:
+        return _native.SgSampleSets(self.offsets.data_ptr(), self.ids.data_ptr() if self.capacity else None,
+                                    self.crho.data_ptr() if self.capacity else None, int(self.capacity),
+                                    self.status.data_ptr())
+
+    def total(self) -> int:
+        """Number of records (synchronises with the GPU)."""
+        return int(self.offsets[-1].item())
+
+    def flags(self) -> int:
+        return int(self.status.item()) & 0xFFFFFFFF
+
+    def check(self) -> None:
+        fl = self.flags()
+        if fl & SG_FLAG_CAPACITY:
+            raise SceneGatherError("sample arena too small (SG_FLAG_CAPACITY)")
+        if fl & SG_FLAG_INCONSISTENT:
+            raise SceneGatherError("count and scatter passes disagree (SG_FLAG_INCONSISTENT)")
+
+
+def scene_stage(rgb_u8: torch.Tensor, depth: torch.Tensor, cam_to_world: torch.Tensor,
+                fx: float, fy: float, cx: float, cy: float) -> StagedClip:
+    """Stage u8 RGB [N,H,W,3] and float32 depth [N,H,W] into binary16 planes."""
+    _need_gpu(rgb_u8, "rgb_u8", torch.uint8)
+    _need_gpu(depth, "depth", torch.float32)
+    _need_gpu(cam_to_world, "cam_to_world", torch.float64)
+    n, h, w, c = rgb_u8.shape
+    if c != 3 or tuple(depth.shape) != (n, h, w) or tuple(cam_to_world.shape) != (n, 4, 4):
+        raise SceneGatherError("shape mismatch between rgb_u8 [N,H,W,3], depth [N,H,W], cam_to_world [N,4,4]")
+    rgbd = torch.empty((n, h, w, 4), dtype=torch.float16, device=rgb_u8.device)
+    d16 = torch.empty((n, h, w), dtype=torch.float16, device=rgb_u8.device)
+    _check(_lib.scene_stage(rgb_u8.data_ptr(), depth.data_ptr(), n * h * w, rgbd.data_ptr(), d16.data_ptr(),
+                            _stream_handle()), "scene_stage")
+    return StagedClip(rgbd, d16, cam_to_world, fx, fy, cx, cy)
+
+
+def scene_gather_workspace_size(clip: StagedClip, f0: int, f1: int, params: GatherParams) -> int:
+    out = ctypes.c_size_t(0)
+    cc, pp = clip.c_struct(), params.c_struct()
+    _check(_lib.scene_gather_workspace_size(ctypes.byref(cc), f0, f1, ctypes.byref(pp), ctypes.byref(out)),
+           "scene_gather_workspace_size")
+    return int(out.value)
+
+
+def alloc_workspace(clip: StagedClip, f0: int, f1: int, params: GatherParams) -> torch.Tensor:
+    nbytes = scene_gather_workspace_size(clip, f0, f1, params)
+    return torch.empty(nbytes, dtype=torch.uint8, device=clip.rgbd.device)
+
+
+def alloc_sets(clip: StagedClip, f0: int, f1: int, window: int, capacity: int) -> SampleSets:
+    dev = clip.rgbd.device
+    p = (f1 - f0) * clip.height * clip.width
+    return SampleSets(f0, f1, window,
+                      torch.empty(p + 1, dtype=torch.int64, device=dev),
+                      torch.empty(capacity, dtype=torch.int32, device=dev),
+                      torch.empty((capacity, 4), dtype=torch.float16, device=dev),
+                      torch.zeros(1, dtype=torch.int32, device=dev))
+
+
+def _call_gather(fn, name, clip, f0, f1, params, sets, ws):
+    _need_gpu(ws, "workspace", torch.uint8)
+    cc, pp, ss = clip.c_struct(), params.c_struct(), sets.c_struct()
+    _check(fn(ctypes.byref(cc), f0, f1, ctypes.byref(pp), ctypes.byref(ss), ws.data_ptr(), ws.numel(),
+              _stream_handle()), name)
+
+
+def scene_gather_count(clip: StagedClip, f0: int, f1: int, params: GatherParams, sets: SampleSets,
+                       ws: torch.Tensor) -> None:
+    _call_gather(_lib.scene_gather_count, "scene_gather_count", clip, f0, f1, params, sets, ws)
+
+
+def scene_gather_scatter(clip: StagedClip, f0: int, f1: int, params: GatherParams, sets: SampleSets,
+                         ws: torch.Tensor) -> None:
+    _call_gather(_lib.scene_gather_scatter, "scene_gather_scatter", clip, f0, f1, params, sets, ws)
+
+
+def scene_gather(clip: StagedClip, f0: int, f1: int, params: GatherParams, capacity: int | None = None,
+                 sets: SampleSets | None = None, ws: torch.Tensor | None = None) -> SampleSets:
+    """Gather the sample sets of output frames [f0, f1).
+
+    capacity None: count, synchronise, size the arena exactly, scatter.
+    Otherwise the arena holds `capacity` records and the call never synchronises;
+    check `sets.check()` afterwards.
+    """
+    if ws is None:
+        ws = alloc_workspace(clip, f0, f1, params)
+    if capacity is None:
+        tmp = sets if sets is not None else alloc_sets(clip, f0, f1, params.window, 0)
+        scene_gather_count(clip, f0, f1, params, tmp, ws)
+        total = tmp.total()
+        if sets is None or sets.capacity < total:
+            sets = alloc_sets(clip, f0, f1, params.window, total)
+            sets.offsets.copy_(tmp.offsets)
+            sets.status.copy_(tmp.status)
+        scene_gather_scatter(clip, f0, f1, params, sets, ws)
+        return sets
+    if sets is None:
+        sets = alloc_sets(clip, f0, f1, params.window, capacity)
+    _call_gather(_lib.scene_gather, "scene_gather", clip, f0, f1, params, sets, ws)
+    return sets
+
+
+@dataclass
+class FilterParams:
+    sigma_d: float = 0.01
+    sigma_c: float = math.inf
+    sigma_t: float = math.inf
+
+    def c_struct(self) -> _native.SgFilterParams:
+        return _native.SgFilterParams(float(self.sigma_d), float(self.sigma_c), float(self.sigma_t), 0.0)
+
+
+def scene_filter(clip: StagedClip, sets: SampleSets, params: FilterParams, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Weighted mean of each set -> [f1 - f0, H, W, 3] float32."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    cc, ss, pp = clip.c_struct(), sets.c_struct(), params.c_struct()
+    _check(_lib.scene_filter(ctypes.byref(cc), sets.f0, sets.f1, sets.window, ctypes.byref(ss), ctypes.byref(pp),
+                             out.data_ptr(), _stream_handle()), "scene_filter")
+    return out

@@ -1,0 +1,77 @@
+"""ctypes declarations of the C ABI in include/scene_gather.h.
+
+Loads the in-tree libscenegather.so. There is no fallback: if the library is
+missing or fails to load, import of the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libscenegather.so")
+
+SG_OK, SG_E_INVALID, SG_E_CAPACITY, SG_E_HIP, SG_E_UNSUPPORTED = 0, 1, 2, 3, 4
+SG_FLAG_CAPACITY, SG_FLAG_INCONSISTENT = 1, 2
+SG_ID_SHIFT = 22
+SG_MAX_WINDOW = 511
+SG_MAX_RADIUS = 3
+
+c_void_p = ctypes.c_void_p
+
+
+class SgClip(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("num_frames", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("rgbd", c_void_p), ("depth", c_void_p), ("cam_to_world", c_void_p),
+        ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+    ]
+
+
+class SgGatherParams(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("tol", ctypes.c_float), ("z_near", ctypes.c_float)]
+
+
+class SgSampleSets(ctypes.Structure):
+    _fields_ = [("offsets", c_void_p), ("ids", c_void_p), ("crho", c_void_p),
+                ("capacity", ctypes.c_int64), ("status", c_void_p)]
+
+
+class SgFilterParams(ctypes.Structure):
+    _fields_ = [("sigma_d", ctypes.c_float), ("sigma_c", ctypes.c_float),
+                ("sigma_t", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+# name -> (restype, argtypes); every function declared in include/scene_gather.h
+SIGNATURES = {
+    "sg_version": (ctypes.c_int32, []),
+    "sg_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "scene_stage": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p]),
+    "scene_gather_workspace_size": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.POINTER(SgGatherParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "scene_gather_count": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                           c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_gather_scatter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                             c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_gather": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                     c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(SgSampleSets), ctypes.POINTER(SgFilterParams),
+                                     c_void_p, c_void_p]),
+}
+
+
+def load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run `python -m paper_2102_03011_amd.build`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib

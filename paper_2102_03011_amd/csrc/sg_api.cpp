@@ -1,0 +1,214 @@
+// C entry points: host-side argument checks (before any GPU work), workspace
+// layout, and the enqueue order of the gather/filter kernels.
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "scene_gather.h"
+#include "sg_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+sg_status check_clip(const sg_clip* c, bool need_depth) {
+  if (c == nullptr) return SG_E_INVALID;
+  if (c->width <= 0 || c->height <= 0 || c->num_frames <= 0) return SG_E_INVALID;
+  if (c->rgbd == nullptr || c->cam_to_world == nullptr) return SG_E_INVALID;
+  if (need_depth && c->depth == nullptr) return SG_E_INVALID;
+  if (!isfinite(c->fx) || !isfinite(c->fy) || c->fx == 0.0 || c->fy == 0.0) return SG_E_INVALID;
+  if (!isfinite(c->cx) || !isfinite(c->cy)) return SG_E_INVALID;
+  if (static_cast<int64_t>(c->width) * c->height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;
+  if (c->num_frames > 65535) return SG_E_UNSUPPORTED;
+  return SG_OK;
+}
+
+sg_status check_range(const sg_clip* c, int32_t f0, int32_t f1) {
+  if (f0 < 0 || f1 <= f0 || f1 > c->num_frames) return SG_E_INVALID;
+  return SG_OK;
+}
+
+sg_status check_params(const sg_gather_params* p) {
+  if (p == nullptr) return SG_E_INVALID;
+  if (p->window < 0 || p->radius < 0) return SG_E_INVALID;
+  if (!finite_pos(p->tol) || !finite_pos(p->z_near)) return SG_E_INVALID;
+  if (p->window > SG_MAX_WINDOW || p->radius > SG_MAX_RADIUS) return SG_E_UNSUPPORTED;
+  return SG_OK;
+}
+
+struct Layout {
+  size_t rel_off, rel_bytes, part_off, part_bytes, total;
+};
+
+Layout layout(const sg_clip* c, int32_t f0, int32_t f1, const sg_gather_params* p) {
+  Layout l{};
+  const size_t n_out = static_cast<size_t>(f1 - f0);
+  const size_t n_pix = n_out * static_cast<size_t>(c->width) * static_cast<size_t>(c->height);
+  l.rel_off = 0;
+  l.rel_bytes = align_up(n_out * (2 * static_cast<size_t>(p->window) + 1) * sg::kRelStride * sizeof(float));
+  l.part_off = l.rel_off + l.rel_bytes;
+  const size_t nb = (n_pix + sg::kScanTile - 1) / sg::kScanTile;
+  l.part_bytes = align_up((nb + 1) * sizeof(int64_t));
+  l.total = l.part_off + l.part_bytes;
+  return l;
+}
+
+sg_status hip_status(hipError_t e) { return e == hipSuccess ? SG_OK : SG_E_HIP; }
+
+sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                  sg_sample_sets* sets, void* ws, size_t ws_bytes, bool need_arena,
+                  sg::GatherJob* jb) {
+  sg_status s = check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if ((s = check_params(params)) != SG_OK) return s;
+  if (sets == nullptr || sets->offsets == nullptr || sets->status == nullptr) return SG_E_INVALID;
+  if (need_arena && (sets->capacity < 0 || (sets->capacity > 0 && (sets->ids == nullptr || sets->crho == nullptr))))
+    return SG_E_INVALID;
+  if (ws == nullptr) return SG_E_INVALID;
+  const Layout l = layout(clip, f0, f1, params);
+  if (ws_bytes < l.total) return SG_E_INVALID;
+  char* base = static_cast<char*>(ws);
+  jb->width = clip->width;
+  jb->height = clip->height;
+  jb->n_frames = clip->num_frames;
+  jb->f0 = f0;
+  jb->n_out = f1 - f0;
+  jb->w = params->window;
+  jb->radius = params->radius;
+  jb->tol = params->tol;
+  jb->z_near = params->z_near;
+  jb->fx = clip->fx;
+  jb->fy = clip->fy;
+  jb->cx = clip->cx;
+  jb->cy = clip->cy;
+  jb->c2w = clip->cam_to_world;
+  jb->rgbd = clip->rgbd;
+  jb->depth = clip->depth;
+  jb->rel = reinterpret_cast<float*>(base + l.rel_off);
+  jb->partial = reinterpret_cast<int64_t*>(base + l.part_off);
+  jb->offsets = sets->offsets;
+  jb->ids = sets->ids;
+  jb->crho = sets->crho;
+  jb->capacity = sets->capacity;
+  jb->status = sets->status;
+  return SG_OK;
+}
+
+sg_status run_count(const sg::GatherJob& jb, hipStream_t st) {
+  sg_status s = hip_status(sg::launch_pose_prep(jb, st));
+  if (s != SG_OK) return s;
+  if ((s = hip_status(sg::launch_count(jb, st))) != SG_OK) return s;
+  const int64_t n = static_cast<int64_t>(jb.n_out) * jb.width * jb.height;
+  return hip_status(sg::launch_scan(jb.offsets, n, jb.partial, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sg_version(void) { return SG_VERSION; }
+
+const char* sg_status_string(int32_t status) {
+  switch (status) {
+    case SG_OK: return "ok";
+    case SG_E_INVALID: return "invalid argument";
+    case SG_E_CAPACITY: return "sample arena capacity exceeded";
+    case SG_E_HIP: return "HIP runtime error";
+    case SG_E_UNSUPPORTED: return "outside supported limits";
+    default: return "unknown status";
+  }
+}
+
+sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int64_t n_pixels, uint16_t* rgbd,
+                      uint16_t* depth16, void* stream) {
+  if (n_pixels < 0) return SG_E_INVALID;
+  if (n_pixels > 0 && (rgb_u8 == nullptr || depth == nullptr || rgbd == nullptr || depth16 == nullptr))
+    return SG_E_INVALID;
+  if (n_pixels > (static_cast<int64_t>(1) << 40)) return SG_E_UNSUPPORTED;
+  return hip_status(sg::launch_stage(rgb_u8, depth, n_pixels, rgbd, depth16,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+sg_status scene_gather_workspace_size(const sg_clip* clip, int32_t f0, int32_t f1,
+                                      const sg_gather_params* params, size_t* bytes) {
+  if (bytes == nullptr) return SG_E_INVALID;
+  sg_status s = check_clip(clip, false);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if ((s = check_params(params)) != SG_OK) return s;
+  *bytes = layout(clip, f0, f1, params).total;
+  return SG_OK;
+}
+
+sg_status scene_gather_count(const sg_clip* clip, int32_t f0, int32_t f1,
+                             const sg_gather_params* params, sg_sample_sets* sets, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+  sg::GatherJob jb{};
+  sg_status s = prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, false, &jb);
+  if (s != SG_OK) return s;
+  return run_count(jb, static_cast<hipStream_t>(stream));
+}
+
+sg_status scene_gather_scatter(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, sg_sample_sets* sets,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+  sg::GatherJob jb{};
+  sg_status s = prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, true, &jb);
+  if (s != SG_OK) return s;
+  return hip_status(sg::launch_scatter(jb, static_cast<hipStream_t>(stream)));
+}
+
+sg_status scene_gather(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                       sg_sample_sets* sets, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+  sg::GatherJob jb{};
+  sg_status s = prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, true, &jb);
+  if (s != SG_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = run_count(jb, st)) != SG_OK) return s;
+  return hip_status(sg::launch_scatter(jb, st));
+}
+
+sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                       const sg_sample_sets* sets, const sg_filter_params* params, float* out_rgb,
+                       void* stream) {
+  sg_status s = check_clip(clip, false);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if (window < 0) return SG_E_INVALID;
+  if (window > SG_MAX_WINDOW) return SG_E_UNSUPPORTED;
+  if (sets == nullptr || sets->offsets == nullptr || params == nullptr || out_rgb == nullptr)
+    return SG_E_INVALID;
+  const float sd = params->sigma_d, sc = params->sigma_c, stt = params->sigma_t;
+  // each sigma must be > 0 (+inf allowed, disabling its term)
+  if (!(sd > 0.0f) || !(sc > 0.0f) || !(stt > 0.0f)) return SG_E_INVALID;
+  const bool use_c = isfinite(sc), use_t = isfinite(stt);
+  if (sets->capacity < 0 || (sets->capacity > 0 && sets->crho == nullptr)) return SG_E_INVALID;
+  if (use_t && sets->capacity > 0 && sets->ids == nullptr) return SG_E_INVALID;
+  const double log2e = 1.4426950408889634;
+  sg::FilterJob fj{};
+  fj.width = clip->width;
+  fj.height = clip->height;
+  fj.f0 = f0;
+  fj.w = window;
+  fj.n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
+  fj.rgbd = clip->rgbd;
+  fj.offsets = sets->offsets;
+  fj.ids = sets->ids;
+  fj.crho = sets->crho;
+  fj.capacity = sets->capacity;
+  fj.a_d = isfinite(sd) ? static_cast<float>(-log2e / (2.0 * sd * static_cast<double>(sd))) : 0.0f;
+  fj.a_c = use_c ? static_cast<float>(-log2e / (2.0 * sc * static_cast<double>(sc))) : 0.0f;
+  fj.a_t = use_t ? static_cast<float>(-log2e / (2.0 * stt * static_cast<double>(stt))) : 0.0f;
+  fj.use_colour = use_c;
+  fj.use_time = use_t;
+  fj.out = out_rgb;
+  return hip_status(sg::launch_filter(fj, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

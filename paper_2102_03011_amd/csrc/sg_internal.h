@@ -1,0 +1,58 @@
+// Internal declarations shared by the C entry points and the kernel launchers.
+#ifndef SG_INTERNAL_H
+#define SG_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "scene_gather.h"
+
+namespace sg {
+
+constexpr int kRelStride = 16;    // floats per (output frame, source frame) map record
+constexpr int kTileW = 64;        // gather tile: one wave per 64-pixel row segment
+constexpr int kTileH = 4;         // four waves per workgroup
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = 4096;   // elements per scan block (16 per thread)
+constexpr int kGroup = 16;        // filter lanes per output pixel
+
+struct GatherJob {
+  int width, height, n_frames, f0, n_out, w, radius;
+  float tol, z_near;
+  double fx, fy, cx, cy;
+  const double* c2w;
+  const uint16_t* rgbd;
+  const uint16_t* depth;
+  float* rel;          // workspace: n_out * (2w+1) * kRelStride floats
+  int64_t* partial;    // workspace: scan partials
+  int64_t* offsets;
+  uint32_t* ids;
+  uint16_t* crho;
+  int64_t capacity;
+  uint32_t* status;
+};
+
+struct FilterJob {
+  int width, height, f0, w;
+  int64_t n_pix;
+  const uint16_t* rgbd;
+  const int64_t* offsets;
+  const uint32_t* ids;
+  const uint16_t* crho;
+  int64_t capacity;
+  float a_d, a_c, a_t;
+  bool use_colour, use_time;
+  float* out;
+};
+
+hipError_t launch_stage(const uint8_t* rgb, const float* depth, int64_t n, uint16_t* rgbd,
+                        uint16_t* depth16, hipStream_t st);
+hipError_t launch_pose_prep(const GatherJob& jb, hipStream_t st);
+hipError_t launch_count(const GatherJob& jb, hipStream_t st);
+hipError_t launch_scan(int64_t* offsets, int64_t n, int64_t* partial, hipStream_t st);
+hipError_t launch_scatter(const GatherJob& jb, hipStream_t st);
+hipError_t launch_filter(const FilterJob& fj, hipStream_t st);
+
+}  // namespace sg
+
+#endif

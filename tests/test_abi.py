@@ -1,0 +1,151 @@
+"""The C ABI on the host: the library loads, exports every declared symbol, and
+rejects bad arguments before any GPU work (no device needed, no kernel launched)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "scene_gather.h")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2102_03011_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_2102_03011_amd import build
+        build.build()
+    return _native, _native.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("SCENE")))
+
+
+def test_header_functions_are_exported(native):
+    mod, lib = native
+    names = _declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in mod.SIGNATURES, n
+
+
+def test_version_and_status_strings(native):
+    mod, lib = native
+    assert lib.sg_version() == 1
+    assert lib.sg_status_string(0) == b"ok"
+    assert lib.sg_status_string(mod.SG_E_INVALID) == b"invalid argument"
+    assert lib.sg_status_string(99) == b"unknown status"
+
+
+def _clip(mod, w=64, h=32, n=10, fx=50.0):
+    # fake, never dereferenced device addresses: every call below fails validation first
+    return mod.SgClip(w, h, n, 0, 0x10000, 0x20000, 0x30000, fx, fx, (w - 1) / 2, (h - 1) / 2)
+
+
+def _sets(mod, cap=0):
+    return mod.SgSampleSets(0x40000, 0x50000 if cap else None, 0x60000 if cap else None, cap, 0x70000)
+
+
+def test_workspace_size(native):
+    mod, lib = native
+    c = _clip(mod)
+    out = ctypes.c_size_t(0)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), 0, 10, ctypes.byref(p), ctypes.byref(out)) == 0
+    big = out.value
+    assert big >= 10 * 7 * 16 * 4
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), 0, 1, ctypes.byref(p), ctypes.byref(out)) == 0
+    assert 0 < out.value < big
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_clip", 1), ("f_empty", 1), ("f_past_end", 1), ("neg_window", 1), ("neg_radius", 1),
+    ("big_window", 4), ("big_radius", 4), ("tol_zero", 1), ("tol_nan", 1), ("znear_neg", 1),
+    ("too_many_pixels", 4), ("zero_fx", 1), ("null_sets", 1), ("null_ws", 1), ("small_ws", 1),
+    ("neg_capacity", 1), ("null_arena", 1), ("null_rgbd", 1),
+])
+def test_gather_rejects_bad_arguments(native, case, expect):
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    s = _sets(mod, 100)
+    f0, f1, ws, wsb = 2, 4, 0x80000, 1 << 20
+    cp = ctypes.byref(c)
+    if case == "null_clip":
+        cp = None
+    elif case == "f_empty":
+        f1 = f0
+    elif case == "f_past_end":
+        f1 = 11
+    elif case == "neg_window":
+        p.window = -1
+    elif case == "neg_radius":
+        p.radius = -1
+    elif case == "big_window":
+        p.window = 512
+    elif case == "big_radius":
+        p.radius = 4
+    elif case == "tol_zero":
+        p.tol = 0.0
+    elif case == "tol_nan":
+        p.tol = math.nan
+    elif case == "znear_neg":
+        p.z_near = -0.01
+    elif case == "too_many_pixels":
+        c.width, c.height = 4097, 1024
+    elif case == "zero_fx":
+        c.fx = 0.0
+    elif case == "null_sets":
+        s = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb = 16
+    elif case == "neg_capacity":
+        s.capacity = -1
+    elif case == "null_arena":
+        s.ids = None
+    elif case == "null_rgbd":
+        c.rgbd = None
+    sp = ctypes.byref(s) if s is not None else None
+    for fn in (lib.scene_gather, lib.scene_gather_scatter):
+        assert fn(cp, f0, f1, ctypes.byref(p), sp, ws, wsb, None) == expect, (case, fn)
+    if case not in ("neg_capacity", "null_arena"):
+        assert lib.scene_gather_count(cp, f0, f1, ctypes.byref(p), sp, ws, wsb, None) == expect, case
+
+
+@pytest.mark.parametrize("case", ["neg_window", "sigma_zero", "sigma_nan", "null_out", "null_sets", "bad_range"])
+def test_filter_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    s = _sets(mod, 100)
+    fp = mod.SgFilterParams(0.01, math.inf, math.inf, 0.0)
+    w, out, f0, f1 = 3, 0x90000, 0, 2
+    sp = ctypes.byref(s)
+    if case == "neg_window":
+        w = -1
+    elif case == "sigma_zero":
+        fp.sigma_d = 0.0
+    elif case == "sigma_nan":
+        fp.sigma_c = math.nan
+    elif case == "null_out":
+        out = None
+    elif case == "null_sets":
+        sp = None
+    elif case == "bad_range":
+        f1 = 0
+    assert lib.scene_filter(ctypes.byref(c), f0, f1, w, sp, ctypes.byref(fp), out, None) == 1
+
+
+def test_stage_rejects_bad_arguments(native):
+    mod, lib = native
+    assert lib.scene_stage(None, 0x1000, 10, 0x2000, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, -1, 0x2000, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, 1 << 41, 0x2000, 0x3000, None) == 4
