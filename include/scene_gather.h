@@ -44,6 +44,11 @@ extern "C" {
 /* Limits. Sample ids pack (J - f + w) into 10 bits and the source pixel index
  * into 22 bits, so W * H <= 2^22 and 2w + 1 <= 1024. */
 #define SG_MAX_PIXELS_PER_FRAME (1 << 22)
+/* Stored planes carry an apron: SG_APRON rows above and below the image and
+ * SG_APRON columns on its left (>= SG_MAX_RADIUS), SG_APRON_RIGHT columns on its
+ * right (room for whole 8-byte reads of a block row). */
+#define SG_APRON 3
+#define SG_APRON_RIGHT 7
 #define SG_MAX_WINDOW 511
 #define SG_MAX_RADIUS 3
 #define SG_ID_SHIFT 22
@@ -60,10 +65,14 @@ typedef enum sg_status {
   SG_E_UNSUPPORTED = 4  /* outside the limits above */
 } sg_status;
 
-/* A staged clip: the stored input planes of N frames of W x H pixels.
- * rgbd : device [N][H][W][4] binary16 (r, g, b, z-depth); the 4th channel is the
- *        same binary16 depth as `depth` (scene_stage writes both).
- * depth: device [N][H][W] binary16 z-depth (read alone by the count pass).
+/* A staged clip: the stored input planes of N frames of W x H pixels, written by
+ * scene_stage. Each plane is padded by the apron: stored rows SH = H + 2A, stored
+ * row pitch SW = W + A + AR (A = SG_APRON, AR = SG_APRON_RIGHT); image pixel (x, y)
+ * sits at stored row y + A, column x + A. Apron pixels hold an invalid depth
+ * (binary16 NaN) and zero colour.
+ * rgbd : device [N][SH][SW][4] binary16 (r, g, b, z-depth); the 4th channel is the
+ *        same binary16 depth as `depth`.
+ * depth: device [N][SH][SW] binary16 z-depth (the membership test reads it).
  * cam_to_world: device [N][4][4] float64.                                    */
 typedef struct sg_clip {
   int32_t width;
@@ -120,15 +129,17 @@ int32_t sg_version(void);
 /* Human-readable name of a status code (static string). */
 const char* sg_status_string(int32_t status);
 
-/* Stage the stored input planes (Sec. 3: the colour of each pixel and its
- * depth D^f(p) are the inputs of sampling).
- * rgb_u8  : device [n_pixels][3] uint8 colour on the 0-255 scale.
- * depth   : device [n_pixels] float32 z-depth.
- * rgbd    : device [n_pixels][4] binary16 out: (c/255 rounded to nearest even, ..., depth).
- * depth16 : device [n_pixels] binary16 out: depth rounded to nearest even (inf above 65504).
- * n_pixels >= 0 (0 enqueues nothing). */
-sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int64_t n_pixels,
-                      uint16_t* rgbd, uint16_t* depth16, void* stream);
+/* Stage the stored input planes of n_frames frames (Sec. 3: the colour of each
+ * pixel and its depth D^f(p) are the inputs of sampling).
+ * rgb_u8  : device [n_frames][H][W][3] uint8 colour on the 0-255 scale.
+ * depth   : device [n_frames][H][W] float32 z-depth.
+ * rgbd    : device [n_frames][SH][SW][4] binary16 out: (c/255, c/255, c/255, depth),
+ *           each rounded to nearest even; stored geometry and apron as at sg_clip.
+ * depth16 : device [n_frames][SH][SW] binary16 out: depth (inf above 65504).
+ * n_frames >= 0 (0 enqueues nothing); W, H > 0 with W * H <= SG_MAX_PIXELS_PER_FRAME. */
+sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int32_t n_frames,
+                      int32_t width, int32_t height, uint16_t* rgbd, uint16_t* depth16,
+                      void* stream);
 
 /* Workspace bytes needed by scene_gather_count / scene_gather_scatter / scene_gather
  * for output frames [f0, f1): relative camera maps for every (f, J) pair plus scan

@@ -18,7 +18,21 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to by sonam
 
 from . import _native
 
-_lib = _native.load()
+
+class _Lib:
+    """The HIP library, loaded on first use (so the package can be imported to
+    build it); a missing library raises ImportError at that first use."""
+
+    def __init__(self):
+        self._cdll = None
+
+    def __getattr__(self, name):
+        if self._cdll is None:
+            self._cdll = _native.load()
+        return getattr(self._cdll, name)
+
+
+_lib = _Lib()
 
 SG_ID_SHIFT = _native.SG_ID_SHIFT
 SG_FLAG_CAPACITY = _native.SG_FLAG_CAPACITY
@@ -52,11 +66,17 @@ def version() -> int:
     return int(_lib.sg_version())
 
 
+SG_APRON = _native.SG_APRON
+SG_APRON_RIGHT = _native.SG_APRON_RIGHT
+
+
 @dataclass
 class StagedClip:
-    """Stored input planes of a clip (all on the GPU)."""
-    rgbd: torch.Tensor          # [N, H, W, 4] float16: r, g, b (0-1), z-depth
-    depth: torch.Tensor         # [N, H, W] float16 z-depth
+    """Stored input planes of a clip (all on the GPU), padded by an apron of
+    invalid depth and zero colour: SG_APRON rows above and below, SG_APRON
+    columns left and SG_APRON_RIGHT columns right of the image."""
+    rgbd: torch.Tensor          # [N, H + 2A, W + A + AR, 4] float16: r, g, b (0-1), z-depth
+    depth: torch.Tensor         # [N, H + 2A, W + A + AR] float16 z-depth
     cam_to_world: torch.Tensor  # [N, 4, 4] float64
     fx: float
     fy: float
@@ -69,11 +89,20 @@ class StagedClip:
 
     @property
     def height(self) -> int:
-        return self.rgbd.shape[1]
+        return self.rgbd.shape[1] - 2 * SG_APRON
 
     @property
     def width(self) -> int:
-        return self.rgbd.shape[2]
+        return self.rgbd.shape[2] - SG_APRON - SG_APRON_RIGHT
+
+    def rgbd_image(self) -> torch.Tensor:
+        """[N, H, W, 4] view of the image pixels (without the apron)."""
+        a = SG_APRON
+        return self.rgbd[:, a:a + self.height, a:a + self.width, :]
+
+    def depth_image(self) -> torch.Tensor:
+        a = SG_APRON
+        return self.depth[:, a:a + self.height, a:a + self.width]
 
     def c_struct(self) -> _native.SgClip:
         return _native.SgClip(self.width, self.height, self.num_frames, 0,
@@ -136,11 +165,24 @@ def scene_stage(rgb_u8: torch.Tensor, depth: torch.Tensor, cam_to_world: torch.T
     n, h, w, c = rgb_u8.shape
     if c != 3 or tuple(depth.shape) != (n, h, w) or tuple(cam_to_world.shape) != (n, 4, 4):
         raise SceneGatherError("shape mismatch between rgb_u8 [N,H,W,3], depth [N,H,W], cam_to_world [N,4,4]")
-    rgbd = torch.empty((n, h, w, 4), dtype=torch.float16, device=rgb_u8.device)
-    d16 = torch.empty((n, h, w), dtype=torch.float16, device=rgb_u8.device)
-    _check(_lib.scene_stage(rgb_u8.data_ptr(), depth.data_ptr(), n * h * w, rgbd.data_ptr(), d16.data_ptr(),
+    a = SG_APRON
+    sw = w + a + SG_APRON_RIGHT
+    rgbd = torch.empty((n, h + 2 * a, sw, 4), dtype=torch.float16, device=rgb_u8.device)
+    d16 = torch.empty((n, h + 2 * a, sw), dtype=torch.float16, device=rgb_u8.device)
+    _check(_lib.scene_stage(rgb_u8.data_ptr(), depth.data_ptr(), n, w, h, rgbd.data_ptr(), d16.data_ptr(),
                             _stream_handle()), "scene_stage")
     return StagedClip(rgbd, d16, cam_to_world, fx, fy, cx, cy)
+
+
+def scene_stage_into(clip: StagedClip, rgb_u8: torch.Tensor, depth: torch.Tensor, frame: int) -> None:
+    """Re-stage one frame of `clip` in place (streaming use: the frame entering a window)."""
+    _need_gpu(rgb_u8, "rgb_u8", torch.uint8)
+    _need_gpu(depth, "depth", torch.float32)
+    h, w = clip.height, clip.width
+    if tuple(rgb_u8.shape) != (h, w, 3) or tuple(depth.shape) != (h, w) or not 0 <= frame < clip.num_frames:
+        raise SceneGatherError("scene_stage_into: frame shape or index mismatch")
+    _check(_lib.scene_stage(rgb_u8.data_ptr(), depth.data_ptr(), 1, w, h, clip.rgbd[frame].data_ptr(),
+                            clip.depth[frame].data_ptr(), _stream_handle()), "scene_stage")
 
 
 def scene_gather_workspace_size(clip: StagedClip, f0: int, f1: int, params: GatherParams) -> int:

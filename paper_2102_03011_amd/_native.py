@@ -15,6 +15,8 @@ SG_FLAG_CAPACITY, SG_FLAG_INCONSISTENT = 1, 2
 SG_ID_SHIFT = 22
 SG_MAX_WINDOW = 511
 SG_MAX_RADIUS = 3
+SG_APRON = 3
+SG_APRON_RIGHT = 7
 
 c_void_p = ctypes.c_void_p
 
@@ -47,7 +49,8 @@ class SgFilterParams(ctypes.Structure):
 SIGNATURES = {
     "sg_version": (ctypes.c_int32, []),
     "sg_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
-    "scene_stage": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p]),
+    "scene_stage": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    c_void_p, c_void_p, c_void_p]),
     "scene_gather_workspace_size": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                                     ctypes.POINTER(SgGatherParams), ctypes.POINTER(ctypes.c_size_t)]),
     "scene_gather_count": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,

@@ -124,13 +124,14 @@ const char* sg_status_string(int32_t status) {
   }
 }
 
-sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int64_t n_pixels, uint16_t* rgbd,
-                      uint16_t* depth16, void* stream) {
-  if (n_pixels < 0) return SG_E_INVALID;
-  if (n_pixels > 0 && (rgb_u8 == nullptr || depth == nullptr || rgbd == nullptr || depth16 == nullptr))
+sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int32_t n_frames, int32_t width,
+                      int32_t height, uint16_t* rgbd, uint16_t* depth16, void* stream) {
+  if (n_frames < 0 || width <= 0 || height <= 0) return SG_E_INVALID;
+  if (n_frames > 0 && (rgb_u8 == nullptr || depth == nullptr || rgbd == nullptr || depth16 == nullptr))
     return SG_E_INVALID;
-  if (n_pixels > (static_cast<int64_t>(1) << 40)) return SG_E_UNSUPPORTED;
-  return hip_status(sg::launch_stage(rgb_u8, depth, n_pixels, rgbd, depth16,
+  if (static_cast<int64_t>(width) * height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;
+  if (n_frames > 65535) return SG_E_UNSUPPORTED;
+  return hip_status(sg::launch_stage(rgb_u8, depth, n_frames, width, height, rgbd, depth16,
                                      static_cast<hipStream_t>(stream)));
 }
 

@@ -45,8 +45,8 @@ struct FilterJob {
   float* out;
 };
 
-hipError_t launch_stage(const uint8_t* rgb, const float* depth, int64_t n, uint16_t* rgbd,
-                        uint16_t* depth16, hipStream_t st);
+hipError_t launch_stage(const uint8_t* rgb, const float* depth, int n_frames, int width, int height,
+                        uint16_t* rgbd, uint16_t* depth16, hipStream_t st);
 hipError_t launch_pose_prep(const GatherJob& jb, hipStream_t st);
 hipError_t launch_count(const GatherJob& jb, hipStream_t st);
 hipError_t launch_scan(int64_t* offsets, int64_t n, int64_t* partial, hipStream_t st);

@@ -11,11 +11,20 @@
 //
 // Filter (Sec. 5 Eq. 3, weight of Eq. 4): weighted mean of each set.
 //
+// Stored planes carry an apron (SG_APRON rows above and below, SG_APRON columns
+// on the left, SG_APRON_RIGHT on the right) holding an invalid depth (binary16
+// NaN) and zero colour, so a block around any projection that passed the bounds
+// test can be read without per-pixel bounds checks: out-of-image block pixels
+// read the apron and fail the depth test. The wider right apron lets each block
+// row be fetched as whole 8-byte words.
+//
 // All kernels are compiled with -ffp-contract=off; every fused multiply-add is
 // written explicitly, so pass 1 and pass 2 make bit-identical decisions.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "sg_internal.h"
 
@@ -29,20 +38,63 @@ __device__ __forceinline__ uint32_t f2h(float v) {
   return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(v)));
 }
 
+constexpr uint32_t kInvalidDepth16 = 0x7E00u;  // binary16 quiet NaN
+
+__host__ __device__ __forceinline__ int stored_pitch(int width) {
+  return width + SG_APRON + SG_APRON_RIGHT;
+}
+__host__ __device__ __forceinline__ int stored_rows(int height) { return height + 2 * SG_APRON; }
+
+// Block rows are fetched as 8-byte words (four binary16 depths) starting at the
+// row's first column: kRowWords words cover the 2R + 1 columns.
+template <int R>
+struct RowLoad {
+  static constexpr int kWords = (2 * R + 1 + 3) / 4;
+};
+
+template <int R>
+__device__ __forceinline__ void load_block_depths(const uint16_t* centre, int pw,
+                                                  uint32_t (&d)[2 * R + 1][2 * R + 1]) {
+  constexpr int kW = RowLoad<R>::kWords;
+#pragma unroll
+  for (int dy = -R; dy <= R; ++dy) {
+    const uint16_t* rowp = centre + dy * pw - R;
+    uint64_t w[kW];
+#pragma unroll
+    for (int c = 0; c < kW; ++c) __builtin_memcpy(&w[c], rowp + 4 * c, 8);
+#pragma unroll
+    for (int o = 0; o <= 2 * R; ++o)
+      d[dy + R][o] = static_cast<uint32_t>(w[o / 4] >> (16 * (o % 4))) & 0xFFFFu;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a1: staging. colour c (0-255) -> binary16(c / 255); depth -> binary16(depth).
+// One thread per stored (padded) pixel; apron pixels get NaN depth, zero colour.
 
 __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
-                                               const float* __restrict__ depth, int64_t n,
-                                               uint2* __restrict__ rgbd,
+                                               const float* __restrict__ depth, int n_frames,
+                                               int width, int height, uint2* __restrict__ rgbd,
                                                uint16_t* __restrict__ depth16) {
+  const int pw = stored_pitch(width), ph = stored_rows(height);
+  const int64_t pplane = static_cast<int64_t>(pw) * ph;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float r = static_cast<float>(rgb[3 * i + 0]) / 255.0f;   // correctly rounded division
-  const float g = static_cast<float>(rgb[3 * i + 1]) / 255.0f;
-  const float b = static_cast<float>(rgb[3 * i + 2]) / 255.0f;
-  const uint32_t d = f2h(depth[i]);
-  rgbd[i] = make_uint2(f2h(r) | (f2h(g) << 16), f2h(b) | (d << 16));
+  if (i >= pplane * n_frames) return;
+  const int64_t n = i / pplane;
+  const int64_t r = i - n * pplane;
+  const int py = static_cast<int>(r / pw), px = static_cast<int>(r - static_cast<int64_t>(py) * pw);
+  const int x = px - SG_APRON, y = py - SG_APRON;
+  if (x < 0 || x >= width || y < 0 || y >= height) {
+    rgbd[i] = make_uint2(0u, kInvalidDepth16 << 16);
+    depth16[i] = static_cast<uint16_t>(kInvalidDepth16);
+    return;
+  }
+  const int64_t s = (n * height + y) * static_cast<int64_t>(width) + x;
+  const float cr = static_cast<float>(rgb[3 * s + 0]) / 255.0f;   // correctly rounded division
+  const float cg = static_cast<float>(rgb[3 * s + 1]) / 255.0f;
+  const float cb = static_cast<float>(rgb[3 * s + 2]) / 255.0f;
+  const uint32_t d = f2h(depth[s]);
+  rgbd[i] = make_uint2(f2h(cr) | (f2h(cg) << 16), f2h(cb) | (d << 16));
   depth16[i] = static_cast<uint16_t>(d);
 }
 
@@ -107,12 +159,41 @@ __global__ __launch_bounds__(64) void k_pose_prep(const double* __restrict__ c2w
 }
 
 // ---------------------------------------------------------------------------
-// Shared projection (identical in both gather passes).
+// Shared projection and depth test (identical in both gather passes).
 
 struct Projected {
-  float z, tz, inv;
+  float z, inv;
   int iu, iv;
+  uint32_t lo16, range16;  // accepted binary16 depth bit patterns: lo16 .. lo16 + range16
 };
+
+// Depth test |D^J(q) - z| <= tol * z, as an interval of binary16 values: with
+// lo = z - tol z and hi = z + tol z (float32), a stored depth d is kept iff
+// lo <= d <= hi and d is positive and finite. For positive binary16 values the
+// bit pattern orders like the value, so the test becomes one unsigned compare
+// (NaN, infinities, zero and negatives all fall outside).
+__device__ __forceinline__ void depth_interval(float z, float tol, Projected& o) {
+  const float tz = tol * z;
+  const float lo = z - tz, hi = z + tz;
+  uint32_t l = 1u;  // smallest positive binary16
+  if (lo > 0.0f) {
+    l = f2h(lo);
+    if (h2f(l) < lo) ++l;  // round up
+  }
+  uint32_t h = f2h(hi);
+  if (h2f(h) > hi) --h;    // round down (an infinite result steps back to 65504)
+  if (h >= l) {
+    o.lo16 = l;
+    o.range16 = h - l;
+  } else {
+    o.lo16 = 0x10000u;     // no 16-bit pattern reaches this
+    o.range16 = 0u;
+  }
+}
+
+__device__ __forceinline__ bool accept16(uint32_t d16, const Projected& p) {
+  return d16 - p.lo16 <= p.range16;
+}
 
 __device__ __forceinline__ bool project(const float* __restrict__ m, float x, float y, float dp,
                                         float z_near, float tol, int width, int height, int r,
@@ -125,41 +206,63 @@ __device__ __forceinline__ bool project(const float* __restrict__ m, float x, fl
   const float z = fmaf(dp, a2, m[11]);
   if (!(z > z_near)) return false;
   const float inv = __builtin_amdgcn_rcpf(z);
-  const float uh = floorf(y0 * inv + 0.5f);
-  const float vh = floorf(y1 * inv + 0.5f);
+  const float uh = floorf(fmaf(y0, inv, 0.5f));
+  const float vh = floorf(fmaf(y1, inv, 0.5f));
   const float fr = static_cast<float>(r);
   if (!(uh >= -fr && uh <= static_cast<float>(width - 1) + fr && vh >= -fr &&
         vh <= static_cast<float>(height - 1) + fr))
     return false;
   o.z = z;
-  o.tz = tol * z;
   o.inv = inv;
   o.iu = static_cast<int>(uh);
   o.iv = static_cast<int>(vh);
+  depth_interval(z, tol, o);
   return true;
 }
 
-__device__ __forceinline__ bool accept(float dq, const Projected& p) {
-  return dq > 0.0f && fabsf(dq - p.z) <= p.tz;
+// Tile of a gather workgroup: 1-D dispatch index -> (tile x, tile y, output frame),
+// x fastest. Consecutive workgroups are dispatched round-robin over the XCDs, so
+// at any moment every XCD works on the same band of rows and the shared memory-side
+// cache serves the source lines all of them miss in their own L2.
+struct Tile {
+  int tx, ty, fo;
+};
+
+__device__ __forceinline__ Tile tile_of_block(int tiles_x, int tiles_y) {
+  const int b = static_cast<int>(blockIdx.x);
+  Tile t;
+  t.tx = b % tiles_x;
+  const int rest = b / tiles_x;
+  t.ty = rest % tiles_y;
+  t.fo = rest / tiles_y;
+  return t;
+}
+
+// Stored-plane index of image pixel (x, y).
+__device__ __forceinline__ size_t padded_index(int x, int y, int pw) {
+  return static_cast<size_t>(y + SG_APRON) * pw + (x + SG_APRON);
 }
 
 // ---------------------------------------------------------------------------
 // a3: gather pass 1 -- count members per output pixel.
 // Block = 64 x 4 pixels (one wave per row segment), grid.z = output frame.
+// Per source frame the (2r+1)^2 depths are loaded unconditionally (apron makes
+// every address valid), so all loads of a block are in flight together.
 
 template <int R>
 __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ depth,
                                                const float* __restrict__ rel, int width, int height,
                                                int n_frames, int f0, int w, float tol, float z_near,
                                                int64_t* __restrict__ counts) {
-  const int x = blockIdx.x * kTileW + threadIdx.x;
-  const int y = blockIdx.y * kTileH + threadIdx.y;
-  const int fo = blockIdx.z;
+  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
+  const int x = tile.tx * kTileW + threadIdx.x;
+  const int y = tile.ty * kTileH + threadIdx.y;
+  const int fo = tile.fo;
   if (x >= width || y >= height) return;
   const int f = f0 + fo;
-  const size_t plane = static_cast<size_t>(width) * height;
-  const size_t self = static_cast<size_t>(y) * width + x;
-  const float dp = h2f(depth[static_cast<size_t>(f) * plane + self]);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const float dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
   int count = 0;
   if (dp > z_near && dp < INFINITY) {
     const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
@@ -169,88 +272,190 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
       Projected p;
       if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p))
         continue;
-      const uint16_t* dj = depth + static_cast<size_t>(j) * plane;
+      uint32_t d[2 * R + 1][2 * R + 1];
+      load_block_depths<R>(depth + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw), pw, d);
 #pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const int row = p.iv + dy;
-        if (row < 0 || row >= height) continue;
-        const uint16_t* drow = dj + static_cast<size_t>(row) * width;
+      for (int dy = 0; dy <= 2 * R; ++dy)
 #pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const int col = p.iu + dx;
-          if (col < 0 || col >= width) continue;
-          count += accept(h2f(drow[col]), p) ? 1 : 0;
-        }
-      }
+        for (int dx = 0; dx <= 2 * R; ++dx) count += accept16(d[dy][dx], p) ? 1 : 0;
     }
   }
-  counts[static_cast<size_t>(fo) * plane + self] = count;
+  counts[static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x] = count;
 }
 
 // ---------------------------------------------------------------------------
 // a5: gather pass 2 -- write records in canonical order.
+//
+// Each wave owns 64 consecutive output pixels of one row, so their CSR segments
+// are adjacent in memory. Per source frame each lane reads its whole block of
+// stored (r, g, b, depth) pixels in one round trip, decides membership from the
+// depth channel exactly as pass 1 does from the depth plane (same binary16 bits,
+// same test), and appends its accepted records to a per-lane buffer in LDS
+// (kSlots entries, odd stride: conflict-free appends). When some lane's buffer
+// could overflow on the next source frame, the wave flushes every lane holding at
+// least kMinRun records: a group of kRunLanes lanes writes each flushed lane's
+// run, so a store instruction writes 64 / kRunLanes contiguous runs instead of 64
+// scattered 8-byte pieces. Records reach global memory in the order they are
+// found, which is the canonical order.
+
+template <int R>
+struct ScatterShape {
+  static constexpr int kCand = (2 * R + 1) * (2 * R + 1);
+  // Odd number of slots per lane (LDS: 12 B per slot, 256 lanes per workgroup).
+  // A flush is triggered when some lane has fewer than kCand free slots and empties
+  // every lane holding >= kMinRun records, so afterwards each lane has room for a
+  // whole block again: kMinRun - 1 <= kSlots - kCand.
+  static constexpr int kSlots = R == 3 ? 51 : (R == 2 ? 41 : 15);
+  static constexpr int kMinRun = R == 3 ? 2 : (R == 2 ? 12 : 7);
+  static constexpr int kRunLanes = kSlots <= 16 ? 16 : 64;  // lanes writing one run
+  static_assert(kMinRun - 1 <= kSlots - kCand, "flush must leave room for one block");
+  static_assert((kSlots & 1) == 1, "odd stride keeps LDS accesses conflict-free");
+  static_assert(kSlots <= kRunLanes, "a run fits its lane group");
+  using Mask = typename std::conditional<(kCand > 32), uint64_t, uint32_t>::type;
+};
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Write the n buffered records of every lane (n = 0 for lanes that keep theirs)
+// to [cur, cur + n) of that lane's segment.
+template <int R>
+__device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const uint2* s_rec,
+                                           const uint32_t* s_id, int* s_n, int64_t* s_dst,
+                                           uint32_t* __restrict__ ids, uint2* __restrict__ crho) {
+  constexpr int kSlots = ScatterShape<R>::kSlots;
+  constexpr int kRun = ScatterShape<R>::kRunLanes;
+  constexpr int kPer = 64 / kRun;
+  const int lane = threadIdx.x;
+  s_n[lane] = n;
+  s_dst[lane] = cur;
+  wave_lds_fence();
+  const int sub = lane % kRun, grp = lane / kRun;
+#pragma unroll 4
+  for (int base = 0; base < 64; base += kPer) {
+    const int own = base + grp;
+    if (sub < s_n[own]) {
+      const int64_t dst = s_dst[own] + sub;
+      crho[dst] = s_rec[own * kSlots + sub];
+      ids[dst] = s_id[own * kSlots + sub];
+    }
+  }
+  wave_lds_fence();
+  cur += n;
+  fill -= n;
+}
 
 template <int R>
 __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
+                                                 const uint16_t* __restrict__ depth,
                                                  const float* __restrict__ rel, int width,
                                                  int height, int n_frames, int f0, int w, float tol,
                                                  float z_near, const int64_t* __restrict__ offsets,
                                                  uint32_t* __restrict__ ids,
                                                  uint2* __restrict__ crho, int64_t capacity,
                                                  uint32_t* __restrict__ status) {
-  const int x = blockIdx.x * kTileW + threadIdx.x;
-  const int y = blockIdx.y * kTileH + threadIdx.y;
-  const int fo = blockIdx.z;
-  if (x >= width || y >= height) return;
+  using Shape = ScatterShape<R>;
+  using Mask = typename Shape::Mask;
+  constexpr int kSlots = Shape::kSlots;
+  constexpr int kSide = 2 * R + 1;
+  __shared__ uint2 s_rec_all[kTileH][kTileW * kSlots];
+  __shared__ uint32_t s_id_all[kTileH][kTileW * kSlots];
+  __shared__ int s_n_all[kTileH][kTileW];
+  __shared__ int64_t s_dst_all[kTileH][kTileW];
+  const int lane = threadIdx.x, wv = threadIdx.y;
+  uint2* s_rec = s_rec_all[wv];
+  uint32_t* s_id = s_id_all[wv];
+  int* s_n = s_n_all[wv];
+  int64_t* s_dst = s_dst_all[wv];
+
+  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
+  const int x = tile.tx * kTileW + lane;
+  const int y = tile.ty * kTileH + wv;
+  const int fo = tile.fo;
   const int f = f0 + fo;
-  const size_t plane = static_cast<size_t>(width) * height;
-  const size_t self = static_cast<size_t>(y) * width + x;
-  const size_t pix = static_cast<size_t>(fo) * plane + self;
-  int64_t cur = offsets[pix];
-  const int64_t end = offsets[pix + 1];
-  if (cur < 0 || end < cur) {  // offsets not produced by the count pass
-    atomicOr(status, SG_FLAG_INCONSISTENT);
-    return;
-  }
-  if (end > capacity) {
-    if (end > cur) atomicOr(status, SG_FLAG_CAPACITY);
-    return;
-  }
-  const float dp = h2f(rgbd[static_cast<size_t>(f) * plane + self].y >> 16);
-  if (dp > z_near && dp < INFINITY) {
-    const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
-    const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
-    const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
-    for (int j = jlo; j <= jhi; ++j) {
-      Projected p;
-      if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p))
-        continue;
-      const uint2* cj = rgbd + static_cast<size_t>(j) * plane;
-      const uint32_t idj = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy) {
-        const int row = p.iv + dy;
-        if (row < 0 || row >= height) continue;
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const int col = p.iu + dx;
-          if (col < 0 || col >= width) continue;
-          const uint32_t q = static_cast<uint32_t>(row * width + col);
-          const uint2 px = cj[q];
-          const float dq = h2f(px.y >> 16);
-          if (accept(dq, p)) {
-            if (cur < end) {
-              const float rho = (dq - p.z) * p.inv;
-              ids[cur] = idj | q;
-              crho[cur] = make_uint2(px.x, (px.y & 0xFFFFu) | (f2h(rho) << 16));
-            }
-            ++cur;
-          }
-        }
-      }
+  const bool in = x < width && y < height;
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  int64_t cur = 0, end = 0, start = 0;
+  bool active = false;
+  float dp = 0.0f;
+  if (in) {
+    const size_t pix = static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x;
+    start = cur = offsets[pix];
+    end = offsets[pix + 1];
+    if (cur < 0 || end < cur) {  // offsets not produced by the count pass
+      atomicOr(status, SG_FLAG_INCONSISTENT);
+    } else if (end > capacity) {
+      if (end > cur) atomicOr(status, SG_FLAG_CAPACITY);
+    } else {
+      dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+      active = dp > z_near && dp < INFINITY;
     }
   }
-  if (cur != end) atomicOr(status, SG_FLAG_INCONSISTENT);
+  int fill = 0;
+  int found = 0;
+  const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
+  const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
+  const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
+  uint2* my_rec = s_rec + lane * kSlots;
+  uint32_t* my_id = s_id + lane * kSlots;
+  for (int j = jlo; j <= jhi; ++j) {
+    Projected p;
+    if (active && project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) {
+      const uint2* cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
+      uint2 px[kSide][kSide];
+#pragma unroll
+      for (int dy = 0; dy < kSide; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = cj[(dy - R) * pw + (dx - R)];
+      Mask mask = 0;
+#pragma unroll
+      for (int k = 0; k < kSide * kSide; ++k)
+        mask |= static_cast<Mask>(accept16(px[k / kSide][k % kSide].y >> 16, p) ? 1 : 0) << k;
+      const int n = __popc(static_cast<uint32_t>(mask)) +
+                    (sizeof(Mask) > 4 ? __popc(static_cast<uint32_t>(static_cast<uint64_t>(mask) >> 32)) : 0);
+      found += n;
+      // keep only as many records as the segment has room for (fewer only when
+      // the planes changed since the count pass; flagged at the end)
+      int kept = n;
+      const int64_t room = end - cur - fill;
+      if (n > room) {
+        Mask keep = 0;
+        int left = static_cast<int>(room);
+        for (int k = 0; k < kSide * kSide && left > 0; ++k)
+          if ((mask >> k) & 1) {
+            keep |= static_cast<Mask>(1) << k;
+            --left;
+          }
+        mask = keep;
+        kept = static_cast<int>(room);
+      }
+      // id = ((J - f + w) << 22) | q; q < 2^22, so the OR is an add of a
+      // per-(p, J) base and a per-candidate constant
+      const uint32_t id0 = (static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT) +
+                           static_cast<uint32_t>((p.iv - R) * width + (p.iu - R));
+      uint2* rec = my_rec + fill;
+      uint32_t* idp = my_id + fill;
+#pragma unroll
+      for (int k = 0; k < kSide * kSide; ++k) {
+        if ((mask >> k) & 1) {
+          const int dy = k / kSide, dx = k % kSide;
+          const uint2 v = px[dy][dx];
+          // rho = (d - z) / z = d * (1 / z) - 1, d = the record's own stored depth
+          const float rho = fmaf(h2f(v.y >> 16), p.inv, -1.0f);
+          *rec++ = make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16));
+          *idp++ = id0 + static_cast<uint32_t>(dy * width + dx);
+        }
+      }
+      fill += kept;
+    }
+    if (__any(fill > kSlots - Shape::kCand))
+      flush_runs<R>(fill >= Shape::kMinRun ? fill : 0, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
+  }
+  if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
+  if (active && found != end - start) atomicOr(status, SG_FLAG_INCONSISTENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,8 +557,11 @@ __global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, 
   int fo = 0;
   if (live) {
     fo = static_cast<int>(pix / static_cast<int64_t>(plane));
-    const size_t self = static_cast<size_t>(pix - static_cast<int64_t>(fo) * plane);
-    const uint2 ref = rgbd[static_cast<size_t>(f0 + fo) * plane + self];
+    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
+    const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
+    const int pw = stored_pitch(width);
+    const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+    const uint2 ref = rgbd[static_cast<size_t>(f0 + fo) * pplane + padded_index(x, y, pw)];
     cr = h2f(ref.x);
     cg = h2f(ref.x >> 16);
     cb = h2f(ref.y);
@@ -409,12 +617,13 @@ __global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, 
 // ---------------------------------------------------------------------------
 // launchers
 
-hipError_t launch_stage(const uint8_t* rgb, const float* depth, int64_t n, uint16_t* rgbd,
-                        uint16_t* depth16, hipStream_t st) {
+hipError_t launch_stage(const uint8_t* rgb, const float* depth, int n_frames, int width, int height,
+                        uint16_t* rgbd, uint16_t* depth16, hipStream_t st) {
+  const int64_t n = static_cast<int64_t>(stored_pitch(width)) * stored_rows(height) * n_frames;
   if (n == 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_stage, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, rgb, depth, n,
-                     reinterpret_cast<uint2*>(rgbd), depth16);
+  hipLaunchKernelGGL(k_stage, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, rgb, depth,
+                     n_frames, width, height, reinterpret_cast<uint2*>(rgbd), depth16);
   return hipGetLastError();
 }
 
@@ -434,13 +643,15 @@ static void count_r(const GatherJob& jb, dim3 g, hipStream_t st) {
 template <int R>
 static void scatter_r(const GatherJob& jb, dim3 g, hipStream_t st) {
   hipLaunchKernelGGL(k_scatter<R>, g, dim3(kTileW, kTileH), 0, st,
-                     reinterpret_cast<const uint2*>(jb.rgbd), jb.rel, jb.width, jb.height,
+                     reinterpret_cast<const uint2*>(jb.rgbd), jb.depth, jb.rel, jb.width, jb.height,
                      jb.n_frames, jb.f0, jb.w, jb.tol, jb.z_near, jb.offsets, jb.ids,
                      reinterpret_cast<uint2*>(jb.crho), jb.capacity, jb.status);
 }
 
 static dim3 gather_grid(const GatherJob& jb) {
-  return dim3((jb.width + kTileW - 1) / kTileW, (jb.height + kTileH - 1) / kTileH, jb.n_out);
+  const int64_t nb = static_cast<int64_t>((jb.width + kTileW - 1) / kTileW) *
+                     ((jb.height + kTileH - 1) / kTileH) * jb.n_out;
+  return dim3(static_cast<unsigned>(nb));
 }
 
 hipError_t launch_count(const GatherJob& jb, hipStream_t st) {
@@ -486,21 +697,19 @@ hipError_t launch_filter(const FilterJob& fj, hipStream_t st) {
   const dim3 g(static_cast<unsigned>((threads + 255) / 256));
   const uint2* rgbd = reinterpret_cast<const uint2*>(fj.rgbd);
   const uint2* crho = reinterpret_cast<const uint2*>(fj.crho);
+#define SG_FILTER_LAUNCH(C, T)                                                                  \
+  hipLaunchKernelGGL((k_filter<C, T>), g, dim3(256), 0, st, rgbd, fj.width, fj.height, fj.f0, \
+                     fj.w, fj.n_pix, fj.offsets, fj.ids, crho, fj.capacity, fj.a_d, fj.a_c,    \
+                     fj.a_t, fj.out)
   if (fj.use_colour && fj.use_time)
-    hipLaunchKernelGGL((k_filter<true, true>), g, dim3(256), 0, st, rgbd, fj.width, fj.height, fj.f0,
-                       fj.w, fj.n_pix, fj.offsets, fj.ids, crho, fj.capacity, fj.a_d, fj.a_c, fj.a_t, fj.out);
+    SG_FILTER_LAUNCH(true, true);
   else if (fj.use_colour)
-    hipLaunchKernelGGL((k_filter<true, false>), g, dim3(256), 0, st, rgbd, fj.width, fj.height,
-                       fj.f0, fj.w, fj.n_pix, fj.offsets, fj.ids, crho, fj.capacity, fj.a_d, fj.a_c,
-                       fj.a_t, fj.out);
+    SG_FILTER_LAUNCH(true, false);
   else if (fj.use_time)
-    hipLaunchKernelGGL((k_filter<false, true>), g, dim3(256), 0, st, rgbd, fj.width, fj.height,
-                       fj.f0, fj.w, fj.n_pix, fj.offsets, fj.ids, crho, fj.capacity, fj.a_d, fj.a_c,
-                       fj.a_t, fj.out);
+    SG_FILTER_LAUNCH(false, true);
   else
-    hipLaunchKernelGGL((k_filter<false, false>), g, dim3(256), 0, st, rgbd, fj.width, fj.height,
-                       fj.f0, fj.w, fj.n_pix, fj.offsets, fj.ids, crho, fj.capacity, fj.a_d, fj.a_c,
-                       fj.a_t, fj.out);
+    SG_FILTER_LAUNCH(false, false);
+#undef SG_FILTER_LAUNCH
   return hipGetLastError();
 }
 

@@ -146,6 +146,9 @@ def test_filter_rejects_bad_arguments(native, case):
 
 def test_stage_rejects_bad_arguments(native):
     mod, lib = native
-    assert lib.scene_stage(None, 0x1000, 10, 0x2000, 0x3000, None) == 1
-    assert lib.scene_stage(0x1000, 0x1000, -1, 0x2000, 0x3000, None) == 1
-    assert lib.scene_stage(0x1000, 0x1000, 1 << 41, 0x2000, 0x3000, None) == 4
+    assert lib.scene_stage(None, 0x1000, 10, 64, 32, 0x2000, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, -1, 64, 32, 0x2000, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, 2, 0, 32, 0x2000, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, 2, 64, 32, None, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, 2, 4097, 1024, 0x2000, 0x3000, None) == 4
+    assert lib.scene_stage(0x1000, 0x1000, 70000, 64, 32, 0x2000, 0x3000, None) == 4

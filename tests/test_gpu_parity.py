@@ -32,7 +32,7 @@ def _stage(clip, dev="cuda"):
 def _oracle_planes(clip, staged):
     col = ostaging.colour_q(clip.rgb_u8.cpu().numpy())
     dep = ostaging.depth_q(clip.depth.cpu().numpy())
-    rgbd = staged.rgbd.cpu().numpy().view(np.uint16)
+    rgbd = staged.rgbd_image().cpu().numpy().view(np.uint16)
     return col, dep, rgbd
 
 
@@ -87,12 +87,21 @@ def test_stage_bit_exact(small):
     assert np.array_equal(parity.f16_to_f64(rgbd[..., :3].copy()), col)
     d_gpu = parity.f16_to_f64(rgbd[..., 3].copy())
     assert np.array_equal(d_gpu, dep)
-    assert np.array_equal(staged.depth.cpu().numpy().view(np.uint16), rgbd[..., 3])
+    assert np.array_equal(staged.depth_image().cpu().numpy().view(np.uint16), rgbd[..., 3])
+    # the apron: binary16 NaN depth in both planes, zero colour
+    a = sg_apron = _sg().SG_APRON
+    full = staged.rgbd.cpu().numpy().view(np.uint16)
+    dfull = staged.depth.cpu().numpy().view(np.uint16)
+    ring = np.ones(full.shape[:3], bool)
+    ring[:, a:a + clip.height, a:a + clip.width] = False
+    assert full.shape[2] == clip.width + a + _sg().SG_APRON_RIGHT and full.shape[1] == clip.height + 2 * a
+    assert sg_apron >= 3 and np.all(dfull[ring] == 0x7E00) and np.all(full[ring][:, 3] == 0x7E00)
+    assert np.all(full[ring][:, :3] == 0)
     sg = _sg()
     allv = torch.arange(256, dtype=torch.uint8).repeat_interleave(3).reshape(1, 16, 16, 3).cuda()
     d = torch.linspace(0.001, 70000.0, 256, dtype=torch.float32).reshape(1, 16, 16).cuda()
     s = sg.scene_stage(allv, d, torch.eye(4, dtype=torch.float64).reshape(1, 4, 4).cuda(), 1, 1, 0, 0)
-    got = s.rgbd.cpu().numpy().view(np.uint16)
+    got = s.rgbd_image().cpu().numpy().view(np.uint16)
     want_c = np.arange(256, dtype=np.float64)[:, None].repeat(3, 1) / 255.0
     assert np.array_equal(got[..., :3].reshape(256, 3), want_c.astype(np.float16).view(np.uint16))
     want_d = ostaging.depth_q(d.cpu().numpy()).astype(np.float16).view(np.uint16)
