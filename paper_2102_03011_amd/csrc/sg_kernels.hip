@@ -320,7 +320,10 @@ __device__ __forceinline__ void wave_lds_fence() {
 }
 
 // Write the n buffered records of every lane (n = 0 for lanes that keep theirs)
-// to [cur, cur + n) of that lane's segment.
+// to [cur, cur + n) of that lane's segment. Only lanes with n > 0 take part: their
+// (count, destination) pairs are compacted into a list (ballot + rank), and each
+// group of kRunLanes lanes writes one list entry's run, so the store instructions
+// stay dense however few lanes flush.
 template <int R>
 __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const uint2* s_rec,
                                            const uint32_t* s_id, int* s_n, int64_t* s_dst,
@@ -329,17 +332,25 @@ __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const
   constexpr int kRun = ScatterShape<R>::kRunLanes;
   constexpr int kPer = 64 / kRun;
   const int lane = threadIdx.x;
-  s_n[lane] = n;
-  s_dst[lane] = cur;
+  const uint64_t flushing = __ballot(n > 0);
+  const int n_list = __popcll(flushing);
+  if (n > 0) {
+    const int rank = __popcll(flushing & ((static_cast<uint64_t>(1) << lane) - 1));
+    s_n[rank] = (lane << 8) | n;  // owner lane, count (count <= kSlots < 256)
+    s_dst[rank] = cur;
+  }
   wave_lds_fence();
   const int sub = lane % kRun, grp = lane / kRun;
-#pragma unroll 4
-  for (int base = 0; base < 64; base += kPer) {
-    const int own = base + grp;
-    if (sub < s_n[own]) {
-      const int64_t dst = s_dst[own] + sub;
-      crho[dst] = s_rec[own * kSlots + sub];
-      ids[dst] = s_id[own * kSlots + sub];
+  for (int base = 0; base < n_list; base += kPer) {
+    const int e = base + grp;
+    if (e < n_list) {
+      const int on = s_n[e];
+      const int own = on >> 8, cnt = on & 0xFF;
+      if (sub < cnt) {
+        const int64_t dst = s_dst[e] + sub;
+        crho[dst] = s_rec[own * kSlots + sub];
+        ids[dst] = s_id[own * kSlots + sub];
+      }
     }
   }
   wave_lds_fence();
