@@ -45,6 +45,23 @@ def _alg_bytes(n_pix: int, n_src: int, samples: int) -> dict:
     }
 
 
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2102_03011_amd", "csrc", "sg_kernels.hip")
+    try:
+        rec = json.load(open(path))["kernels"][kernel]
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 def cpu_baseline(clip, wl, f: int, row_step: int) -> dict:
     """The float64 oracle on every `row_step`-th row of output frame f (one process)."""
     import numpy as np
@@ -81,6 +98,8 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=300, help="clip length (the workload uses 300)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-step", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run one plain 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -202,12 +221,18 @@ def main() -> int:
         "samples_per_pixel": mean_s / n_pix,
         "per_kernel_ms": per,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(dom),
                      "alg_bytes_per_launch": alg[dom]},
         "path_hbm_frac": path_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if args.copy_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     if not args.no_cpu_baseline:
         log("timing the float64 oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(clip, wl, timed[0], args.cpu_row_step)

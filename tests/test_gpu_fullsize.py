@@ -1,0 +1,108 @@
+"""GPU parity at the full workload sizes, on sampled output pixels.
+
+1920x1080 with a +-50-frame window (300 frames, 60 static + 5 moving boxes) and
+1280x720 with +-30 (120 frames, 40 + 3 moving boxes), generated on the GPU from
+their seeds. The HIP path runs in the benchmark's launch configuration (one
+output frame per call: count, size the arena, scatter, filter); the oracle
+computes the sampled pixels one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import filters as ofilters
+from oracle import gather as ogather
+from oracle import staging as ostaging
+from scenegen import configs, generate
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _window_planes(clip, f, w):
+    lo, hi = max(0, f - w), min(clip.n_frames - 1, f + w)
+    col = ostaging.colour_q(clip.rgb_u8[lo:hi + 1].cpu().numpy())
+    dep = ostaging.depth_q(clip.depth[lo:hi + 1].cpu().numpy())
+    return lo, col, dep
+
+
+def _check(wl, clip, staged, f, pixels, report):
+    import paper_2102_03011_amd as sg
+    params = sg.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
+    sets = sg.scene_gather(staged, f, f + 1, params)
+    out = sg.scene_filter(staged, sets, sg.FilterParams(sigma_d=wl.sigma_d))
+    torch.cuda.synchronize()
+    sets.check()
+    h, w = clip.height, clip.width
+    g_off, g_ids, g_crho = parity.gpu_sets_to_host(sets, 0, h * w)
+    lo, col, dep = _window_planes(clip, f, wl.window)
+    cams = clip.cam_to_world[lo:lo + col.shape[0]].numpy()
+    oprm = ogather.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
+    orc = ogather.gather_frame(col, dep, cams, clip.fx, clip.fy, clip.cx, clip.cy, f - lo, oprm, pixels=pixels)
+    rgbd = staged.rgbd_image()[lo:lo + col.shape[0]].cpu().numpy().view(np.uint16)
+    st = parity.compare_membership(orc, g_off, g_ids, g_crho, rgbd, f - lo, wl.window, pixels=pixels)
+    got = out[0].reshape(-1, 3).cpu().numpy().astype(np.float64)[pixels]
+    want = ofilters.filter_sets(orc, col[f - lo], wl.window, wl.sigma_d)
+    band = parity.pixels_with_band_cases(orc)
+    err = np.abs(got - want).max(axis=1)
+    assert err[~band].max() <= parity.COLOUR_TOL
+    # mode F (unquantised inputs): reported, not gated
+    colf = ostaging.colour_f(clip.rgb_u8[lo:lo + col.shape[0]].cpu().numpy())
+    depf = ostaging.depth_f(clip.depth[lo:lo + col.shape[0]].cpu().numpy())
+    orf = ogather.gather_frame(colf, depf, cams, clip.fx, clip.fy, clip.cx, clip.cy, f - lo, oprm, pixels=pixels)
+    wantf = ofilters.filter_sets(orf, colf[f - lo], wl.window, wl.sigma_d)
+    errf = np.abs(got - wantf).max(axis=1)
+    seg_g = np.repeat(np.arange(len(pixels)), np.diff(g_off)[pixels])
+    key_g = set(zip(seg_g.tolist(), np.concatenate([g_ids[g_off[p]:g_off[p + 1]] for p in pixels]).tolist()))
+    seg_f = np.repeat(np.arange(len(pixels)), np.diff(orf.offsets))
+    key_f = set(zip(seg_f.tolist(), orf.ids.tolist()))
+    report.append({
+        "workload": wl.name, "frame": f, "pixels": len(pixels), **st,
+        "band_pixels": int(band.sum()), "max_colour_err_q": float(err[~band].max()),
+        "modeF_membership_diff": len(key_g ^ key_f), "modeF_members": len(key_f),
+        "modeF_colour_err_max": float(errf.max()), "modeF_colour_err_mean": float(errf.mean()),
+    })
+    return sets
+
+
+@pytest.fixture(scope="module")
+def report():
+    rows = []
+    yield rows
+    for r in rows:
+        print(r)
+
+
+def _make(wl):
+    import paper_2102_03011_amd as sg
+    clip = generate(wl.spec, device="cuda", chunk_rays=1 << 20)
+    staged = sg.scene_stage(clip.rgb_u8, clip.depth, clip.cam_to_world.cuda(), clip.fx, clip.fy, clip.cx, clip.cy)
+    clip.rgb_u8, clip.depth = clip.rgb_u8.cpu(), clip.depth.cpu()
+    return wl, clip, staged
+
+
+@pytest.fixture(scope="module")
+def full_clip():
+    return _make(configs.full_scale())
+
+
+@pytest.fixture(scope="module")
+def hd_clip():
+    return _make(configs.hd_plain())
+
+
+@pytest.mark.parametrize("f", [0, 150, 299])
+def test_full_scale_1080p_w50_sampled(report, full_clip, f):
+    wl, clip, staged = full_clip
+    rng = np.random.default_rng(f)
+    pixels = np.sort(rng.choice(clip.width * clip.height, 2500, replace=False))
+    sets = _check(wl, clip, staged, f, pixels, report)
+    assert sets.total() > (1e8 if f == 150 else 5e7)
+
+
+@pytest.mark.parametrize("f", [15, 45, 75, 105])
+def test_hd_720p_w30_sampled_frames(report, hd_clip, f):
+    wl, clip, staged = hd_clip
+    rows = np.arange(f % 8, clip.height, 8)
+    pixels = (rows[:, None] * clip.width + np.arange(clip.width)[None, :]).ravel()
+    _check(wl, clip, staged, f, pixels, report)
