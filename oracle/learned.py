@@ -12,19 +12,22 @@ Features of sample s (source frame J, source pixel q) of output pixel p in frame
   x2 = |c_s - med(S)|_2, med the per-channel lower median (sorted[(n - 1) // 2])
   x3 = |J - f| / w
   x4 = |q - (u, v)|_2, distance from q to the unrounded projection in J (pixels)
-  x5 = cosine of the angle at X between the rays from the camera centres of f and J
+  x5 = 1 - cos of the angle at X between the rays from the camera centres of f and J
   x6 = |grad D^J|(q) / D^J(q), central differences (one-sided where a neighbour is
        outside the image or has no valid depth; 0 when both are missing)
   x7 = log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)),  n = |S|
   x8 = (J - f) / w
 (w = 0 gives x3 = x8 = 0.) Readings of the feature list (the workload names the
-features only): lower median, L2 colour distance, signed vs absolute frame term.
+features only): lower median, L2 colour distance, signed vs absolute frame term,
+and the view-angle term as 1 - cos (an affine image of the cosine, which the
+standardisation absorbs; near 1 the cosine itself is ill-conditioned in float32).
 
-Precision: quantize=True rounds the standardised features and both hidden
-activations to bfloat16 (round to nearest even), as the kernels store them, and
-takes weights already representable in bfloat16; accumulation is float64.
-quantize=False evaluates the exact float64 function (used by the finite-
-difference pins). Training minimises L = sum_p |O(p) - G(p)|^2 / (3 P) with Adam
+Precision: the weights are values representable in bfloat16 (the caller rounds
+them; bf16_round below); features and activations are exact float64 here. The
+kernels carry features and layer-1 activations as bfloat16 hi/lo pairs (about 16
+significant bits), so they evaluate this same function to float32-level error.
+Training minimises L = sum_p |O(p) - G(p)|^2 / (3 P) (P pixels of the
+minibatch; an empty set contributes nothing) with Adam
 (beta1 0.9, beta2 0.999, eps 1e-8) on float32 master weights.
 """
 from __future__ import annotations
@@ -33,13 +36,13 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.special import erf as _erf
 
 from . import gather as _gather
 from . import poses as _poses
 
 N_FEAT, N_HID = 8, 64
 _SQRT2 = math.sqrt(2.0)
-_erf = np.vectorize(math.erf, otypes=[np.float64])
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
@@ -171,7 +174,7 @@ def features(pix_of: np.ndarray, ids: np.ndarray, rho: np.ndarray, colour: np.nd
         xf = dp[sel][None, :] * (kinv @ np.stack([x[sel], y[sel], np.ones(sel.sum())]))
         a = t[:3, :3] @ xf                     # X - o_f, in frame-J axes
         yj = a + t[:3, 3:4]                    # X - o_J
-        out[sel, 4] = np.sum(a * yj, axis=0) / (np.linalg.norm(a, axis=0) * np.linalg.norm(yj, axis=0))
+        out[sel, 4] = 1.0 - np.sum(a * yj, axis=0) / (np.linalg.norm(a, axis=0) * np.linalg.norm(yj, axis=0))
         out[sel, 5] = _depth_gradient(depth[j], qx[sel], qy[sel])
     return out
 
@@ -179,21 +182,16 @@ def features(pix_of: np.ndarray, ids: np.ndarray, rho: np.ndarray, colour: np.nd
 # ---------------------------------------------------------------------------
 # forward, set softmax, loss, backward
 
-def standardise(x: np.ndarray, mlp: MLP, quantize: bool) -> np.ndarray:
-    xs = (x - mlp.mean) / mlp.std
-    return bf16_round(xs) if quantize else xs
+def standardise(x: np.ndarray, mlp: MLP) -> np.ndarray:
+    return (x - mlp.mean) / mlp.std
 
 
-def forward(xs: np.ndarray, mlp: MLP, quantize: bool):
+def forward(xs: np.ndarray, mlp: MLP):
     """Logits for standardised features xs [S, 8]; returns (m, cache)."""
     z1 = xs @ mlp.w1 + mlp.b1
     h1 = gelu(z1)
-    if quantize:
-        h1 = bf16_round(h1)
     z2 = h1 @ mlp.w2 + mlp.b2
     h2 = gelu(z2)
-    if quantize:
-        h2 = bf16_round(h2)
     m = h2 @ mlp.w3 + mlp.b3
     return m, (xs, z1, h1, z2, h2)
 
@@ -212,16 +210,16 @@ def set_softmax_mean(m: np.ndarray, colour: np.ndarray, offsets: np.ndarray, c_r
     return out, a
 
 
-def loss_and_grads(xs, colour, offsets, c_ref, clean, mlp: MLP, quantize: bool):
-    """L = sum |O - G|^2 / (3 P) over the sets with at least one sample, and dL/dtheta."""
-    m, (xs, z1, h1, z2, h2) = forward(xs, mlp, quantize)
+def loss_and_grads(xs, colour, offsets, c_ref, clean, mlp: MLP):
+    """L = sum over non-empty sets of |O - G|^2, divided by 3 x (number of sets), and dL/dtheta."""
+    m, (xs, z1, h1, z2, h2) = forward(xs, mlp)
     o, a = set_softmax_mean(m, colour, offsets, c_ref)
     counts = np.diff(offsets)
     used = counts > 0
-    p_used = max(int(used.sum()), 1)
+    n_sets = max(counts.size, 1)
     diff = (o - clean) * used[:, None]
-    loss = float(np.sum(diff * diff) / (3 * p_used))
-    d_o = 2.0 * diff / (3 * p_used)
+    loss = float(np.sum(diff * diff) / (3 * n_sets))
+    d_o = 2.0 * diff / (3 * n_sets)
     seg = np.repeat(np.arange(counts.size), counts)
     # dO/dm_s = a_s (c_s - O)
     dm = a * np.sum((colour - o[seg]) * d_o[seg], axis=1)

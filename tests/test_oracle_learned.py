@@ -46,7 +46,7 @@ def test_zero_output_layer_is_arithmetic_mean():
     mlp = learned.init_mlp(3)
     mlp.w3[:] = 0.0
     mlp.b3 = 0.0
-    m, _ = learned.forward(learned.standardise(x, mlp, True), mlp, True)
+    m, _ = learned.forward(learned.standardise(x, mlp), mlp)
     cref = rng.random((4, 3))
     o, a = learned.set_softmax_mean(m, col, off, cref)
     want = filters.weighted_mean(off, col, np.zeros(off[-1]), np.zeros(off[-1]), cref, math.inf)
@@ -71,7 +71,7 @@ def test_set_output_is_permutation_invariant():
     rng = np.random.default_rng(3)
     off, col, x = _random_sets(rng, [12])
     mlp = learned.init_mlp(4)
-    m, _ = learned.forward(x, mlp, False)
+    m, _ = learned.forward(x, mlp)
     o1, _ = learned.set_softmax_mean(m, col, off, np.zeros((1, 3)))
     perm = rng.permutation(12)
     o2, _ = learned.set_softmax_mean(m[perm], col[perm], off, np.zeros((1, 3)))
@@ -87,7 +87,7 @@ def test_backward_matches_central_differences():
     mlp.b2 = rng.normal(size=64) * 0.1
     cref = rng.random((4, 3))
     clean = rng.random((4, 3))
-    _, g, _ = learned.loss_and_grads(x, col, off, cref, clean, mlp, quantize=False)
+    _, g, _ = learned.loss_and_grads(x, col, off, cref, clean, mlp)
     h = 1e-6
     for name, idx in [("w1", (3, 17)), ("b1", (5,)), ("w2", (40, 2)), ("b2", (63,)), ("w3", (11,)), ("b3", None)]:
         p = mlp.copy()
@@ -98,8 +98,8 @@ def test_backward_matches_central_differences():
         else:
             getattr(p, name)[idx] += h
             getattr(q, name)[idx] -= h
-        lp, _, _ = learned.loss_and_grads(x, col, off, cref, clean, p, quantize=False)
-        lq, _, _ = learned.loss_and_grads(x, col, off, cref, clean, q, quantize=False)
+        lp, _, _ = learned.loss_and_grads(x, col, off, cref, clean, p)
+        lq, _, _ = learned.loss_and_grads(x, col, off, cref, clean, q)
         fd = (lp - lq) / (2 * h)
         got = g[name] if idx is None else g[name][idx]
         assert abs(got - fd) <= 1e-7 * max(1.0, abs(fd)) + 1e-10, (name, got, fd)
@@ -185,7 +185,7 @@ def test_features_on_planar_scene_closed_forms():
         u, v = fx * xj[0] / xj[2] + cx, fy * xj[1] / xj[2] + cy
         assert abs(feat[s, 3] - math.hypot(qx - u, qy - v)) < 1e-9
         a, b = xw[:3] - cams[f][:3, 3], xw[:3] - cams[j][:3, 3]
-        assert abs(feat[s, 4] - a @ b / (np.linalg.norm(a) * np.linalg.norm(b))) < 1e-12
+        assert abs(feat[s, 4] - (1.0 - a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))) < 1e-12
         # depth gradient from the analytic plane depth at the neighbours
         def dd(xx, yy):
             return plane_depth(cams[j], np.array([float(xx)]), np.array([float(yy)]))[0]
@@ -196,7 +196,7 @@ def test_features_on_planar_scene_closed_forms():
         assert abs(feat[s, 5] - math.hypot(gx, gy) / dd(qx, qy)) < 1e-12
         assert feat[s, 2] == abs(dj[s]) and feat[s, 7] == dj[s]
         if dj[s] == 0 and qx == x and qy == y:
-            assert feat[s, 0] == 0 and feat[s, 3] < 1e-12 and abs(feat[s, 4] - 1) < 1e-15
+            assert feat[s, 0] == 0 and feat[s, 3] < 1e-12 and abs(feat[s, 4]) < 1e-15
         checked += 1
     assert checked > 300
     n = np.diff(sets.offsets)[seg]
