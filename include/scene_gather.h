@@ -180,6 +180,72 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
                        const sg_sample_sets* sets, const sg_filter_params* params,
                        float* out_rgb, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned per-sample weights (replacing the hand-set weight of Sec. 5.1 Eq. 4 in
+ * the weighted mean of Sec. 5 Eq. 3): O(p) = sum_s softmax(m)_s c_s over the set of
+ * p, m_s = MLP(standardised features of s), MLP 8 -> 64 -> 64 -> 1 with GELU.
+ * Features of a sample (source frame J, source pixel q) of output pixel p, frame f:
+ *   1 rho; 2 |c - lower median of the set|_2 (per channel); 3 |J - f| / w;
+ *   4 |q - (u, v)|_2 with (u, v) the unrounded projection in J; 5 cosine of the angle
+ *   at the scene point between the rays from the camera centres of f and J;
+ *   6 |grad D^J|(q) / D^J(q) (central differences, one-sided where a neighbour has
+ *   no valid depth); 7 log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)); 8 (J - f) / w.
+ * GELU uses the tanh form 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3)))
+ * (Hendrycks and Gimpel); activations are stored as bfloat16, products accumulate
+ * in float32 on the matrix cores.
+ *
+ * Parameter layout (device):
+ *   w : bfloat16 [SG_MLP_NW] = W1 [8][64] (feature, hidden), W2 [64][64] (in, out), W3 [64]
+ *   b : float32  [SG_MLP_NB] = b1 [64], b2 [64], b3, 3 unused, feature mean [8],
+ *       feature 1/std [8].                                                      */
+#define SG_MLP_NW (8 * 64 + 64 * 64 + 64)
+#define SG_MLP_NB (64 + 64 + 4 + 8 + 8)
+/* trainable parameters in float32 master order: W1, W2, W3, b1, b2, b3 */
+#define SG_MLP_NPARAM (SG_MLP_NW + 64 + 64 + 1)
+
+typedef struct sg_mlp {
+  const uint16_t* w;
+  const float* b;
+} sg_mlp;
+
+/* Learned filter. Same sets, geometry and workspace contract as the gather of
+ * [f0, f1) with `params` (the workspace's relative maps are recomputed here).
+ * out_rgb device [P][3] float32; an empty set gives I^f(p); a set that did not fit
+ * the arena gives NaN. */
+sg_status scene_filter_learned(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, const sg_sample_sets* sets,
+                               const sg_mlp* mlp, void* workspace, size_t workspace_bytes,
+                               float* out_rgb, void* stream);
+
+/* Training state (device, caller-owned).
+ *   master : float32 [SG_MLP_NPARAM] parameters; adam_m, adam_v : same size;
+ *   grad   : float32 [SG_MLP_NPARAM] accumulator (cleared by the step);
+ *   w_bf16 : the step writes the bfloat16 forward copy of W1, W2, W3 here;
+ *   b_f32  : [SG_MLP_NB]; the step writes b1, b2, b3, reads the feature mean / 1/std;
+ *   loss   : float32 [1], the step's loss L = sum_p |O(p) - G(p)|^2 / (3 n_pix).    */
+typedef struct sg_mlp_train {
+  float* master;
+  float* adam_m;
+  float* adam_v;
+  float* grad;
+  uint16_t* w_bf16;
+  float* b_f32;
+  float* loss;
+} sg_mlp_train;
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr, step number
+ * t >= 1) on the loss over the sets of the n_pix output pixels pixel_idx (device
+ * int32, indices into [0, P)); clean_rgb device [n_pix][3] float32 is the ground
+ * truth G of those pixels, row i for pixel_idx[i]. An index outside [0, P) is
+ * skipped. Forward uses the bfloat16 copy in state->w_bf16 / b_f32 (the previous step's
+ * result, or the caller's initial copy); the backward pass is float32. Requires the
+ * workspace of a gather of [f0, f1) with `params` (relative maps recomputed here). */
+sg_status scene_mlp_train_step(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, const sg_sample_sets* sets,
+                               const int32_t* pixel_idx, int32_t n_pix, const float* clean_rgb,
+                               sg_mlp_train* state, float lr, int32_t t, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -273,3 +273,106 @@ def scene_filter(clip: StagedClip, sets: SampleSets, params: FilterParams, out: 
     _check(_lib.scene_filter(ctypes.byref(cc), sets.f0, sets.f1, sets.window, ctypes.byref(ss), ctypes.byref(pp),
                              out.data_ptr(), _stream_handle()), "scene_filter")
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned per-sample weights
+
+SG_MLP_NW, SG_MLP_NB, SG_MLP_NPARAM = _native.SG_MLP_NW, _native.SG_MLP_NB, _native.SG_MLP_NPARAM
+
+
+def _bf16_bits(x: torch.Tensor) -> torch.Tensor:
+    return x.to(torch.float32).to(torch.bfloat16).view(torch.int16)
+
+
+@dataclass
+class MLPParams:
+    """Device copy of the MLP: w = bfloat16 [W1 (8x64), W2 (64x64), W3 (64)] as int16
+    bit patterns, b = float32 [b1 (64), b2 (64), b3, 3 unused, mean (8), 1/std (8)]."""
+    w: torch.Tensor
+    b: torch.Tensor
+
+    @staticmethod
+    def from_arrays(w1, b1, w2, b2, w3, b3, mean, std, device="cuda") -> "MLPParams":
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1)
+        w = torch.cat([t(w1), t(w2), t(w3)])
+        b = torch.cat([t(b1), t(b2), torch.tensor([float(b3), 0.0, 0.0, 0.0], dtype=torch.float64), t(mean),
+                       1.0 / t(std)])
+        return MLPParams(_bf16_bits(w).to(device).contiguous(), b.to(torch.float32).to(device).contiguous())
+
+    def c_struct(self) -> _native.SgMlp:
+        return _native.SgMlp(self.w.data_ptr(), self.b.data_ptr())
+
+    def weights_f64(self):
+        """(w1, b1, w2, b2, w3, b3) as float64 arrays of the stored values."""
+        w = self.w.view(torch.bfloat16).to(torch.float64).cpu().numpy()
+        b = self.b.to(torch.float64).cpu().numpy()
+        return (w[:512].reshape(8, 64), b[:64], w[512:512 + 4096].reshape(64, 64), b[64:128],
+                w[512 + 4096:], float(b[128]))
+
+
+def scene_filter_learned(clip: StagedClip, sets: SampleSets, params: GatherParams, mlp: MLPParams,
+                         ws: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Softmax-weighted mean of each set with MLP logits -> [f1 - f0, H, W, 3] float32."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    if ws is None:
+        ws = alloc_workspace(clip, sets.f0, sets.f1, params)
+    _need_gpu(out, "out", torch.float32)
+    _need_gpu(ws, "workspace", torch.uint8)
+    _need_gpu(mlp.w, "mlp.w", torch.int16)
+    _need_gpu(mlp.b, "mlp.b", torch.float32)
+    if tuple(out.shape) != shape or mlp.w.numel() != SG_MLP_NW or mlp.b.numel() != SG_MLP_NB:
+        raise SceneGatherError("scene_filter_learned: shape mismatch")
+    cc, pp, ss, mm = clip.c_struct(), params.c_struct(), sets.c_struct(), mlp.c_struct()
+    _check(_lib.scene_filter_learned(ctypes.byref(cc), sets.f0, sets.f1, ctypes.byref(pp), ctypes.byref(ss),
+                                     ctypes.byref(mm), ws.data_ptr(), ws.numel(), out.data_ptr(),
+                                     _stream_handle()), "scene_filter_learned")
+    return out
+
+
+class MLPTrainState:
+    """Device training state: float32 masters + Adam moments + gradient accumulator,
+    the bfloat16 forward copy (`params`) and the last step's loss."""
+
+    def __init__(self, init: MLPParams, w_master=None, b_master=None):
+        dev = init.w.device
+        if w_master is None:
+            w_master = init.w.view(torch.bfloat16).to(torch.float32)
+        if b_master is None:
+            b_master = init.b[:129].clone()
+        self.master = torch.cat([w_master.reshape(-1).to(dev, torch.float32),
+                                 b_master.reshape(-1).to(dev, torch.float32)]).contiguous()
+        assert self.master.numel() == SG_MLP_NPARAM
+        self.adam_m = torch.zeros_like(self.master)
+        self.adam_v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.params = MLPParams(init.w.clone(), init.b.clone())
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.t = 0
+
+    def c_struct(self) -> _native.SgMlpTrain:
+        return _native.SgMlpTrain(self.master.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr(),
+                                  self.grad.data_ptr(), self.params.w.data_ptr(), self.params.b.data_ptr(),
+                                  self.loss.data_ptr())
+
+
+def scene_mlp_train_step(clip: StagedClip, sets: SampleSets, params: GatherParams, pixel_idx: torch.Tensor,
+                         clean_rgb: torch.Tensor, state: MLPTrainState, lr: float,
+                         ws: torch.Tensor | None = None, t: int | None = None) -> None:
+    """One Adam step on the sets of `pixel_idx` (int32, indices into the P pixels of
+    [f0, f1)) against clean_rgb [len(pixel_idx), 3] float32, row i the ground truth of
+    pixel_idx[i]. Increments state.t unless t is given."""
+    _need_gpu(pixel_idx, "pixel_idx", torch.int32)
+    _need_gpu(clean_rgb, "clean_rgb", torch.float32)
+    if pixel_idx.dim() != 1 or tuple(clean_rgb.shape) != (pixel_idx.numel(), 3):
+        raise SceneGatherError("scene_mlp_train_step: pixel_idx must be [n] and clean_rgb [n, 3]")
+    if ws is None:
+        ws = alloc_workspace(clip, sets.f0, sets.f1, params)
+    state.t = state.t + 1 if t is None else t
+    cc, pp, ss, st = clip.c_struct(), params.c_struct(), sets.c_struct(), state.c_struct()
+    _check(_lib.scene_mlp_train_step(ctypes.byref(cc), sets.f0, sets.f1, ctypes.byref(pp), ctypes.byref(ss),
+                                     pixel_idx.data_ptr(), pixel_idx.numel(), clean_rgb.data_ptr(),
+                                     ctypes.byref(st), float(lr), int(state.t), ws.data_ptr(), ws.numel(),
+                                     _stream_handle()), "scene_mlp_train_step")

@@ -45,6 +45,20 @@ class SgFilterParams(ctypes.Structure):
                 ("sigma_t", ctypes.c_float), ("reserved", ctypes.c_float)]
 
 
+SG_MLP_NW = 8 * 64 + 64 * 64 + 64
+SG_MLP_NB = 64 + 64 + 4 + 8 + 8
+SG_MLP_NPARAM = SG_MLP_NW + 64 + 64 + 1
+
+
+class SgMlp(ctypes.Structure):
+    _fields_ = [("w", c_void_p), ("b", c_void_p)]
+
+
+class SgMlpTrain(ctypes.Structure):
+    _fields_ = [("master", c_void_p), ("adam_m", c_void_p), ("adam_v", c_void_p), ("grad", c_void_p),
+                ("w_bf16", c_void_p), ("b_f32", c_void_p), ("loss", c_void_p)]
+
+
 # name -> (restype, argtypes); every function declared in include/scene_gather.h
 SIGNATURES = {
     "sg_version": (ctypes.c_int32, []),
@@ -65,6 +79,13 @@ SIGNATURES = {
     "scene_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(SgSampleSets), ctypes.POINTER(SgFilterParams),
                                      c_void_p, c_void_p]),
+    "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                             ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),
+    "scene_mlp_train_step": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                             c_void_p, ctypes.c_int32, c_void_p, ctypes.POINTER(SgMlpTrain),
+                                             ctypes.c_float, ctypes.c_int32, c_void_p, ctypes.c_size_t, c_void_p]),
 }
 
 

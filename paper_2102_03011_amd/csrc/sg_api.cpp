@@ -212,4 +212,104 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
   return hip_status(sg::launch_filter(fj, static_cast<hipStream_t>(stream)));
 }
 
+static sg_status learned_prepare(const sg_clip* clip, int32_t f0, int32_t f1,
+                                 const sg_gather_params* params, const sg_sample_sets* sets,
+                                 void* ws, size_t ws_bytes, sg::GatherJob* jb, sg::LearnedJob* lj) {
+  sg_status s = check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if ((s = check_params(params)) != SG_OK) return s;
+  if (sets == nullptr || sets->offsets == nullptr || sets->capacity < 0) return SG_E_INVALID;
+  if (sets->capacity > 0 && (sets->ids == nullptr || sets->crho == nullptr)) return SG_E_INVALID;
+  if (ws == nullptr) return SG_E_INVALID;
+  const Layout l = layout(clip, f0, f1, params);
+  if (ws_bytes < l.total) return SG_E_INVALID;
+  char* base = static_cast<char*>(ws);
+  *jb = sg::GatherJob{};
+  jb->width = clip->width;
+  jb->height = clip->height;
+  jb->n_frames = clip->num_frames;
+  jb->f0 = f0;
+  jb->n_out = f1 - f0;
+  jb->w = params->window;
+  jb->fx = clip->fx;
+  jb->fy = clip->fy;
+  jb->cx = clip->cx;
+  jb->cy = clip->cy;
+  jb->c2w = clip->cam_to_world;
+  jb->rel = reinterpret_cast<float*>(base + l.rel_off);
+  jb->status = nullptr;
+  *lj = sg::LearnedJob{};
+  lj->width = clip->width;
+  lj->height = clip->height;
+  lj->n_frames = clip->num_frames;
+  lj->f0 = f0;
+  lj->w = params->window;
+  lj->n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
+  const double side = 2.0 * params->radius + 1.0;
+  lj->log_norm = static_cast<float>(log1p(side * side * (2.0 * params->window + 1.0)));
+  lj->fx = clip->fx;
+  lj->fy = clip->fy;
+  lj->cx = clip->cx;
+  lj->cy = clip->cy;
+  lj->rgbd = clip->rgbd;
+  lj->depth = clip->depth;
+  lj->rel = jb->rel;
+  lj->offsets = sets->offsets;
+  lj->ids = sets->ids;
+  lj->crho = sets->crho;
+  lj->capacity = sets->capacity;
+  return SG_OK;
+}
+
+sg_status scene_filter_learned(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, const sg_sample_sets* sets,
+                               const sg_mlp* mlp, void* workspace, size_t workspace_bytes,
+                               float* out_rgb, void* stream) {
+  sg::GatherJob jb;
+  sg::LearnedJob lj;
+  sg_status s = learned_prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, &jb, &lj);
+  if (s != SG_OK) return s;
+  if (mlp == nullptr || mlp->w == nullptr || mlp->b == nullptr || out_rgb == nullptr) return SG_E_INVALID;
+  lj.mw = mlp->w;
+  lj.mb = mlp->b;
+  lj.out = out_rgb;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = hip_status(sg::launch_pose_prep(jb, st))) != SG_OK) return s;
+  return hip_status(sg::launch_filter_learned(lj, st));
+}
+
+sg_status scene_mlp_train_step(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, const sg_sample_sets* sets,
+                               const int32_t* pixel_idx, int32_t n_pix, const float* clean_rgb,
+                               sg_mlp_train* state, float lr, int32_t t, void* workspace,
+                               size_t workspace_bytes, void* stream) {
+  sg::GatherJob jb;
+  sg::LearnedJob lj;
+  sg_status s = learned_prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, &jb, &lj);
+  if (s != SG_OK) return s;
+  if (state == nullptr || state->master == nullptr || state->adam_m == nullptr ||
+      state->adam_v == nullptr || state->grad == nullptr || state->w_bf16 == nullptr ||
+      state->b_f32 == nullptr || state->loss == nullptr)
+    return SG_E_INVALID;
+  if (n_pix < 0 || (n_pix > 0 && (pixel_idx == nullptr || clean_rgb == nullptr))) return SG_E_INVALID;
+  if (t < 1 || !(lr > 0.0f) || !isfinite(lr)) return SG_E_INVALID;
+  sg::TrainJob tj{};
+  tj.pixel_idx = pixel_idx;
+  tj.n_pix = n_pix;
+  tj.clean = clean_rgb;
+  tj.master = state->master;
+  tj.adam_m = state->adam_m;
+  tj.adam_v = state->adam_v;
+  tj.grad = state->grad;
+  tj.w_bf16 = state->w_bf16;
+  tj.b_f32 = state->b_f32;
+  tj.loss = state->loss;
+  tj.lr = lr;
+  tj.t = t;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = hip_status(sg::launch_pose_prep(jb, st))) != SG_OK) return s;
+  return hip_status(sg::launch_mlp_train(lj, tj, st));
+}
+
 }  // extern "C"

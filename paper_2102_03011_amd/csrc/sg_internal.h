@@ -45,6 +45,41 @@ struct FilterJob {
   float* out;
 };
 
+struct LearnedJob {
+  int width, height, n_frames, f0, w;
+  int64_t n_pix;
+  float log_norm;
+  double fx, fy, cx, cy;
+  const uint16_t* rgbd;
+  const uint16_t* depth;
+  const float* rel;
+  const int64_t* offsets;
+  const uint32_t* ids;
+  const uint16_t* crho;
+  int64_t capacity;
+  const uint16_t* mw;
+  const float* mb;
+  float* out;
+};
+
+struct TrainJob {
+  const int32_t* pixel_idx;
+  int n_pix;
+  const float* clean;
+  float* master;
+  float* adam_m;
+  float* adam_v;
+  float* grad;
+  uint16_t* w_bf16;
+  float* b_f32;
+  float* loss;
+  float lr;
+  int t;
+};
+
+hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st);
+hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st);
+
 hipError_t launch_stage(const uint8_t* rgb, const float* depth, int n_frames, int width, int height,
                         uint16_t* rgbd, uint16_t* depth16, hipStream_t st);
 hipError_t launch_pose_prep(const GatherJob& jb, hipStream_t st);

@@ -26,24 +26,10 @@
 
 #include <type_traits>
 
+#include "sg_device.h"
 #include "sg_internal.h"
 
 namespace sg {
-
-__device__ __forceinline__ float h2f(uint32_t bits16) {
-  return __half2float(__ushort_as_half(static_cast<unsigned short>(bits16 & 0xFFFFu)));
-}
-
-__device__ __forceinline__ uint32_t f2h(float v) {
-  return static_cast<uint32_t>(__half_as_ushort(__float2half_rn(v)));
-}
-
-constexpr uint32_t kInvalidDepth16 = 0x7E00u;  // binary16 quiet NaN
-
-__host__ __device__ __forceinline__ int stored_pitch(int width) {
-  return width + SG_APRON + SG_APRON_RIGHT;
-}
-__host__ __device__ __forceinline__ int stored_rows(int height) { return height + 2 * SG_APRON; }
 
 // Block rows are fetched as 8-byte words (four binary16 depths) starting at the
 // row's first column: kRowWords words cover the 2R + 1 columns.
@@ -236,11 +222,6 @@ __device__ __forceinline__ Tile tile_of_block(int tiles_x, int tiles_y) {
   t.ty = rest % tiles_y;
   t.fo = rest / tiles_y;
   return t;
-}
-
-// Stored-plane index of image pixel (x, y).
-__device__ __forceinline__ size_t padded_index(int x, int y, int pw) {
-  return static_cast<size_t>(y + SG_APRON) * pw + (x + SG_APRON);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,717 @@
+// Learned per-sample weights for the sample-set filter (gfx950, wave64).
+//
+// The weighted mean of Sec. 5 Eq. 3 takes its weights from a small MLP on eight
+// per-sample features, normalised over each set with a softmax (the learned
+// replacement of the hand-set Gaussian of Sec. 5.1 Eq. 4):
+//   O(p) = sum_s softmax(m)_s c_s,  m_s = MLP(standardised features of s).
+//
+// Inference (k_filter_learned): a wave serves 4 output pixels with 16 lanes each,
+// so every step feeds 64 samples through the MLP on the matrix cores
+// (v_mfma_f32_32x32x8_bf16: bfloat16 weights, operands as bfloat16 hi/lo pairs,
+// float32 accumulate). The layers are
+// evaluated transposed, H^T = W^T X^T (rows = hidden units, columns = samples):
+// then the accumulator layout of layer 1 is exactly the B-operand layout of
+// layer 2 (per lane: four consecutive hidden units of one sample), so the hidden
+// activations never leave registers. The softmax is evaluated online per lane and
+// merged over the pixel's 16 lanes.
+//
+// Training (k_mlp_train_grad): float32 on the vector units, one wave per pixel of
+// the minibatch: a forward pass over the set gives the softmax statistics and O(p);
+// a second pass recomputes each sample's forward pass, back-propagates
+// dL/dm_s = a_s (c_s - O) . dL/dO through the MLP and accumulates weight gradients
+// through LDS; k_mlp_adam applies Adam to the float32 masters.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_device.h"
+#include "sg_internal.h"
+
+namespace sg {
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int kNF = 8, kNH = 64;
+constexpr int kOffW2 = kNF * kNH;            // W2 inside the bfloat16 weight block
+constexpr int kOffW3 = kOffW2 + kNH * kNH;   // W3
+constexpr int kOffB2 = kNH, kOffB3 = 2 * kNH, kOffMean = 2 * kNH + 4, kOffInvStd = kOffMean + kNF;
+
+__device__ __forceinline__ uint32_t bf16_bits(float v) {  // round to nearest even
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_f(uint32_t b) { return __uint_as_float((b & 0xFFFFu) << 16); }
+
+// An operand of the matrix cores (a standardised feature, a layer-1 activation)
+// enters as two bfloat16 values, hi = bf16(v) and lo = bf16(v - hi) (v - hi is
+// exact in float32), so it carries about 16 significant bits; W v = W hi + W lo
+// takes two products. The kernel is bound by its vector work (features, GELU),
+// so the second product costs little, and no value is rounded to 8 bits.
+struct SplitBf16 {
+  uint32_t hi, lo;
+};
+__device__ __forceinline__ SplitBf16 split_bf16(float v) {
+  SplitBf16 r;
+  r.hi = bf16_bits(v);
+  r.lo = bf16_bits(v - bf16_to_f(r.hi));
+  return r;
+}
+__device__ __forceinline__ float split_value(float v) {
+  const SplitBf16 r = split_bf16(v);
+  return bf16_to_f(r.hi) + bf16_to_f(r.lo);
+}
+
+// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, with erf from Abramowitz and
+// Stegun 7.1.26 (Hastings' rational approximation, |error| <= 1.5e-7 for x >= 0):
+//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x).
+// For z < 0, Phi(z) = erfc(|z| / sqrt 2) / 2 directly (no cancellation). The same
+// exponential gives the normal density, so GELU'(z) = Phi(z) + z phi(z) is nearly free.
+constexpr float kAsP = 0.3275911f;
+constexpr float kAsA1 = 0.254829592f, kAsA2 = -0.284496736f, kAsA3 = 1.421413741f,
+                kAsA4 = -1.453152027f, kAsA5 = 1.061405429f;
+constexpr float kRsqrt2 = 0.7071067811865476f;
+constexpr float kInvSqrt2Pi = 0.3989422804014327f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+struct PhiPair {
+  float cdf, pdf;  // Phi(z), phi(z)
+};
+
+__device__ __forceinline__ PhiPair normal_cdf_pdf(float z) {
+  const float x = fabsf(z) * kRsqrt2;
+  const float t = __builtin_amdgcn_rcpf(fmaf(kAsP, x, 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, kAsA5, kAsA4), kAsA3), kAsA2), kAsA1);
+  const float g = __builtin_amdgcn_exp2f(-(x * x) * kLog2e);  // exp(-z^2 / 2)
+  const float half_erfc = 0.5f * poly * g;
+  PhiPair r;
+  r.cdf = z >= 0.0f ? 1.0f - half_erfc : half_erfc;
+  r.pdf = kInvSqrt2Pi * g;
+  return r;
+}
+__device__ __forceinline__ float gelu(float z) { return z * normal_cdf_pdf(z).cdf; }
+__device__ __forceinline__ float gelu_grad(float z) {
+  const PhiPair p = normal_cdf_pdf(z);
+  return fmaf(z, p.pdf, p.cdf);
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel context and the eight features of one sample.
+
+struct PixelCtx {
+  float x, y, dp;
+  int f;
+  float medr, medg, medb;
+  float x7;  // log(1 + n) / log(1 + (2r+1)^2 (2w+1))
+};
+
+struct FeatureArgs {
+  const float* rel;        // relative maps of this output frame, [2w+1][kRelStride]
+  const uint16_t* depth;   // stored depth planes
+  int width, height, n_frames, pw, w;
+  size_t pplane;
+  float inv_w, fx, fy, cx, cy;
+};
+
+__device__ __forceinline__ bool valid_depth(float d) { return d > 0.0f && d < INFINITY; }
+
+// A record id names frame slot id >> 22 of the window and source pixel id & (2^22 - 1);
+// one that lies outside the clip (sets from another gather) is skipped, not read.
+__device__ __forceinline__ bool id_in_clip(const FeatureArgs& a, int f, uint32_t id) {
+  const int slot = static_cast<int>(id >> SG_ID_SHIFT);
+  const int j = f + slot - a.w;
+  const uint32_t q = id & ((1u << SG_ID_SHIFT) - 1u);
+  return slot <= 2 * a.w && j >= 0 && j < a.n_frames &&
+         q < static_cast<uint32_t>(a.width) * static_cast<uint32_t>(a.height);
+}
+
+__device__ __forceinline__ void sample_features(const FeatureArgs& a, const PixelCtx& px, uint32_t id,
+                                                uint2 rec, float* feat) {
+  const int slot = static_cast<int>(id >> SG_ID_SHIFT);
+  const int dj = slot - a.w;
+  const int j = px.f + dj;
+  const int q = static_cast<int>(id & ((1u << SG_ID_SHIFT) - 1u));
+  int qy = static_cast<int>(static_cast<float>(q) / static_cast<float>(a.width));
+  int qx = q - qy * a.width;
+  if (qx < 0) { --qy; qx += a.width; }
+  if (qx >= a.width) { ++qy; qx -= a.width; }
+  const float* m = a.rel + slot * kRelStride;
+  const float a0 = fmaf(m[0], px.x, fmaf(m[1], px.y, m[2]));
+  const float a1 = fmaf(m[3], px.x, fmaf(m[4], px.y, m[5]));
+  const float a2 = fmaf(m[6], px.x, fmaf(m[7], px.y, m[8]));
+  const float y0 = fmaf(px.dp, a0, m[9]), y1 = fmaf(px.dp, a1, m[10]), z = fmaf(px.dp, a2, m[11]);
+  const float u = y0 / z, v = y1 / z;
+  // metric: X - o_f and X - o_J in frame-J axes (undo K on the folded map)
+  const float ax = (px.dp * a0 - a.cx * px.dp * a2) / a.fx;
+  const float ay = (px.dp * a1 - a.cy * px.dp * a2) / a.fy;
+  const float az = px.dp * a2;
+  const float tx = (m[9] - a.cx * m[11]) / a.fx, ty = (m[10] - a.cy * m[11]) / a.fy, tzv = m[11];
+  const float bx = ax + tx, by = ay + ty, bz = az + tzv;
+  // 1 - cos(angle) = |a/|a| - b/|b||^2 / 2: no cancellation for nearly parallel rays
+  const float ra = rsqrtf(ax * ax + ay * ay + az * az), rb = rsqrtf(bx * bx + by * by + bz * bz);
+  const float ux = ax * ra - bx * rb, uy = ay * ra - by * rb, uz = az * ra - bz * rb;
+  const float one_minus_cos = 0.5f * (ux * ux + uy * uy + uz * uz);
+  // depth gradient at q in J (apron neighbours read as invalid)
+  const uint16_t* dq = a.depth + static_cast<size_t>(j) * a.pplane + padded_index(qx, qy, a.pw);
+  const float d0 = h2f(dq[0]);
+  const float dxp = h2f(dq[1]), dxm = h2f(dq[-1]), dyp = h2f(dq[a.pw]), dym = h2f(dq[-a.pw]);
+  float gx = 0.0f, gy = 0.0f;
+  const bool vxp = valid_depth(dxp), vxm = valid_depth(dxm), vyp = valid_depth(dyp), vym = valid_depth(dym);
+  if (vxp && vxm) gx = 0.5f * (dxp - dxm); else if (vxp) gx = dxp - d0; else if (vxm) gx = d0 - dxm;
+  if (vyp && vym) gy = 0.5f * (dyp - dym); else if (vyp) gy = dyp - d0; else if (vym) gy = d0 - dym;
+  const float cr = h2f(rec.x), cg = h2f(rec.x >> 16), cb = h2f(rec.y);
+  const float er = cr - px.medr, eg = cg - px.medg, eb = cb - px.medb;
+  feat[0] = h2f(rec.y >> 16);
+  feat[1] = sqrtf(er * er + eg * eg + eb * eb);
+  feat[2] = fabsf(static_cast<float>(dj)) * a.inv_w;
+  feat[3] = sqrtf((qx - u) * (qx - u) + (qy - v) * (qy - v));
+  feat[4] = one_minus_cos;
+  feat[5] = sqrtf(gx * gx + gy * gy) / d0;
+  feat[6] = px.x7;
+  feat[7] = static_cast<float>(dj) * a.inv_w;
+}
+
+// Lower median (sorted[(n - 1) / 2]) of each colour channel over records [s, e),
+// by binary search on binary16 bit patterns (colours are non-negative, so the
+// patterns order like the values). Lanes lane0 .. lane0 + width - 1 cooperate.
+template <int kWidth>
+__device__ __forceinline__ void set_median(const uint2* __restrict__ crho, int64_t s, int64_t e, int sub,
+                                           float& mr, float& mg, float& mb) {
+  const int64_t n = e - s;
+  mr = mg = mb = 0.0f;
+  if (n <= 0) return;
+  const int need = static_cast<int>((n - 1) / 2 + 1);
+  uint32_t lo[3] = {0u, 0u, 0u}, hi[3] = {0x7BFFu, 0x7BFFu, 0x7BFFu};
+  for (int it = 0; it < 15; ++it) {
+    uint32_t mid[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mid[c] = (lo[c] + hi[c]) >> 1;
+    int cnt[3] = {0, 0, 0};
+    for (int64_t i = s + sub; i < e; i += kWidth) {
+      const uint2 r = crho[i];
+      cnt[0] += (r.x & 0xFFFFu) <= mid[0];
+      cnt[1] += (r.x >> 16) <= mid[1];
+      cnt[2] += (r.y & 0xFFFFu) <= mid[2];
+    }
+#pragma unroll
+    for (int off = kWidth / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cnt[c] += __shfl_xor(cnt[c], off, kWidth);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (cnt[c] >= need) hi[c] = mid[c]; else lo[c] = mid[c] + 1;
+    }
+  }
+  mr = h2f(lo[0]);
+  mg = h2f(lo[1]);
+  mb = h2f(lo[2]);
+}
+
+// ---------------------------------------------------------------------------
+// a7: learned filter (inference).
+
+constexpr int kLGroup = 16;  // lanes per output pixel
+
+__global__ __launch_bounds__(256) void k_filter_learned(
+    const uint2* __restrict__ rgbd, const uint16_t* __restrict__ depth, const float* __restrict__ rel,
+    int width, int height, int n_frames, int f0, int w, float log_norm, float fx, float fy, float cx, float cy,
+    int64_t n_pix, const int64_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
+    const uint2* __restrict__ crho, int64_t capacity, const uint16_t* __restrict__ mw,
+    const float* __restrict__ mb, float* __restrict__ out) {
+  __shared__ float s_b[SG_MLP_NB];
+  __shared__ float s_w3[kNH];
+  __shared__ uint4 s_x[2][4][64];  // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
+  for (int i = threadIdx.x + threadIdx.y * 64; i < SG_MLP_NB; i += 256) s_b[i] = mb[i];
+  for (int i = threadIdx.x + threadIdx.y * 64; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
+  __syncthreads();
+
+  const int lane = threadIdx.x, wv = threadIdx.y;
+  const int g = lane / kLGroup, sub = lane % kLGroup;
+  const int hi32 = lane >> 5, col = lane & 31;
+  const int64_t pix = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 4 + g;
+  const bool live_pix = pix < n_pix;
+  const size_t plane = static_cast<size_t>(width) * height;
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+
+  // A operands (rows = hidden units): layer 1 W1^T, layer 2 W2^T, kept in registers
+  v4i16 a1[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) a1[t][jj] = static_cast<short>(mw[(4 * hi32 + jj) * kNH + 32 * t + col]);
+  v4i16 a2[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+        a2[t][s8][jj] = static_cast<short>(mw[kOffW2 + (8 * s8 + 4 * hi32 + jj) * kNH + 32 * t + col]);
+
+  int64_t s = 0, e = 0;
+  bool bad = false;
+  PixelCtx px{};
+  float cref[3] = {0.f, 0.f, 0.f};
+  int fo = 0;
+  if (live_pix) {
+    fo = static_cast<int>(pix / static_cast<int64_t>(plane));
+    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
+    const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
+    const size_t pi = static_cast<size_t>(f0 + fo) * pplane + padded_index(x, y, pw);
+    const uint2 ref = rgbd[pi];
+    cref[0] = h2f(ref.x);
+    cref[1] = h2f(ref.x >> 16);
+    cref[2] = h2f(ref.y);
+    px.x = static_cast<float>(x);
+    px.y = static_cast<float>(y);
+    px.dp = h2f(depth[pi]);
+    px.f = f0 + fo;
+    s = offsets[pix];
+    e = offsets[pix + 1];
+    bad = s < 0 || e < s || e > capacity;
+    if (bad) s = e = 0;
+    px.x7 = __logf(1.0f + static_cast<float>(e - s)) / log_norm;
+  }
+  set_median<kLGroup>(crho, s, e, sub, px.medr, px.medg, px.medb);
+
+  FeatureArgs fa;
+  fa.rel = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
+  fa.depth = depth;
+  fa.width = width;
+  fa.height = height;
+  fa.n_frames = n_frames;
+  fa.pw = pw;
+  fa.w = w;
+  fa.pplane = pplane;
+  fa.inv_w = w > 0 ? 1.0f / static_cast<float>(w) : 0.0f;
+  fa.fx = fx;
+  fa.fy = fy;
+  fa.cx = cx;
+  fa.cy = cy;
+
+  // steps needed by the longest of the wave's four sets
+  int steps = static_cast<int>((e - s + kLGroup - 1) / kLGroup);
+#pragma unroll
+  for (int off = 16; off < 64; off <<= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+
+  float run_m = -INFINITY, run_z = 0.0f, acc[3] = {0.f, 0.f, 0.f};
+  const float b3 = s_b[kOffB3];
+  for (int st = 0; st < steps; ++st) {
+    const int64_t idx = s + static_cast<int64_t>(st) * kLGroup + sub;
+    bool live = idx < e;
+    uint2 rec = make_uint2(0u, 0u);
+    float feat[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live) {
+      const uint32_t id = ids[idx];
+      live = id_in_clip(fa, px.f, id);
+      if (live) {
+        rec = crho[idx];
+        sample_features(fa, px, id, rec, feat);
+      }
+    }
+    SplitBf16 xb[kNF];
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) xb[k] = split_bf16((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
+    s_x[0][wv][lane] = make_uint4(xb[0].hi | (xb[1].hi << 16), xb[2].hi | (xb[3].hi << 16),
+                                  xb[4].hi | (xb[5].hi << 16), xb[6].hi | (xb[7].hi << 16));
+    s_x[1][wv][lane] = make_uint4(xb[0].lo | (xb[1].lo << 16), xb[2].lo | (xb[3].lo << 16),
+                                  xb[4].lo | (xb[5].lo << 16), xb[6].lo | (xb[7].lo << 16));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    float m_own = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      // B operands of layer 1: features 4*hi32 .. +3 of sample 32u + col, hi and lo parts
+      v4i16 bx[2];
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const uint4 xs = s_x[part][wv][32 * u + col];
+        const uint32_t w01 = hi32 ? xs.z : xs.x, w23 = hi32 ? xs.w : xs.y;
+        bx[part][0] = static_cast<short>(w01 & 0xFFFFu);
+        bx[part][1] = static_cast<short>(w01 >> 16);
+        bx[part][2] = static_cast<short>(w23 & 0xFFFFu);
+        bx[part][3] = static_cast<short>(w23 >> 16);
+      }
+      // layer 1: hidden 32t + 8(a/4) + 4 hi32 + a%4 of sample 32u + col in element a
+      v4i16 h1[2][8];  // hi / lo B operands of layer 2, K-step s8 = 4t + a/4
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        v16f d = {};
+        d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx[0], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx[1], d, 0, 0, 0);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int hid = 32 * t + 8 * q4 + 4 * hi32 + r;
+            const SplitBf16 hv = split_bf16(gelu(d[4 * q4 + r] + s_b[hid]));
+            h1[0][4 * t + q4][r] = static_cast<short>(hv.hi);
+            h1[1][4 * t + q4][r] = static_cast<short>(hv.lo);
+          }
+      }
+      // layer 2 (hi and lo passes) and the output unit on the vector units
+      float mpart = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        v16f d = {};
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[t][s8], h1[0][s8], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[t][s8], h1[1][s8], d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int hid = 32 * t + 8 * q4 + 4 * hi32 + r;
+            mpart = fmaf(s_w3[hid], gelu(d[4 * q4 + r] + s_b[kOffB2 + hid]), mpart);
+          }
+      }
+      const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
+      if (u == hi32) m_own = msum;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (live) {
+      const float cr = h2f(rec.x), cg = h2f(rec.x >> 16), cb = h2f(rec.y);
+      const float nm = fmaxf(run_m, m_own);
+      const float sc = __builtin_amdgcn_exp2f((run_m - nm) * kLog2e);
+      const float ew = __builtin_amdgcn_exp2f((m_own - nm) * kLog2e);
+      run_z = fmaf(run_z, sc, ew);
+      acc[0] = fmaf(acc[0], sc, ew * cr);
+      acc[1] = fmaf(acc[1], sc, ew * cg);
+      acc[2] = fmaf(acc[2], sc, ew * cb);
+      run_m = nm;
+    }
+  }
+  // merge the 16 lanes of each pixel
+#pragma unroll
+  for (int off = kLGroup / 2; off > 0; off >>= 1) {
+    const float om = __shfl_xor(run_m, off, kLGroup);
+    const float oz = __shfl_xor(run_z, off, kLGroup);
+    const float o0 = __shfl_xor(acc[0], off, kLGroup), o1 = __shfl_xor(acc[1], off, kLGroup),
+                o2 = __shfl_xor(acc[2], off, kLGroup);
+    const float nm = fmaxf(run_m, om);
+    const float sa = run_z > 0.0f ? __builtin_amdgcn_exp2f((run_m - nm) * kLog2e) : 0.0f;
+    const float sb = oz > 0.0f ? __builtin_amdgcn_exp2f((om - nm) * kLog2e) : 0.0f;
+    run_z = run_z * sa + oz * sb;
+    acc[0] = acc[0] * sa + o0 * sb;
+    acc[1] = acc[1] * sa + o1 * sb;
+    acc[2] = acc[2] * sa + o2 * sb;
+    run_m = nm;
+  }
+  if (live_pix && sub == 0) {
+    float* o = out + static_cast<size_t>(pix) * 3;
+    if (bad) {
+      o[0] = o[1] = o[2] = __builtin_nanf("");
+    } else if (run_z > 0.0f) {
+      const float inv = 1.0f / run_z;
+      o[0] = acc[0] * inv;
+      o[1] = acc[1] * inv;
+      o[2] = acc[2] * inv;
+    } else {
+      o[0] = cref[0];
+      o[1] = cref[1];
+      o[2] = cref[2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a8: training. One wave (block of 64) per minibatch pixel at a time.
+
+constexpr int kTS = 65;  // LDS row stride (odd: conflict-free column access)
+
+struct TrainArgs {
+  const uint2* rgbd;
+  const uint16_t* depth;
+  const float* rel;
+  int width, height, n_frames, f0, w;
+  float log_norm, fx, fy, cx, cy;
+  const int64_t* offsets;
+  const uint32_t* ids;
+  const uint2* crho;
+  int64_t capacity, n_all;
+  const int32_t* pixel_idx;
+  int n_pix;
+  const float* clean;
+  const uint16_t* mw;
+  const float* mb;
+  float* grad;
+  float* loss;
+};
+
+// forward of one sample in float32, h1 carried as the hi + lo pair of the
+// inference kernel; leaves h1 in h1out, z2 in z2out; returns the logit.
+__device__ __forceinline__ float forward_sample(const float* xs, const float* s_w1, const float* s_w2,
+                                                const float* s_w3, const float* s_b, float* h1out,
+                                                float* z2out) {
+#pragma unroll 4
+  for (int i = 0; i < kNH; ++i) {
+    float z = s_b[i];
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) z = fmaf(xs[k], s_w1[k * kNH + i], z);
+    h1out[i] = split_value(gelu(z));
+  }
+  float m = s_b[kOffB3];
+  for (int j = 0; j < kNH; ++j) {
+    float z = s_b[kOffB2 + j];
+#pragma unroll 8
+    for (int i = 0; i < kNH; ++i) z = fmaf(h1out[i], s_w2[i * kNH + j], z);
+    z2out[j] = z;
+    m = fmaf(s_w3[j], gelu(z), m);
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
+  __shared__ float s_w1[kNF * kNH];
+  __shared__ float s_w2[kNH * kNH];
+  __shared__ float s_w3[kNH];
+  __shared__ float s_b[SG_MLP_NB];
+  __shared__ float s_h1[64 * kTS];
+  __shared__ float s_dz2[64 * kTS];
+  __shared__ float s_dz1[64 * kTS];
+  __shared__ float s_x[64 * 9];
+  __shared__ float s_dm[64];
+  __shared__ float s_h2w[64 * kTS];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < kNF * kNH; i += 64) s_w1[i] = bf16_to_f(ta.mw[i]);
+  for (int i = lane; i < kNH * kNH; i += 64) s_w2[i] = bf16_to_f(ta.mw[kOffW2 + i]);
+  s_w3[lane] = bf16_to_f(ta.mw[kOffW3 + lane]);
+  for (int i = lane; i < SG_MLP_NB; i += 64) s_b[i] = ta.mb[i];
+  __syncthreads();
+
+  const size_t plane = static_cast<size_t>(ta.width) * ta.height;
+  const int pw = stored_pitch(ta.width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
+  FeatureArgs fa;
+  fa.depth = ta.depth;
+  fa.width = ta.width;
+  fa.height = ta.height;
+  fa.n_frames = ta.n_frames;
+  fa.pw = pw;
+  fa.w = ta.w;
+  fa.pplane = pplane;
+  fa.inv_w = ta.w > 0 ? 1.0f / static_cast<float>(ta.w) : 0.0f;
+  fa.fx = ta.fx;
+  fa.fy = ta.fy;
+  fa.cx = ta.cx;
+  fa.cy = ta.cy;
+
+  // per-lane gradient accumulators: dW2 row `lane`, dW1 entries (k = lane/8, j = 8*(lane%8)+..),
+  // dW3[lane], db1[lane], db2[lane], db3 (lane 0)
+  float gw2[kNH];
+#pragma unroll
+  for (int j = 0; j < kNH; ++j) gw2[j] = 0.0f;
+  float gw1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float gw3 = 0.f, gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;
+  const float inv3n = 1.0f / (3.0f * static_cast<float>(ta.n_pix));
+
+  for (int bi = blockIdx.x; bi < ta.n_pix; bi += gridDim.x) {
+    const int64_t pix = ta.pixel_idx[bi];
+    if (pix < 0 || pix >= ta.n_all) continue;
+    const int fo = static_cast<int>(pix / static_cast<int64_t>(plane));
+    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
+    const int y = static_cast<int>(self / ta.width), x = static_cast<int>(self - static_cast<int64_t>(y) * ta.width);
+    const size_t pi = static_cast<size_t>(ta.f0 + fo) * pplane + padded_index(x, y, pw);
+    int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
+    if (s < 0 || e <= s || e > ta.capacity) continue;
+    PixelCtx px;
+    px.x = static_cast<float>(x);
+    px.y = static_cast<float>(y);
+    px.dp = h2f(ta.depth[pi]);
+    px.f = ta.f0 + fo;
+    px.x7 = __logf(1.0f + static_cast<float>(e - s)) / ta.log_norm;
+    set_median<64>(ta.crho, s, e, lane, px.medr, px.medg, px.medb);
+    fa.rel = ta.rel + static_cast<size_t>(fo) * (2 * ta.w + 1) * kRelStride;
+
+    float h1[kNH], z2[kNH];
+    // pass 1: softmax statistics and O(p)
+    float run_m = -INFINITY, run_z = 0.f, acc[3] = {0.f, 0.f, 0.f};
+    for (int64_t idx = s + lane; idx < e; idx += 64) {
+      const uint32_t id = ta.ids[idx];
+      if (!id_in_clip(fa, px.f, id)) continue;
+      const uint2 rec = ta.crho[idx];
+      float feat[kNF], xs[kNF];
+      sample_features(fa, px, id, rec, feat);
+#pragma unroll
+      for (int k = 0; k < kNF; ++k) xs[k] = split_value((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
+      const float m = forward_sample(xs, s_w1, s_w2, s_w3, s_b, h1, z2);
+      const float nm = fmaxf(run_m, m);
+      const float sc = __expf(run_m - nm), ew = __expf(m - nm);
+      run_z = fmaf(run_z, sc, ew);
+      acc[0] = fmaf(acc[0], sc, ew * h2f(rec.x));
+      acc[1] = fmaf(acc[1], sc, ew * h2f(rec.x >> 16));
+      acc[2] = fmaf(acc[2], sc, ew * h2f(rec.y));
+      run_m = nm;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float om = __shfl_xor(run_m, off, 64), oz = __shfl_xor(run_z, off, 64);
+      const float o0 = __shfl_xor(acc[0], off, 64), o1 = __shfl_xor(acc[1], off, 64), o2 = __shfl_xor(acc[2], off, 64);
+      const float nm = fmaxf(run_m, om);
+      const float sa = run_z > 0.f ? __expf(run_m - nm) : 0.f, sb = oz > 0.f ? __expf(om - nm) : 0.f;
+      run_z = run_z * sa + oz * sb;
+      acc[0] = acc[0] * sa + o0 * sb;
+      acc[1] = acc[1] * sa + o1 * sb;
+      acc[2] = acc[2] * sa + o2 * sb;
+      run_m = nm;
+    }
+    if (!(run_z > 0.0f)) continue;  // every record skipped: nothing to learn from (uniform)
+    const float zinv = 1.0f / run_z;
+    float o[3], dO[3];
+    float l2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o[c] = acc[c] * zinv;
+      const float d = o[c] - ta.clean[static_cast<size_t>(bi) * 3 + c];
+      l2 = fmaf(d, d, l2);
+      dO[c] = 2.0f * d * inv3n;
+    }
+    if (lane == 0) atomicAdd(ta.loss, l2 * inv3n);
+
+    // pass 2: backward, 64 samples per chunk
+    for (int64_t base = s; base < e; base += 64) {
+      const int64_t idx = base + lane;
+      const bool live = idx < e && id_in_clip(fa, px.f, ta.ids[idx]);
+      float xs[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float dm = 0.f;
+      if (live) {
+        const uint2 rec = ta.crho[idx];
+        float feat[kNF];
+        sample_features(fa, px, ta.ids[idx], rec, feat);
+#pragma unroll
+        for (int k = 0; k < kNF; ++k) xs[k] = split_value((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
+        const float m = forward_sample(xs, s_w1, s_w2, s_w3, s_b, h1, z2);
+        const float a = __expf(m - run_m) * zinv;
+        dm = a * ((h2f(rec.x) - o[0]) * dO[0] + (h2f(rec.x >> 16) - o[1]) * dO[1] +
+                  (h2f(rec.y) - o[2]) * dO[2]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < kNH; ++i) h1[i] = z2[i] = 0.f;
+      }
+      // dz2, h2; then dh1 -> dz1
+#pragma unroll 4
+      for (int j = 0; j < kNH; ++j) {
+        s_h2w[lane * kTS + j] = live ? gelu(z2[j]) : 0.f;
+        s_dz2[lane * kTS + j] = live ? dm * s_w3[j] * gelu_grad(z2[j]) : 0.f;
+        s_h1[lane * kTS + j] = h1[j];
+      }
+#pragma unroll 2
+      for (int i = 0; i < kNH; ++i) {
+        float dh = 0.f;
+#pragma unroll 8
+        for (int j = 0; j < kNH; ++j) dh = fmaf(s_w2[i * kNH + j], s_dz2[lane * kTS + j], dh);
+        float z1 = s_b[i];
+#pragma unroll
+        for (int k = 0; k < kNF; ++k) z1 = fmaf(xs[k], s_w1[k * kNH + i], z1);
+        s_dz1[lane * kTS + i] = live ? dh * gelu_grad(z1) : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kNF; ++k) s_x[lane * 9 + k] = xs[k];
+      s_dm[lane] = dm;
+      __syncthreads();
+      // weight gradients of this chunk
+      for (int r = 0; r < 64; ++r) {
+        const float h1v = s_h1[r * kTS + lane];
+#pragma unroll
+        for (int j = 0; j < kNH; ++j) gw2[j] = fmaf(h1v, s_dz2[r * kTS + j], gw2[j]);
+        const float xk = s_x[r * 9 + lane / 8];
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) gw1[jj] = fmaf(xk, s_dz1[r * kTS + 8 * (lane % 8) + jj], gw1[jj]);
+        gw3 = fmaf(s_dm[r], s_h2w[r * kTS + lane], gw3);
+        gb1 += s_dz1[r * kTS + lane];
+        gb2 += s_dz2[r * kTS + lane];
+        gb3 += s_dm[r];
+      }
+      __syncthreads();
+    }
+  }
+  // master order: W1 [8][64], W2 [64][64], W3 [64], b1 [64], b2 [64], b3
+#pragma unroll
+  for (int j = 0; j < kNH; ++j) atomicAdd(&ta.grad[kOffW2 + lane * kNH + j], gw2[j]);
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) atomicAdd(&ta.grad[(lane / 8) * kNH + 8 * (lane % 8) + jj], gw1[jj]);
+  atomicAdd(&ta.grad[kOffW3 + lane], gw3);
+  atomicAdd(&ta.grad[SG_MLP_NW + lane], gb1);
+  atomicAdd(&ta.grad[SG_MLP_NW + kNH + lane], gb2);
+  if (lane == 0) atomicAdd(&ta.grad[SG_MLP_NW + 2 * kNH], gb3);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ master, float* __restrict__ mm,
+                                                  float* __restrict__ vv, float* __restrict__ grad,
+                                                  uint16_t* __restrict__ wb, float* __restrict__ bf,
+                                                  float lr, float bc1, float bc2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= SG_MLP_NPARAM) return;
+  const float gv = grad[i];
+  const float m = 0.9f * mm[i] + 0.1f * gv;
+  const float v = 0.999f * vv[i] + 0.001f * gv * gv;
+  mm[i] = m;
+  vv[i] = v;
+  const float p = master[i] - lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+  master[i] = p;
+  grad[i] = 0.0f;
+  if (i < SG_MLP_NW) wb[i] = static_cast<uint16_t>(bf16_bits(p));
+  else bf[i - SG_MLP_NW] = p;  // b1, b2, b3 occupy the first 129 entries of b
+}
+
+__global__ void k_clear1(float* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st) {
+  const int64_t waves = (lj.n_pix + 3) / 4;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_filter_learned, dim3(static_cast<unsigned>(blocks)), dim3(64, 4), 0, st,
+                     reinterpret_cast<const uint2*>(lj.rgbd), lj.depth, lj.rel, lj.width, lj.height,
+                     lj.n_frames, lj.f0, lj.w, lj.log_norm, static_cast<float>(lj.fx), static_cast<float>(lj.fy),
+                     static_cast<float>(lj.cx), static_cast<float>(lj.cy), lj.n_pix, lj.offsets, lj.ids,
+                     reinterpret_cast<const uint2*>(lj.crho), lj.capacity, lj.mw, lj.mb, lj.out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear1, dim3(1), dim3(64), 0, st, tj.loss);
+  TrainArgs ta;
+  ta.rgbd = reinterpret_cast<const uint2*>(lj.rgbd);
+  ta.depth = lj.depth;
+  ta.rel = lj.rel;
+  ta.width = lj.width;
+  ta.height = lj.height;
+  ta.n_frames = lj.n_frames;
+  ta.f0 = lj.f0;
+  ta.w = lj.w;
+  ta.log_norm = lj.log_norm;
+  ta.fx = static_cast<float>(lj.fx);
+  ta.fy = static_cast<float>(lj.fy);
+  ta.cx = static_cast<float>(lj.cx);
+  ta.cy = static_cast<float>(lj.cy);
+  ta.offsets = lj.offsets;
+  ta.ids = lj.ids;
+  ta.crho = reinterpret_cast<const uint2*>(lj.crho);
+  ta.capacity = lj.capacity;
+  ta.n_all = lj.n_pix;
+  ta.pixel_idx = tj.pixel_idx;
+  ta.n_pix = tj.n_pix;
+  ta.clean = tj.clean;
+  ta.mw = tj.w_bf16;
+  ta.mb = tj.b_f32;
+  ta.grad = tj.grad;
+  ta.loss = tj.loss;
+  if (tj.n_pix > 0) {
+    const int blocks = tj.n_pix < 2048 ? tj.n_pix : 2048;
+    hipLaunchKernelGGL(k_mlp_train_grad, dim3(blocks), dim3(64), 0, st, ta);
+  }
+  const float bc1 = 1.0f - powf(0.9f, static_cast<float>(tj.t));
+  const float bc2 = 1.0f - powf(0.999f, static_cast<float>(tj.t));
+  hipLaunchKernelGGL(k_mlp_adam, dim3((SG_MLP_NPARAM + 255) / 256), dim3(256), 0, st, tj.master, tj.adam_m,
+                     tj.adam_v, tj.grad, tj.w_bf16, tj.b_f32, tj.lr, bc1, bc2);
+  return hipGetLastError();
+}
+
+}  // namespace sg

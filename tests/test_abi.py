@@ -152,3 +152,74 @@ def test_stage_rejects_bad_arguments(native):
     assert lib.scene_stage(0x1000, 0x1000, 2, 64, 32, None, 0x3000, None) == 1
     assert lib.scene_stage(0x1000, 0x1000, 2, 4097, 1024, 0x2000, 0x3000, None) == 4
     assert lib.scene_stage(0x1000, 0x1000, 70000, 64, 32, 0x2000, 0x3000, None) == 4
+
+
+def _mlp(mod):
+    return mod.SgMlp(0xA0000, 0xB0000)
+
+
+def _train_state(mod):
+    return mod.SgMlpTrain(0xC0000, 0xC1000, 0xC2000, 0xC3000, 0xC4000, 0xC5000, 0xC6000)
+
+
+@pytest.mark.parametrize("case", ["null_clip", "bad_range", "neg_window", "null_sets", "null_mlp", "null_w",
+                                  "null_out", "null_ws", "small_ws"])
+def test_learned_filter_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    s = _sets(mod, 100)
+    m = _mlp(mod)
+    cp, sp, mp = ctypes.byref(c), ctypes.byref(s), ctypes.byref(m)
+    f0, f1, ws, wsb, out = 2, 4, 0x80000, 1 << 20, 0x90000
+    if case == "null_clip":
+        cp = None
+    elif case == "bad_range":
+        f1 = 1
+    elif case == "neg_window":
+        p.window = -2
+    elif case == "null_sets":
+        sp = None
+    elif case == "null_mlp":
+        mp = None
+    elif case == "null_w":
+        m.w = None
+    elif case == "null_out":
+        out = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb = 8
+    assert lib.scene_filter_learned(cp, f0, f1, ctypes.byref(p), sp, mp, ws, wsb, out, None) == 1, case
+
+
+@pytest.mark.parametrize("case", ["null_state", "null_master", "neg_pixels", "null_idx", "t_zero", "lr_zero",
+                                  "lr_nan", "null_clean", "small_ws"])
+def test_train_step_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    s = _sets(mod, 100)
+    st = _train_state(mod)
+    stp = ctypes.byref(st)
+    idx, n, clean, lr, t, ws, wsb = 0xD0000, 64, 0xE0000, 1e-3, 1, 0x80000, 1 << 20
+    if case == "null_state":
+        stp = None
+    elif case == "null_master":
+        st.master = None
+    elif case == "neg_pixels":
+        n = -1
+    elif case == "null_idx":
+        idx = None
+    elif case == "t_zero":
+        t = 0
+    elif case == "lr_zero":
+        lr = 0.0
+    elif case == "lr_nan":
+        lr = math.nan
+    elif case == "null_clean":
+        clean = None
+    elif case == "small_ws":
+        wsb = 8
+    assert lib.scene_mlp_train_step(ctypes.byref(c), 2, 4, ctypes.byref(p), ctypes.byref(s), idx, n, clean, stp,
+                                    lr, t, ws, wsb, None) == 1, case
