@@ -246,6 +246,17 @@ sg_status scene_mlp_train_step(const sg_clip* clip, int32_t f0, int32_t f1,
                                sg_mlp_train* state, float lr, int32_t t, void* workspace,
                                size_t workspace_bytes, void* stream);
 
+/* Feature statistics for the standardisation of the MLP input: over the records
+ * of the sets of pixel_idx[0 .. n_pix) (device int32 indices into [0, P); an index
+ * outside is skipped), ADDS the record count to moments[0], the sum of raw feature
+ * k to moments[1 + k] and the sum of its square to moments[9 + k] (device float64
+ * [17]; the caller clears it, and can accumulate over several calls and clips).
+ * Same workspace contract as scene_filter_learned. */
+sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
+                                const sg_gather_params* params, const sg_sample_sets* sets,
+                                const int32_t* pixel_idx, int32_t n_pix, double* moments,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

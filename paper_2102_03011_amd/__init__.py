@@ -14,6 +14,7 @@ import ctypes
 import math
 from dataclasses import dataclass
 
+import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to by soname)
 
 from . import _native
@@ -376,3 +377,37 @@ def scene_mlp_train_step(clip: StagedClip, sets: SampleSets, params: GatherParam
                                      pixel_idx.data_ptr(), pixel_idx.numel(), clean_rgb.data_ptr(),
                                      ctypes.byref(st), float(lr), int(state.t), ws.data_ptr(), ws.numel(),
                                      _stream_handle()), "scene_mlp_train_step")
+
+
+N_FEATURES = 8
+
+
+def scene_feature_moments(clip: StagedClip, sets: SampleSets, params: GatherParams, pixel_idx: torch.Tensor,
+                          moments: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Add the record count, per-feature sums and sums of squares over the sets of
+    `pixel_idx` into `moments` (float64 [17] on the device; new and zeroed if None)."""
+    _need_gpu(pixel_idx, "pixel_idx", torch.int32)
+    if moments is None:
+        moments = torch.zeros(1 + 2 * N_FEATURES, dtype=torch.float64, device=clip.rgbd.device)
+    _need_gpu(moments, "moments", torch.float64)
+    if moments.numel() != 1 + 2 * N_FEATURES or pixel_idx.dim() != 1:
+        raise SceneGatherError("scene_feature_moments: moments must have 17 entries, pixel_idx be 1-D")
+    if ws is None:
+        ws = alloc_workspace(clip, sets.f0, sets.f1, params)
+    cc, pp, ss = clip.c_struct(), params.c_struct(), sets.c_struct()
+    _check(_lib.scene_feature_moments(ctypes.byref(cc), sets.f0, sets.f1, ctypes.byref(pp), ctypes.byref(ss),
+                                      pixel_idx.data_ptr(), pixel_idx.numel(), moments.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream_handle()), "scene_feature_moments")
+    return moments
+
+
+def standardisation_from_moments(moments: torch.Tensor):
+    """(mean, std) float64 numpy arrays [8] from accumulated moments; a feature
+    with no spread gets std 1."""
+    m = moments.detach().cpu().double().numpy()
+    n = max(m[0], 1.0)
+    mean = m[1:1 + N_FEATURES] / n
+    var = np.maximum(m[1 + N_FEATURES:] / n - mean * mean, 0.0)
+    std = np.sqrt(var)
+    std[~(std > 1e-12 * np.maximum(np.abs(mean), 1.0))] = 1.0
+    return mean, std

@@ -82,6 +82,10 @@ SIGNATURES = {
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),
+    "scene_feature_moments": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                              c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_size_t,
+                                              c_void_p]),
     "scene_mlp_train_step": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              c_void_p, ctypes.c_int32, c_void_p, ctypes.POINTER(SgMlpTrain),

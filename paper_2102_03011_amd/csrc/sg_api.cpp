@@ -312,4 +312,18 @@ sg_status scene_mlp_train_step(const sg_clip* clip, int32_t f0, int32_t f1,
   return hip_status(sg::launch_mlp_train(lj, tj, st));
 }
 
+sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
+                                const sg_gather_params* params, const sg_sample_sets* sets,
+                                const int32_t* pixel_idx, int32_t n_pix, double* moments,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+  sg::GatherJob jb;
+  sg::LearnedJob lj;
+  sg_status s = learned_prepare(clip, f0, f1, params, sets, workspace, workspace_bytes, &jb, &lj);
+  if (s != SG_OK) return s;
+  if (n_pix < 0 || moments == nullptr || (n_pix > 0 && pixel_idx == nullptr)) return SG_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = hip_status(sg::launch_pose_prep(jb, st))) != SG_OK) return s;
+  return hip_status(sg::launch_feature_moments(lj, pixel_idx, n_pix, moments, st));
+}
+
 }  // extern "C"

@@ -79,6 +79,8 @@ struct TrainJob {
 
 hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st);
 hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st);
+hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,
+                                  hipStream_t st);
 
 hipError_t launch_stage(const uint8_t* rgb, const float* depth, int n_frames, int width, int height,
                         uint16_t* rgbd, uint16_t* depth16, hipStream_t st);

@@ -660,6 +660,79 @@ __global__ void k_clear1(float* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0f;
 }
 
+// Feature statistics for the standardisation: adds, over the records of the
+// minibatch pixels, the record count, sum x_k and sum x_k^2 of the raw features
+// into moments[0], [1 + k], [9 + k] (float64). One wave per pixel.
+__global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta, double* __restrict__ moments) {
+  const int lane = threadIdx.x;
+  const size_t plane = static_cast<size_t>(ta.width) * ta.height;
+  const int pw = stored_pitch(ta.width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
+  FeatureArgs fa;
+  fa.depth = ta.depth;
+  fa.width = ta.width;
+  fa.height = ta.height;
+  fa.n_frames = ta.n_frames;
+  fa.pw = pw;
+  fa.w = ta.w;
+  fa.pplane = pplane;
+  fa.inv_w = ta.w > 0 ? 1.0f / static_cast<float>(ta.w) : 0.0f;
+  fa.fx = ta.fx;
+  fa.fy = ta.fy;
+  fa.cx = ta.cx;
+  fa.cy = ta.cy;
+  double cnt = 0.0, sum[kNF], sq[kNF];
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) sum[k] = sq[k] = 0.0;
+  for (int bi = blockIdx.x; bi < ta.n_pix; bi += gridDim.x) {
+    const int64_t pix = ta.pixel_idx[bi];
+    if (pix < 0 || pix >= ta.n_all) continue;
+    const int fo = static_cast<int>(pix / static_cast<int64_t>(plane));
+    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
+    const int y = static_cast<int>(self / ta.width), x = static_cast<int>(self - static_cast<int64_t>(y) * ta.width);
+    const size_t pi = static_cast<size_t>(ta.f0 + fo) * pplane + padded_index(x, y, pw);
+    const int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
+    if (s < 0 || e <= s || e > ta.capacity) continue;
+    PixelCtx px;
+    px.x = static_cast<float>(x);
+    px.y = static_cast<float>(y);
+    px.dp = h2f(ta.depth[pi]);
+    px.f = ta.f0 + fo;
+    px.x7 = __logf(1.0f + static_cast<float>(e - s)) / ta.log_norm;
+    set_median<64>(ta.crho, s, e, lane, px.medr, px.medg, px.medb);
+    fa.rel = ta.rel + static_cast<size_t>(fo) * (2 * ta.w + 1) * kRelStride;
+    for (int64_t idx = s + lane; idx < e; idx += 64) {
+      const uint32_t id = ta.ids[idx];
+      if (!id_in_clip(fa, px.f, id)) continue;
+      float feat[kNF];
+      sample_features(fa, px, id, ta.crho[idx], feat);
+      cnt += 1.0;
+#pragma unroll
+      for (int k = 0; k < kNF; ++k) {
+        sum[k] += feat[k];
+        sq[k] += static_cast<double>(feat[k]) * feat[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_xor(cnt, off, 64);
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) {
+      sum[k] += __shfl_xor(sum[k], off, 64);
+      sq[k] += __shfl_xor(sq[k], off, 64);
+    }
+  }
+  if (lane == 0 && cnt > 0.0) {
+    atomicAdd(&moments[0], cnt);
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) {
+      atomicAdd(&moments[1 + k], sum[k]);
+      atomicAdd(&moments[1 + kNF + k], sq[k]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -675,9 +748,8 @@ hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st) {
-  hipLaunchKernelGGL(k_clear1, dim3(1), dim3(64), 0, st, tj.loss);
-  TrainArgs ta;
+static TrainArgs train_args(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix) {
+  TrainArgs ta{};
   ta.rgbd = reinterpret_cast<const uint2*>(lj.rgbd);
   ta.depth = lj.depth;
   ta.rel = lj.rel;
@@ -696,8 +768,23 @@ hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_
   ta.crho = reinterpret_cast<const uint2*>(lj.crho);
   ta.capacity = lj.capacity;
   ta.n_all = lj.n_pix;
-  ta.pixel_idx = tj.pixel_idx;
-  ta.n_pix = tj.n_pix;
+  ta.pixel_idx = pixel_idx;
+  ta.n_pix = n_pix;
+  return ta;
+}
+
+hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,
+                                  hipStream_t st) {
+  if (n_pix <= 0) return hipSuccess;
+  const TrainArgs ta = train_args(lj, pixel_idx, n_pix);
+  const int blocks = n_pix < 4096 ? n_pix : 4096;
+  hipLaunchKernelGGL(k_feature_moments, dim3(blocks), dim3(64), 0, st, ta, moments);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear1, dim3(1), dim3(64), 0, st, tj.loss);
+  TrainArgs ta = train_args(lj, tj.pixel_idx, tj.n_pix);
   ta.clean = tj.clean;
   ta.mw = tj.w_bf16;
   ta.mb = tj.b_f32;

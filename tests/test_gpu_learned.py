@@ -281,3 +281,32 @@ def test_train_step_skips_out_of_range_pixels(small):
     assert torch.equal(state.master, master0)
     with pytest.raises(sg.SceneGatherError):
         sg.scene_mlp_train_step(small.staged, small.sets, small.params, idx, clean[:2], state, 1e-2)
+
+
+def test_feature_moments_match_oracle(small):
+    sg = _sg()
+    pixels = _train_batch(small, 700, 3)
+    off, x, _ = small.features(pixels)
+    idx = torch.tensor(pixels, dtype=torch.int32, device="cuda")
+    mom = sg.scene_feature_moments(small.staged, small.sets, small.params, idx)
+    mom = sg.scene_feature_moments(small.staged, small.sets, small.params, idx[:100], moments=mom)
+    got = mom.cpu().numpy()
+    x2 = np.concatenate([x, x[:off[100]]])
+    assert got[0] == x2.shape[0]
+    # float32 features summed in float64: relative 1e-5 of the sum of magnitudes
+    assert np.all(np.abs(got[1:9] - x2.sum(0)) <= 1e-5 * np.abs(x2).sum(0) + 1e-12)
+    assert np.all(np.abs(got[9:] - (x2 * x2).sum(0)) <= 1e-5 * (x2 * x2).sum(0) + 1e-12)
+    mean, std = sg.standardisation_from_moments(mom)
+    assert np.allclose(mean, x2.mean(0), rtol=1e-5, atol=1e-9)
+
+
+def test_training_driver_runs_and_checkpoint_loads(tmp_path):
+    from paper_2102_03011_amd import train
+    params, meta = train.train(n_clips=2, frames_per_clip=1, steps_per_frame=5, batch=512, stats_clips=1,
+                               log=lambda s: None)
+    assert math.isfinite(meta["final_loss"]) and meta["steps"] == 10
+    path = str(tmp_path / "w.npz")
+    train.save_mlp(path, params, meta)
+    back, meta2 = train.load_mlp(path)
+    assert torch.equal(back.w, params.w) and torch.equal(back.b, params.b)
+    assert meta2["steps"] == 10
