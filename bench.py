@@ -90,6 +90,118 @@ def cpu_baseline(clip, wl, f: int, row_step: int) -> dict:
             "host_cores": os.cpu_count()}
 
 
+MLP_FLOP_PER_SAMPLE = 2 * (8 * 64 + 64 * 64 + 64)   # 8 -> 64 -> 64 -> 1, multiply-adds x 2
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int) -> dict:
+    """The learned-weight filter on the same gathers (window +-w), timed like the plain
+    step; PSNR of plain and learned on a few spread frames; and the learned path at
+    the largest smaller window whose whole step is no slower than the plain step."""
+    import torch
+    from paper_2102_03011_amd import train
+
+    try:
+        mlp, meta = train.load_mlp()
+    except OSError as e:
+        return {"skipped": f"no trained weights ({e})"}
+    dev = staged.rgbd.device
+    n, h, w = clip.n_frames, clip.height, clip.width
+
+    def arena_for(p, frames):
+        plan = sg.alloc_sets(staged, 0, 1, p.window, 0)
+        ws = sg.alloc_workspace(staged, 0, 1, p)
+        tot = {}
+        for f in frames:
+            sg.scene_gather_count(staged, f, f + 1, p, plan, ws)
+            tot[f] = plan.total()
+        return sg.alloc_sets(staged, 0, 1, p.window, max(tot.values())), ws, tot
+
+    def step_fn(p, arena, ws, out, learned: bool):
+        def run(f, ev=None):
+            sgs = sg.SampleSets(f, f + 1, p.window, arena.offsets, arena.ids, arena.crho, arena.status)
+            g = min(n - 1, f + p.window)   # the frame entering the window, as in the plain step
+            sg.scene_stage_into(staged, clip.rgb_u8[g], clip.depth[g], g)
+            sg.scene_gather_count(staged, f, f + 1, p, sgs, ws)
+            sg.scene_gather_scatter(staged, f, f + 1, p, sgs, ws)
+            if ev is not None:
+                ev[0].record()
+            if learned:
+                sg.scene_filter_learned(staged, sgs, p, mlp, ws=ws, out=out)
+            else:
+                sg.scene_filter(staged, sgs, fparams, out=out)
+            if ev is not None:
+                ev[1].record()
+            return sgs
+        return run
+
+    def timed_run(run, frames):
+        run(frames[0])
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in frames]
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k, f in enumerate(frames):
+            run(f, evs[k])
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / len(frames), sum(e[0].elapsed_time(e[1]) for e in evs) / len(frames)
+
+    def psnr(x, ref):
+        mse = torch.mean((x.to(torch.float64) - ref) ** 2).item()
+        return 10 * math.log10(1 / mse)
+
+    frames = timed[:steps]
+    quality = sorted(set(timed[i * len(timed) // 4] for i in range(4)))
+    out = torch.empty((1, h, w, 3), dtype=torch.float32, device=dev)
+    arena, ws, tot = arena_for(params, sorted(set(frames) | set(quality)))
+    ms_l, ms_lf = timed_run(step_fn(params, arena, ws, out, True), frames)
+    samples = sum(tot[f] for f in frames) / len(frames)
+    # quality on the same gathers
+    ps_plain, ps_learned = [], []
+    for f in quality:
+        clean = clip.clean_u8[f].to(dev, torch.float64) / 255.0
+        sgs = step_fn(params, arena, ws, out, False)(f)
+        ps_plain.append(psnr(out[0], clean))
+        sg.scene_filter_learned(staged, sgs, params, mlp, ws=ws, out=out)
+        ps_learned.append(psnr(out[0], clean))
+    res = {"weights": os.path.relpath(train.DEFAULT_WEIGHTS, ROOT), "trained_on": meta.get("clips"),
+           "window": params.window, "ms_per_step": ms_l, "filter_ms": ms_lf,
+           "samples_per_s": samples / (ms_l / 1e3),
+           "mlp_tflops": samples * MLP_FLOP_PER_SAMPLE / (ms_lf / 1e3) / 1e12,
+           "mlp_frac_of_bf16_peak": samples * MLP_FLOP_PER_SAMPLE / (ms_lf / 1e3) / 1e12 / BF16_DENSE_PEAK_TFLOPS,
+           "quality_frames": quality, "psnr_plain_db": sum(ps_plain) / len(ps_plain),
+           "psnr_learned_db": sum(ps_learned) / len(ps_learned)}
+    log(f"learned w={params.window}: {ms_l:.2f} ms/step (filter {ms_lf:.2f}), PSNR plain "
+        f"{res['psnr_plain_db']:.2f} learned {res['psnr_learned_db']:.2f}")
+    del arena, ws
+    # equal time: the largest window whose learned step fits the plain step's time;
+    # the whole window / time / PSNR curve is reported
+    curve = []
+    for wq in (40, 30, 20, 12, 8, 6, 4, 3, 2, 1):
+        if wq >= params.window:
+            continue
+        pq = sg.GatherParams(window=wq, radius=params.radius, tol=params.tol, z_near=params.z_near)
+        arena, ws, totq = arena_for(pq, sorted(set(frames) | set(quality)))
+        ms_q, ms_qf = timed_run(step_fn(pq, arena, ws, out, True), frames)
+        pl = []
+        for f in quality:
+            clean = clip.clean_u8[f].to(dev, torch.float64) / 255.0
+            step_fn(pq, arena, ws, out, True)(f)
+            pl.append(psnr(out[0], clean))
+        row = {"window": wq, "ms_per_step": ms_q, "filter_ms": ms_qf, "psnr_learned_db": sum(pl) / len(pl),
+               "samples_per_pixel": sum(totq[f] for f in frames) / len(frames) / (h * w)}
+        curve.append(row)
+        log(f"learned w={wq}: {ms_q:.2f} ms/step, PSNR {row['psnr_learned_db']:.2f} "
+            f"(plain w={params.window}: {plain_ms:.2f} ms, {res['psnr_plain_db']:.2f} dB)")
+        if ms_q <= plain_ms and "equal_time" not in res:
+            res["equal_time"] = {**row, "plain_ms_per_step": plain_ms,
+                                 "psnr_plain_db_full_window": res["psnr_plain_db"]}
+        del arena, ws
+    res["curve"] = curve
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +210,8 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=300, help="clip length (the workload uses 300)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-step", type=int, default=16)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
+    ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one plain 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
@@ -227,6 +341,9 @@ def main() -> int:
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if not args.no_learned:
+        res["learned"] = learned_leg(sg, clip, staged, wl, params, fparams, frames[args.warmup:], ms_step,
+                                     args.learned_steps)
     if args.copy_probe:
         x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)

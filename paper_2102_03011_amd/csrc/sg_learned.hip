@@ -7,7 +7,7 @@
 //
 // Inference (k_filter_learned): a wave serves 4 output pixels with 16 lanes each,
 // so every step feeds 64 samples through the MLP on the matrix cores
-// (v_mfma_f32_32x32x8_bf16: bfloat16 weights, operands as bfloat16 hi/lo pairs,
+// (v_mfma_f32_32x32x16_bf16: bfloat16 weights, operands as bfloat16 hi/lo pairs,
 // float32 accumulate). The layers are
 // evaluated transposed, H^T = W^T X^T (rows = hidden units, columns = samples):
 // then the accumulator layout of layer 1 is exactly the B-operand layout of
@@ -28,7 +28,6 @@
 
 namespace sg {
 
-typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kNF = 8, kNH = 64;
@@ -61,37 +60,68 @@ __device__ __forceinline__ float split_value(float v) {
   return bf16_to_f(r.hi) + bf16_to_f(r.lo);
 }
 
-// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, with erf from Abramowitz and
-// Stegun 7.1.26 (Hastings' rational approximation, |error| <= 1.5e-7 for x >= 0):
-//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),  t = 1 / (1 + p x).
-// For z < 0, Phi(z) = erfc(|z| / sqrt 2) / 2 directly (no cancellation). The same
-// exponential gives the normal density, so GELU'(z) = Phi(z) + z phi(z) is nearly free.
-constexpr float kAsP = 0.3275911f;
-constexpr float kAsA1 = 0.254829592f, kAsA2 = -0.284496736f, kAsA3 = 1.421413741f,
-                kAsA4 = -1.453152027f, kAsA5 = 1.061405429f;
-constexpr float kRsqrt2 = 0.7071067811865476f;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two values to packed bfloat16 (round to nearest even, a in the low half): one
+// v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+// hi/lo split of two values as packed pairs (same values as split_bf16)
+__device__ __forceinline__ void split_pack(float a, float b, uint32_t& hi, uint32_t& lo) {
+  hi = pack_bf16(a, b);
+  lo = pack_bf16(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xFFFF0000u));
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// GELU(z) = z Phi(z) = z/2 + (|z|/2) erf(|z| / sqrt 2), with erf from Abramowitz and
+// Stegun 7.1.28 (|error| <= 3e-7 for x >= 0):
+//   erf(x) = 1 - 1 / (1 + a1 x + a2 x^2 + ... + a6 x^6)^16.
+// The kernels evaluate it at y = z/2 (the matrix products use W/2 and b/2, which
+// are exact in bfloat16): x = sqrt(2) |y|, so the polynomial in |y| has
+// coefficients a_k 2^(k/2) and constant term 1, and GELU = y + |y| erf. Six
+// multiply-adds, four squarings, one reciprocal and one subtraction; for large
+// |y| the 16th power overflows to +inf and erf = 1 exactly.
+constexpr float kE1 = static_cast<float>(0.0705230784 * 1.4142135623730951);
+constexpr float kE2 = static_cast<float>(0.0422820123 * 2.0);
+constexpr float kE3 = static_cast<float>(0.0092705272 * 2.8284271247461903);
+constexpr float kE4 = static_cast<float>(0.0001520143 * 4.0);
+constexpr float kE5 = static_cast<float>(0.0002765672 * 5.6568542494923806);
+constexpr float kE6 = static_cast<float>(0.0000430638 * 8.0);
 constexpr float kInvSqrt2Pi = 0.3989422804014327f;
 constexpr float kLog2e = 1.4426950408889634f;
 
-struct PhiPair {
-  float cdf, pdf;  // Phi(z), phi(z)
-};
-
-__device__ __forceinline__ PhiPair normal_cdf_pdf(float z) {
-  const float x = fabsf(z) * kRsqrt2;
-  const float t = __builtin_amdgcn_rcpf(fmaf(kAsP, x, 1.0f));
-  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, kAsA5, kAsA4), kAsA3), kAsA2), kAsA1);
-  const float g = __builtin_amdgcn_exp2f(-(x * x) * kLog2e);  // exp(-z^2 / 2)
-  const float half_erfc = 0.5f * poly * g;
-  PhiPair r;
-  r.cdf = z >= 0.0f ? 1.0f - half_erfc : half_erfc;
-  r.pdf = kInvSqrt2Pi * g;
-  return r;
+__device__ __forceinline__ float erf_of_half(float y) {  // erf(sqrt(2) |y|)
+  const float a = fabsf(y);
+  float q = fmaf(kE6, a, kE5);
+  q = fmaf(q, a, kE4);
+  q = fmaf(q, a, kE3);
+  q = fmaf(q, a, kE2);
+  q = fmaf(q, a, kE1);
+  q = fmaf(q, a, 1.0f);
+  q *= q;
+  q *= q;
+  q *= q;
+  q *= q;
+  return 1.0f - __builtin_amdgcn_rcpf(q);
 }
-__device__ __forceinline__ float gelu(float z) { return z * normal_cdf_pdf(z).cdf; }
+// GELU(2y) from y = z/2
+__device__ __forceinline__ float gelu_half(float y) { return fmaf(fabsf(y), erf_of_half(y), y); }
+__device__ __forceinline__ float gelu(float z) { return gelu_half(0.5f * z); }
+// GELU'(z) = Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad(float z) {
-  const PhiPair p = normal_cdf_pdf(z);
-  return fmaf(z, p.pdf, p.cdf);
+  const float e = erf_of_half(0.5f * z);
+  const float cdf = 0.5f + (z >= 0.0f ? 0.5f * e : -0.5f * e);
+  const float pdf = kInvSqrt2Pi * __builtin_amdgcn_exp2f(-0.5f * kLog2e * z * z);
+  return fmaf(z, pdf, cdf);
+}
+// bfloat16 bits of w / 2 (exact for every normal bfloat16)
+__device__ __forceinline__ uint32_t bf16_half_bits(uint16_t b) {
+  return __float_as_uint(__uint_as_float(static_cast<uint32_t>(b) << 16) * 0.5f) >> 16;
 }
 
 // ---------------------------------------------------------------------------
@@ -218,9 +248,11 @@ __global__ __launch_bounds__(256) void k_filter_learned(
     const uint2* __restrict__ crho, int64_t capacity, const uint16_t* __restrict__ mw,
     const float* __restrict__ mb, float* __restrict__ out) {
   __shared__ float s_b[SG_MLP_NB];
+  __shared__ float s_bh[2 * kNH];  // b1 / 2, b2 / 2
   __shared__ float s_w3[kNH];
   __shared__ uint4 s_x[2][4][64];  // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
   for (int i = threadIdx.x + threadIdx.y * 64; i < SG_MLP_NB; i += 256) s_b[i] = mb[i];
+  for (int i = threadIdx.x + threadIdx.y * 64; i < 2 * kNH; i += 256) s_bh[i] = 0.5f * mb[i];
   for (int i = threadIdx.x + threadIdx.y * 64; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
   __syncthreads();
 
@@ -233,20 +265,39 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
 
-  // A operands (rows = hidden units): layer 1 W1^T, layer 2 W2^T, kept in registers
-  v4i16 a1[2];
+  // A operands (rows = hidden units), kept in registers. v_mfma_f32_32x32x16_bf16:
+  // lane (hi32, col) holds A[col][8 hi32 + j] and B[8 hi32 + j][col], j = 0..7.
+  // Layer 1, tile t: K = 16 = the 8 features' hi parts (hi32 = 0) and lo parts
+  // (hi32 = 1), so both halves hold W1[j][32t + col].
+  bf16x8 a1[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 2; ++t) {
+    u32x4 v;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) a1[t][jj] = static_cast<short>(mw[(4 * hi32 + jj) * kNH + 32 * t + col]);
-  v4i16 a2[2][8];
+    for (int p = 0; p < 4; ++p)
+      v[p] = bf16_half_bits(mw[(2 * p) * kNH + 32 * t + col]) |
+             (bf16_half_bits(mw[(2 * p + 1) * kNH + 32 * t + col]) << 16);
+    a1[t] = as_bf16x8(v);
+  }
+  // Layer 2, output tile t2, K-step s (hi and lo passes share it): k = 8 hi32 + j is
+  // input hidden unit 32(s/2) + 8(2(s%2) + j/4) + 4 hi32 + j%4, which is element
+  // 8(s%2) + j of this lane's layer-1 tile s/2 (no data movement between lanes).
+  bf16x8 a2[2][4];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-    for (int s8 = 0; s8 < 8; ++s8)
+    for (int st = 0; st < 4; ++st) {
+      u32x4 v;
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj)
-        a2[t][s8][jj] = static_cast<short>(mw[kOffW2 + (8 * s8 + 4 * hi32 + jj) * kNH + 32 * t + col]);
+      for (int p = 0; p < 4; ++p) {
+        const int j0 = 2 * p, j1 = 2 * p + 1;
+        const int h0 = 32 * (st / 2) + 8 * (2 * (st % 2) + j0 / 4) + 4 * hi32 + j0 % 4;
+        const int h1 = 32 * (st / 2) + 8 * (2 * (st % 2) + j1 / 4) + 4 * hi32 + j1 % 4;
+        v[p] = bf16_half_bits(mw[kOffW2 + h0 * kNH + 32 * t2 + col]) |
+               (bf16_half_bits(mw[kOffW2 + h1 * kNH + 32 * t2 + col]) << 16);
+      }
+      a2[t2][st] = as_bf16x8(v);
+    }
 
   int64_t s = 0, e = 0;
   bool bad = false;
@@ -309,62 +360,55 @@ __global__ __launch_bounds__(256) void k_filter_learned(
         sample_features(fa, px, id, rec, feat);
       }
     }
-    SplitBf16 xb[kNF];
+    uint32_t xh[4], xl[4];
 #pragma unroll
-    for (int k = 0; k < kNF; ++k) xb[k] = split_bf16((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
-    s_x[0][wv][lane] = make_uint4(xb[0].hi | (xb[1].hi << 16), xb[2].hi | (xb[3].hi << 16),
-                                  xb[4].hi | (xb[5].hi << 16), xb[6].hi | (xb[7].hi << 16));
-    s_x[1][wv][lane] = make_uint4(xb[0].lo | (xb[1].lo << 16), xb[2].lo | (xb[3].lo << 16),
-                                  xb[4].lo | (xb[5].lo << 16), xb[6].lo | (xb[7].lo << 16));
+    for (int p = 0; p < 4; ++p)
+      split_pack((feat[2 * p] - s_b[kOffMean + 2 * p]) * s_b[kOffInvStd + 2 * p],
+                 (feat[2 * p + 1] - s_b[kOffMean + 2 * p + 1]) * s_b[kOffInvStd + 2 * p + 1], xh[p], xl[p]);
+    s_x[0][wv][lane] = make_uint4(xh[0], xh[1], xh[2], xh[3]);
+    s_x[1][wv][lane] = make_uint4(xl[0], xl[1], xl[2], xl[3]);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     float m_own = 0.0f;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      // B operands of layer 1: features 4*hi32 .. +3 of sample 32u + col, hi and lo parts
-      v4i16 bx[2];
-#pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        const uint4 xs = s_x[part][wv][32 * u + col];
-        const uint32_t w01 = hi32 ? xs.z : xs.x, w23 = hi32 ? xs.w : xs.y;
-        bx[part][0] = static_cast<short>(w01 & 0xFFFFu);
-        bx[part][1] = static_cast<short>(w01 >> 16);
-        bx[part][2] = static_cast<short>(w23 & 0xFFFFu);
-        bx[part][3] = static_cast<short>(w23 >> 16);
-      }
-      // layer 1: hidden 32t + 8(a/4) + 4 hi32 + a%4 of sample 32u + col in element a
-      v4i16 h1[2][8];  // hi / lo B operands of layer 2, K-step s8 = 4t + a/4
+      // B operand of layer 1: sample 32u + col, hi parts (hi32 = 0) or lo parts (hi32 = 1)
+      const uint4 xs = s_x[hi32][wv][32 * u + col];
+      const bf16x8 bx = as_bf16x8(u32x4{xs.x, xs.y, xs.z, xs.w});
+      // layer 1 + GELU; element a of tile t is hidden 32t + 8(a/4) + 4 hi32 + a%4
+      uint32_t ph[2][8], pl[2][8];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        v16f d = {};
-        d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx[0], d, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx[1], d, 0, 0, 0);
+        // y = z/2: the accumulator starts at b/2 (element a: hidden 32t + 8(a/4) + 4 hi32 + a%4)
+        v16f c;
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
+        for (int a = 0; a < 16; ++a) c[a] = s_bh[32 * t + 8 * (a / 4) + 4 * hi32 + a % 4];
+        const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[t], bx, c, 0, 0, 0);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int hid = 32 * t + 8 * q4 + 4 * hi32 + r;
-            const SplitBf16 hv = split_bf16(gelu(d[4 * q4 + r] + s_b[hid]));
-            h1[0][4 * t + q4][r] = static_cast<short>(hv.hi);
-            h1[1][4 * t + q4][r] = static_cast<short>(hv.lo);
-          }
+        for (int p = 0; p < 8; ++p)
+          split_pack(gelu_half(d[2 * p]), gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
       }
       // layer 2 (hi and lo passes) and the output unit on the vector units
       float mpart = 0.0f;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        v16f d = {};
+      for (int t2 = 0; t2 < 2; ++t2) {
+        v16f d;
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-          d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[t][s8], h1[0][s8], d, 0, 0, 0);
-          d = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[t][s8], h1[1][s8], d, 0, 0, 0);
+        for (int a = 0; a < 16; ++a) d[a] = s_bh[kOffB2 + 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int t = st / 2, p0 = 4 * (st % 2);
+          const u32x4 bh = {ph[t][p0], ph[t][p0 + 1], ph[t][p0 + 2], ph[t][p0 + 3]};
+          const u32x4 bl = {pl[t][p0], pl[t][p0 + 1], pl[t][p0 + 2], pl[t][p0 + 3]};
+          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bh), d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bl), d, 0, 0, 0);
         }
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int hid = 32 * t + 8 * q4 + 4 * hi32 + r;
-            mpart = fmaf(s_w3[hid], gelu(d[4 * q4 + r] + s_b[kOffB2 + hid]), mpart);
+            const int hid = 32 * t2 + 8 * q4 + 4 * hi32 + r;
+            mpart = fmaf(s_w3[hid], gelu_half(d[4 * q4 + r]), mpart);
           }
       }
       const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
