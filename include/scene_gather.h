@@ -186,8 +186,8 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
  * p, m_s = MLP(standardised features of s), MLP 8 -> 64 -> 64 -> 1 with GELU.
  * Features of a sample (source frame J, source pixel q) of output pixel p, frame f:
  *   1 rho; 2 |c - lower median of the set|_2 (per channel); 3 |J - f| / w;
- *   4 |q - (u, v)|_2 with (u, v) the unrounded projection in J; 5 cosine of the angle
- *   at the scene point between the rays from the camera centres of f and J;
+ *   4 |q - (u, v)|_2 with (u, v) the unrounded projection in J; 5 1 - cosine of the
+ *   angle at the scene point between the rays from the camera centres of f and J;
  *   6 |grad D^J|(q) / D^J(q) (central differences, one-sided where a neighbour has
  *   no valid depth); 7 log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)); 8 (J - f) / w.
  * GELU uses the tanh form 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3)))
@@ -256,6 +256,81 @@ sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
                                 const sg_gather_params* params, const sg_sample_sets* sets,
                                 const int32_t* pixel_idx, int32_t n_pix, double* moments,
                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched gather + filter (the per-clip computation of Sec. 4 and Sec. 5 Eq. 3,
+ * run for many clips of different size, length and window in one step).
+ *
+ * A batch holds n_clips clips and, per clip, n_out consecutive output frames per
+ * step; their output pixels form ONE CSR over the batch: clip c's pixels start at
+ * sg_batch_pixel_base(b, c), frame-major then row-major within the clip. A step
+ * (scene_gather_batched) runs pose prep, count, scan, scatter and filter for every
+ * clip, each pass as one persistent launch whose workgroups draw work items from
+ * an atomic queue (gather items: 64 x TH pixel tiles, clips in decreasing order of
+ * estimated work; filter items: runs of CSR pixels). Each clip's records and
+ * filtered colours are bit-identical to those of scene_gather / scene_filter on
+ * that clip alone. All clips of a batch share one radius (else SG_E_UNSUPPORTED).
+ * The batch object owns only small device buffers (plan, relative maps, scan
+ * partials, queues) and a pinned copy of the step's frames; it is not thread-safe.
+ */
+#define SG_MAX_BATCH_CLIPS 4096
+
+typedef struct sg_batch sg_batch;
+
+/* Caller-owned device buffers of a step; P = sg_batch_pixel_base(b, n_clips).
+ *   offsets : [P + 1] int64 CSR offsets (written by the step)
+ *   ids, crho, capacity : record arena as in sg_sample_sets (scatter writes at most
+ *             capacity records, else sets SG_FLAG_CAPACITY)
+ *   status  : device uint32 flags of the step (cleared by the step)
+ *   out_rgb : [P][3] float32 filtered colours, or NULL to gather only. */
+typedef struct sg_batch_io {
+  int64_t* offsets;
+  uint32_t* ids;
+  uint16_t* crho;
+  int64_t capacity;
+  uint32_t* status;
+  float* out_rgb;
+} sg_batch_io;
+
+/* Plan a batch: clips[c] (stored planes, device poses, intrinsics), params[c],
+ * fparams[c] (sigmas, as scene_filter) and n_out[c] >= 1 output frames per step.
+ * The descriptors' device pointers must stay valid for the batch's lifetime. */
+sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
+                          const sg_gather_params* params, const sg_filter_params* fparams,
+                          const int32_t* n_out);
+void sg_batch_destroy(sg_batch* b);
+
+/* CSR index of clip c's first output pixel (c = n_clips: total pixels P); -1 on a
+ * bad argument. */
+int64_t sg_batch_pixel_base(const sg_batch* b, int32_t clip);
+
+/* First output frame of every clip for the next step (host [n_clips]; f0 + n_out
+ * <= num_frames). Waits until the previous step has consumed the last frames. */
+sg_status sg_batch_set_frames(sg_batch* b, const int32_t* f0);
+
+/* Count pass only (pose prep, count, scan): offsets[P] = records of the step.
+ * For sizing the arena; the caller synchronises and reads it. */
+sg_status sg_batch_count(sg_batch* b, const sg_batch_io* io, void* stream);
+
+/* One step. Replays the captured graph when io equals the captured one. */
+sg_status scene_gather_batched(sg_batch* b, const sg_batch_io* io, void* stream);
+
+/* Capture one step for io into a HIP graph (stream: not the null stream); later
+ * scene_gather_batched calls with the same io replay it (frames still come from
+ * sg_batch_set_frames through a copy node). Any configuration change drops it. */
+sg_status sg_batch_capture(sg_batch* b, const sg_batch_io* io, void* stream);
+
+/* Autotuner: times every count configuration (tile height 1, 2, 4, 8 waves x
+ * source-frame unroll 1, 2, 4) and every scatter tile height that fits LDS on
+ * this batch and step, keeps the fastest and writes it to cfg_out[3] (may be
+ * NULL). Needs frames set and an arena that holds the step (else SG_E_CAPACITY).
+ * Synchronises the stream. */
+sg_status sg_batch_autotune(sg_batch* b, const sg_batch_io* io, void* stream, int32_t* cfg_out);
+
+/* Set / read the configuration (count tile height, count unroll, scatter tile
+ * height); results do not depend on it. */
+sg_status sg_batch_set_config(sg_batch* b, int32_t th_count, int32_t k_count, int32_t th_scatter);
+sg_status sg_batch_get_config(const sg_batch* b, int32_t* cfg);
 
 #ifdef __cplusplus
 }

@@ -411,3 +411,121 @@ def standardisation_from_moments(moments: torch.Tensor):
     std = np.sqrt(var)
     std[~(std > 1e-12 * np.maximum(np.abs(mean), 1.0))] = 1.0
     return mean, std
+
+
+# ---------------------------------------------------------------------------
+# batched persistent gather + filter over uneven clips
+
+
+@dataclass
+class BatchIO:
+    """Device buffers of one batched step (P = total output pixels of the batch)."""
+    offsets: torch.Tensor        # [P + 1] int64
+    ids: torch.Tensor            # [capacity] int32
+    crho: torch.Tensor           # [capacity, 4] float16
+    status: torch.Tensor         # [1] int32
+    out: torch.Tensor | None     # [P, 3] float32 or None (gather only)
+
+    @property
+    def capacity(self) -> int:
+        return self.ids.shape[0]
+
+    def c_struct(self) -> _native.SgBatchIo:
+        return _native.SgBatchIo(self.offsets.data_ptr(), self.ids.data_ptr() if self.capacity else None,
+                                 self.crho.data_ptr() if self.capacity else None, int(self.capacity),
+                                 self.status.data_ptr(), self.out.data_ptr() if self.out is not None else None)
+
+    def flags(self) -> int:
+        return int(self.status.item()) & 0xFFFFFFFF
+
+    def check(self) -> None:
+        fl = self.flags()
+        if fl & SG_FLAG_CAPACITY:
+            raise SceneGatherError("batch arena too small (SG_FLAG_CAPACITY)")
+        if fl & SG_FLAG_INCONSISTENT:
+            raise SceneGatherError("count and scatter passes disagree (SG_FLAG_INCONSISTENT)")
+
+
+class Batch:
+    """A planned batch of clips (sg_batch): one CSR over every clip's output pixels,
+    persistent count / scan / scatter / filter passes, graph capture, autotuner."""
+
+    def __init__(self, clips, params, fparams, n_out=1):
+        n = len(clips)
+        if not (len(params) == len(fparams) == n) or n == 0:
+            raise SceneGatherError("Batch: clips, params and fparams must have the same non-zero length")
+        n_out = [n_out] * n if isinstance(n_out, int) else list(n_out)
+        self.clips, self.params, self.fparams, self.n_out = list(clips), list(params), list(fparams), n_out
+        self._cc = (_native.SgClip * n)(*[c.c_struct() for c in clips])
+        self._pp = (_native.SgGatherParams * n)(*[p.c_struct() for p in params])
+        self._ff = (_native.SgFilterParams * n)(*[f.c_struct() for f in fparams])
+        self._no = (ctypes.c_int32 * n)(*n_out)
+        h = ctypes.c_void_p()
+        _check(_lib.sg_batch_create(ctypes.byref(h), self._cc, n, self._pp, self._ff, self._no), "sg_batch_create")
+        self._h = h
+        self.bases = [int(_lib.sg_batch_pixel_base(h, c)) for c in range(n + 1)]
+        self.f0 = None
+
+    @property
+    def total_pixels(self) -> int:
+        return self.bases[-1]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_frames(self, f0) -> None:
+        arr = (ctypes.c_int32 * len(self.clips))(*[int(v) for v in f0])
+        _check(_lib.sg_batch_set_frames(self._h, arr), "sg_batch_set_frames")
+        self.f0 = [int(v) for v in f0]
+
+    def alloc_io(self, capacity: int, with_out: bool = True, device=None) -> BatchIO:
+        dev = device or self.clips[0].rgbd.device
+        p = self.total_pixels
+        return BatchIO(torch.zeros(p + 1, dtype=torch.int64, device=dev),
+                       torch.empty(capacity, dtype=torch.int32, device=dev),
+                       torch.empty((capacity, 4), dtype=torch.float16, device=dev),
+                       torch.zeros(1, dtype=torch.int32, device=dev),
+                       torch.empty((p, 3), dtype=torch.float32, device=dev) if with_out else None)
+
+    def count(self, io: BatchIO) -> int:
+        """Count pass; returns the step's record total (synchronises)."""
+        st = io.c_struct()
+        _check(_lib.sg_batch_count(self._h, ctypes.byref(st), _stream_handle()), "sg_batch_count")
+        return int(io.offsets[-1].item())
+
+    def gather(self, io: BatchIO) -> None:
+        st = io.c_struct()
+        _check(_lib.scene_gather_batched(self._h, ctypes.byref(st), _stream_handle()), "scene_gather_batched")
+
+    def capture(self, io: BatchIO) -> None:
+        """Capture one step into a graph on torch's current stream (not the null stream)."""
+        st = io.c_struct()
+        _check(_lib.sg_batch_capture(self._h, ctypes.byref(st), _stream_handle()), "sg_batch_capture")
+
+    def autotune(self, io: BatchIO):
+        cfg = (ctypes.c_int32 * 3)()
+        st = io.c_struct()
+        _check(_lib.sg_batch_autotune(self._h, ctypes.byref(st), _stream_handle(), cfg), "sg_batch_autotune")
+        return tuple(cfg)
+
+    def set_config(self, th_count: int, k_count: int, th_scatter: int) -> None:
+        _check(_lib.sg_batch_set_config(self._h, th_count, k_count, th_scatter), "sg_batch_set_config")
+
+    def config(self):
+        cfg = (ctypes.c_int32 * 3)()
+        _check(_lib.sg_batch_get_config(self._h, cfg), "sg_batch_get_config")
+        return tuple(cfg)
+
+    def clip_sets(self, io: BatchIO, c: int) -> SampleSets:
+        """Clip c's sets inside the batch arena (offsets are batch record indices)."""
+        b0, b1 = self.bases[c], self.bases[c + 1]
+        return SampleSets(self.f0[c], self.f0[c] + self.n_out[c], self.params[c].window, io.offsets[b0:b1 + 1],
+                          io.ids, io.crho, io.status)

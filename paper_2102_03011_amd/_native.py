@@ -59,6 +59,13 @@ class SgMlpTrain(ctypes.Structure):
                 ("w_bf16", c_void_p), ("b_f32", c_void_p), ("loss", c_void_p)]
 
 
+class SgBatchIo(ctypes.Structure):
+    _fields_ = [("offsets", c_void_p), ("ids", c_void_p), ("crho", c_void_p), ("capacity", ctypes.c_int64),
+                ("status", c_void_p), ("out_rgb", c_void_p)]
+
+
+SG_MAX_BATCH_CLIPS = 4096
+
 # name -> (restype, argtypes); every function declared in include/scene_gather.h
 SIGNATURES = {
     "sg_version": (ctypes.c_int32, []),
@@ -86,6 +93,19 @@ SIGNATURES = {
                                               ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                               c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_size_t,
                                               c_void_p]),
+    "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.POINTER(SgClip), ctypes.c_int32,
+                                        ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgFilterParams),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "sg_batch_destroy": (None, [c_void_p]),
+    "sg_batch_pixel_base": (ctypes.c_int64, [c_void_p, ctypes.c_int32]),
+    "sg_batch_set_frames": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "sg_batch_count": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p]),
+    "scene_gather_batched": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p]),
+    "sg_batch_capture": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p]),
+    "sg_batch_autotune": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p,
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "sg_batch_set_config": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "sg_batch_get_config": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "scene_mlp_train_step": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              c_void_p, ctypes.c_int32, c_void_p, ctypes.POINTER(SgMlpTrain),

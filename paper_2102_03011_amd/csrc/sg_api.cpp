@@ -6,39 +6,18 @@
 
 #include "scene_gather.h"
 #include "sg_internal.h"
+#include "sg_validate.h"
 
 namespace {
+
+using sg::check_clip;
+using sg::check_params;
+using sg::check_range;
+using sg::hip_status;
 
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
-
-sg_status check_clip(const sg_clip* c, bool need_depth) {
-  if (c == nullptr) return SG_E_INVALID;
-  if (c->width <= 0 || c->height <= 0 || c->num_frames <= 0) return SG_E_INVALID;
-  if (c->rgbd == nullptr || c->cam_to_world == nullptr) return SG_E_INVALID;
-  if (need_depth && c->depth == nullptr) return SG_E_INVALID;
-  if (!isfinite(c->fx) || !isfinite(c->fy) || c->fx == 0.0 || c->fy == 0.0) return SG_E_INVALID;
-  if (!isfinite(c->cx) || !isfinite(c->cy)) return SG_E_INVALID;
-  if (static_cast<int64_t>(c->width) * c->height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;
-  if (c->num_frames > 65535) return SG_E_UNSUPPORTED;
-  return SG_OK;
-}
-
-sg_status check_range(const sg_clip* c, int32_t f0, int32_t f1) {
-  if (f0 < 0 || f1 <= f0 || f1 > c->num_frames) return SG_E_INVALID;
-  return SG_OK;
-}
-
-sg_status check_params(const sg_gather_params* p) {
-  if (p == nullptr) return SG_E_INVALID;
-  if (p->window < 0 || p->radius < 0) return SG_E_INVALID;
-  if (!finite_pos(p->tol) || !finite_pos(p->z_near)) return SG_E_INVALID;
-  if (p->window > SG_MAX_WINDOW || p->radius > SG_MAX_RADIUS) return SG_E_UNSUPPORTED;
-  return SG_OK;
-}
 
 struct Layout {
   size_t rel_off, rel_bytes, part_off, part_bytes, total;
@@ -56,8 +35,6 @@ Layout layout(const sg_clip* c, int32_t f0, int32_t f1, const sg_gather_params* 
   l.total = l.part_off + l.part_bytes;
   return l;
 }
-
-sg_status hip_status(hipError_t e) { return e == hipSuccess ? SG_OK : SG_E_HIP; }
 
 sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
                   sg_sample_sets* sets, void* ws, size_t ws_bytes, bool need_arena,

@@ -77,6 +77,61 @@ struct TrainJob {
   int t;
 };
 
+// ---------------------------------------------------------------------------
+// batched persistent gather + filter over uneven clips
+
+// One clip of a batch as the batched kernels read it (device memory).
+struct BatchClip {
+  const uint16_t* rgbd;
+  const uint16_t* depth;
+  const double* c2w;
+  float* rel;            // n_out x (2w+1) x kRelStride floats, owned by the batch
+  int width, height, n_frames, n_out, w, pad0;
+  float tol, z_near;
+  double fx, fy, cx, cy;
+  int64_t pix_base;      // CSR index of the clip's first output pixel
+  float a_d, a_c, a_t, pad1;
+};
+
+// Device-side plan of a batch: clips, per-step first output frames, and the work
+// order of the gather passes (clip slots sorted by estimated cost).
+struct BatchDev {
+  const BatchClip* clips;
+  const int* f0;             // [n_clips], updated per step
+  const int* order;          // [n_clips]: clip of each slot
+  const int64_t* prefix;     // [n_clips + 1] first work item of each slot (tile height th)
+  const int64_t* pix_prefix; // [n_clips + 1] CSR base of each clip (clip order)
+  int n_clips;
+  int radius;
+};
+
+struct BatchIo {
+  int64_t* offsets;
+  uint32_t* ids;
+  uint16_t* crho;
+  int64_t capacity;
+  uint32_t* status;
+  float* out;
+};
+
+struct BatchLaunch {
+  int th_count, k_count, th_scatter;  // tile heights (waves per workgroup), source-frame unroll
+  int blocks_count, blocks_scatter, blocks_filter;
+  bool colour, time;
+  int max_slots;                     // max over clips of n_out (2w + 1)
+};
+
+int batch_scatter_max_th(int radius);         // largest scatter tile height that fits LDS
+size_t batch_scatter_lds_bytes(int radius);   // LDS of one scatter wave
+hipError_t launch_batch_prep(const BatchDev& bd, unsigned int* queues, uint32_t* status, int max_slots,
+                             hipStream_t st);
+hipError_t launch_batch_count(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl,
+                              unsigned int* queue, hipStream_t st);
+hipError_t launch_batch_scatter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl,
+                                unsigned int* queue, hipStream_t st);
+hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, int64_t n_pix,
+                               unsigned int* queue, hipStream_t st);
+
 hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st);
 hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st);
 hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,

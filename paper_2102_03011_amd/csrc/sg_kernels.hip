@@ -89,14 +89,10 @@ __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
 // One thread per (output frame fo, window slot s): J = f - w + s.
 // Record layout (kRelStride floats): M row-major (9), k (3), unused (4).
 
-__global__ __launch_bounds__(64) void k_pose_prep(const double* __restrict__ c2w, int n_frames,
-                                                  int f0, int n_out, int w, double fx, double fy,
-                                                  double cx, double cy, float* __restrict__ rel,
-                                                  uint32_t* __restrict__ status) {
+__device__ __forceinline__ void pose_prep_one(const double* __restrict__ c2w, int n_frames, int f0, int w,
+                                              double fx, double fy, double cx, double cy,
+                                              float* __restrict__ rel, int i) {
   const int slots = 2 * w + 1;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && status != nullptr) *status = 0u;
-  if (i >= n_out * slots) return;
   const int fo = i / slots, s = i - fo * slots;
   const int f = f0 + fo, j = f - w + s;
   float* out = rel + static_cast<size_t>(i) * kRelStride;
@@ -142,6 +138,16 @@ __global__ __launch_bounds__(64) void k_pose_prep(const double* __restrict__ c2w
   for (int e = 0; e < 3; ++e) out[9 + e] = static_cast<float>(kt[e]);
   out[12] = 1.0f;  // slot valid
   out[13] = out[14] = out[15] = 0.0f;
+}
+
+__global__ __launch_bounds__(64) void k_pose_prep(const double* __restrict__ c2w, int n_frames,
+                                                  int f0, int n_out, int w, double fx, double fy,
+                                                  double cx, double cy, float* __restrict__ rel,
+                                                  uint32_t* __restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && status != nullptr) *status = 0u;
+  if (i >= n_out * (2 * w + 1)) return;
+  pose_prep_one(c2w, n_frames, f0, w, fx, fy, cx, cy, rel, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,17 +236,11 @@ __device__ __forceinline__ Tile tile_of_block(int tiles_x, int tiles_y) {
 // Per source frame the (2r+1)^2 depths are loaded unconditionally (apron makes
 // every address valid), so all loads of a block are in flight together.
 
+// Members of output pixel (x, y) of output frame f; relf = the relative maps of f.
 template <int R>
-__global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ depth,
-                                               const float* __restrict__ rel, int width, int height,
-                                               int n_frames, int f0, int w, float tol, float z_near,
-                                               int64_t* __restrict__ counts) {
-  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
-  const int x = tile.tx * kTileW + threadIdx.x;
-  const int y = tile.ty * kTileH + threadIdx.y;
-  const int fo = tile.fo;
-  if (x >= width || y >= height) return;
-  const int f = f0 + fo;
+__device__ __forceinline__ int count_pixel(const uint16_t* __restrict__ depth, const float* __restrict__ relf,
+                                           int width, int height, int n_frames, int f, int w, float tol,
+                                           float z_near, int x, int y) {
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
   const float dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
@@ -248,7 +248,6 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
   if (dp > z_near && dp < INFINITY) {
     const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
     const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
-    const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
     for (int j = jlo; j <= jhi; ++j) {
       Projected p;
       if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p))
@@ -261,7 +260,64 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
         for (int dx = 0; dx <= 2 * R; ++dx) count += accept16(d[dy][dx], p) ? 1 : 0;
     }
   }
-  counts[static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x] = count;
+  return count;
+}
+
+// The same count with K source frames per step: the K projections are made and all
+// K blocks' loads issued before any test, for more loads in flight per lane. A
+// source frame past the window or whose projection fails loads a valid apron block
+// of frame jlo and contributes nothing, so the count equals count_pixel's.
+template <int R, int K>
+__device__ __forceinline__ int count_pixel_k(const uint16_t* __restrict__ depth, const float* __restrict__ relf,
+                                             int width, int height, int n_frames, int f, int w, float tol,
+                                             float z_near, int x, int y) {
+  if (K == 1) return count_pixel<R>(depth, relf, width, height, n_frames, f, w, tol, z_near, x, y);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const float dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+  int count = 0;
+  if (dp > z_near && dp < INFINITY) {
+    const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
+    const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
+    for (int j0 = jlo; j0 <= jhi; j0 += K) {
+      Projected p[K];
+      bool ok[K];
+      uint32_t d[K][2 * R + 1][2 * R + 1];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = j0 + k;
+        ok[k] = j <= jhi &&
+                project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p[k]);
+        const size_t at = ok[k] ? static_cast<size_t>(j) * pplane + padded_index(p[k].iu, p[k].iv, pw)
+                                : static_cast<size_t>(jlo) * pplane + padded_index(0, 0, pw);
+        load_block_depths<R>(depth + at, pw, d[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (!ok[k]) continue;
+#pragma unroll
+        for (int dy = 0; dy <= 2 * R; ++dy)
+#pragma unroll
+          for (int dx = 0; dx <= 2 * R; ++dx) count += accept16(d[k][dy][dx], p[k]) ? 1 : 0;
+      }
+    }
+  }
+  return count;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ depth,
+                                               const float* __restrict__ rel, int width, int height,
+                                               int n_frames, int f0, int w, float tol, float z_near,
+                                               int64_t* __restrict__ counts) {
+  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
+  const int x = tile.tx * kTileW + threadIdx.x;
+  const int y = tile.ty * kTileH + threadIdx.y;
+  const int fo = tile.fo;
+  if (x >= width || y >= height) return;
+  const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
+  counts[static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x] =
+      count_pixel<R>(depth, relf, width, height, n_frames, f0 + fo, w, tol, z_near, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,34 +395,35 @@ __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const
   fill -= n;
 }
 
+// LDS of one scatter wave
 template <int R>
-__global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
-                                                 const uint16_t* __restrict__ depth,
-                                                 const float* __restrict__ rel, int width,
-                                                 int height, int n_frames, int f0, int w, float tol,
-                                                 float z_near, const int64_t* __restrict__ offsets,
-                                                 uint32_t* __restrict__ ids,
-                                                 uint2* __restrict__ crho, int64_t capacity,
-                                                 uint32_t* __restrict__ status) {
+struct ScatterLds {
+  uint2 rec[kTileW * ScatterShape<R>::kSlots];
+  uint32_t id[kTileW * ScatterShape<R>::kSlots];
+  int n[kTileW];
+  int64_t dst[kTileW];
+};
+
+// One wave writes the records of the 64 output pixels (x0 + lane, y) of output
+// frame f; pix0 = CSR index of pixel (x0, y). Every lane of the wave calls it.
+template <int R>
+__device__ __forceinline__ void scatter_wave(const uint2* __restrict__ rgbd, const uint16_t* __restrict__ depth,
+                                             const float* __restrict__ relf, int width, int height,
+                                             int n_frames, int f, int w, float tol, float z_near, int x0, int y,
+                                             int64_t pix0, const int64_t* __restrict__ offsets,
+                                             uint32_t* __restrict__ ids, uint2* __restrict__ crho,
+                                             int64_t capacity, uint32_t* __restrict__ status,
+                                             ScatterLds<R>& lds) {
   using Shape = ScatterShape<R>;
   using Mask = typename Shape::Mask;
   constexpr int kSlots = Shape::kSlots;
   constexpr int kSide = 2 * R + 1;
-  __shared__ uint2 s_rec_all[kTileH][kTileW * kSlots];
-  __shared__ uint32_t s_id_all[kTileH][kTileW * kSlots];
-  __shared__ int s_n_all[kTileH][kTileW];
-  __shared__ int64_t s_dst_all[kTileH][kTileW];
-  const int lane = threadIdx.x, wv = threadIdx.y;
-  uint2* s_rec = s_rec_all[wv];
-  uint32_t* s_id = s_id_all[wv];
-  int* s_n = s_n_all[wv];
-  int64_t* s_dst = s_dst_all[wv];
-
-  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
-  const int x = tile.tx * kTileW + lane;
-  const int y = tile.ty * kTileH + wv;
-  const int fo = tile.fo;
-  const int f = f0 + fo;
+  const int lane = threadIdx.x;
+  uint2* s_rec = lds.rec;
+  uint32_t* s_id = lds.id;
+  int* s_n = lds.n;
+  int64_t* s_dst = lds.dst;
+  const int x = x0 + lane;
   const bool in = x < width && y < height;
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
@@ -374,7 +431,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
   bool active = false;
   float dp = 0.0f;
   if (in) {
-    const size_t pix = static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x;
+    const int64_t pix = pix0 + lane;
     start = cur = offsets[pix];
     end = offsets[pix + 1];
     if (cur < 0 || end < cur) {  // offsets not produced by the count pass
@@ -390,7 +447,6 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
   int found = 0;
   const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
   const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
-  const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
   uint2* my_rec = s_rec + lane * kSlots;
   uint32_t* my_id = s_id + lane * kSlots;
   for (int j = jlo; j <= jhi; ++j) {
@@ -448,6 +504,26 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
   }
   if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
   if (active && found != end - start) atomicOr(status, SG_FLAG_INCONSISTENT);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
+                                                 const uint16_t* __restrict__ depth,
+                                                 const float* __restrict__ rel, int width,
+                                                 int height, int n_frames, int f0, int w, float tol,
+                                                 float z_near, const int64_t* __restrict__ offsets,
+                                                 uint32_t* __restrict__ ids,
+                                                 uint2* __restrict__ crho, int64_t capacity,
+                                                 uint32_t* __restrict__ status) {
+  __shared__ ScatterLds<R> lds[kTileH];
+  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
+  const int x0 = tile.tx * kTileW;
+  const int y = tile.ty * kTileH + threadIdx.y;
+  const int fo = tile.fo;
+  const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
+  const int64_t pix0 = static_cast<int64_t>(fo) * width * height + static_cast<int64_t>(y) * width + x0;
+  scatter_wave<R>(rgbd, depth, relf, width, height, n_frames, f0 + fo, w, tol, z_near, x0, y, pix0, offsets,
+                  ids, crho, capacity, status, lds[threadIdx.y]);
 }
 
 // ---------------------------------------------------------------------------
@@ -531,29 +607,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* __restrict
 // a6: filter. kGroup lanes per output pixel stride through its CSR segment;
 // each lane accumulates in a fixed order, then a fixed butterfly reduces.
 
+// kGroup lanes filter one pixel: pixel `self` (y * W + x) of frame f, whose set is
+// CSR entry `pix` of offsets / out. Every lane of the group calls it (live or not).
 template <bool kColour, bool kTime>
-__global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, int width,
-                                                int height, int f0, int w, int64_t n_pix,
-                                                const int64_t* __restrict__ offsets,
-                                                const uint32_t* __restrict__ ids,
-                                                const uint2* __restrict__ crho, int64_t capacity,
-                                                float a_d, float a_c, float a_t,
-                                                float* __restrict__ out) {
-  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t pix = gid / kGroup;
-  const int lane = static_cast<int>(gid % kGroup);
-  const bool live = pix < n_pix;
-  const size_t plane = static_cast<size_t>(width) * height;
+__device__ __forceinline__ void filter_group(const uint2* __restrict__ rgbd, int width, int height, int f,
+                                             int w, bool live, int64_t self, int64_t pix, int lane,
+                                             const int64_t* __restrict__ offsets,
+                                             const uint32_t* __restrict__ ids,
+                                             const uint2* __restrict__ crho, int64_t capacity, float a_d,
+                                             float a_c, float a_t, float* __restrict__ out) {
   float cr = 0.f, cg = 0.f, cb = 0.f;
   int64_t s = 0, e = 0;
-  int fo = 0;
   if (live) {
-    fo = static_cast<int>(pix / static_cast<int64_t>(plane));
-    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
     const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
     const int pw = stored_pitch(width);
     const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-    const uint2 ref = rgbd[static_cast<size_t>(f0 + fo) * pplane + padded_index(x, y, pw)];
+    const uint2 ref = rgbd[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)];
     cr = h2f(ref.x);
     cg = h2f(ref.x >> 16);
     cb = h2f(ref.y);
@@ -602,6 +671,152 @@ __global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, 
       o[0] = cr;
       o[1] = cg;
       o[2] = cb;
+    }
+  }
+}
+
+template <bool kColour, bool kTime>
+__global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, int width,
+                                                int height, int f0, int w, int64_t n_pix,
+                                                const int64_t* __restrict__ offsets,
+                                                const uint32_t* __restrict__ ids,
+                                                const uint2* __restrict__ crho, int64_t capacity,
+                                                float a_d, float a_c, float a_t,
+                                                float* __restrict__ out) {
+  const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t pix = gid / kGroup;
+  const int lane = static_cast<int>(gid % kGroup);
+  const bool live = pix < n_pix;
+  const int64_t plane = static_cast<int64_t>(width) * height;
+  const int fo = live ? static_cast<int>(pix / plane) : 0;
+  filter_group<kColour, kTime>(rgbd, width, height, f0 + fo, w, live, pix - fo * plane, pix, lane, offsets,
+                               ids, crho, capacity, a_d, a_c, a_t, out);
+}
+
+// ---------------------------------------------------------------------------
+// a9: batched persistent passes over uneven clips. Each pass is one launch of a
+// grid sized to the machine; a workgroup takes the next work item from an atomic
+// queue until the queue is exhausted (every workgroup reaches the exit). Gather
+// items are tiles (64 x TH pixels of one output frame of one clip) in cost order
+// (clip slots sorted by estimated work, largest first); filter items are runs of
+// consecutive CSR pixels. The per-pixel work is the single-clip kernels' code, so
+// each clip's records and colours equal those of its own calls.
+
+__global__ __launch_bounds__(64) void k_batch_prep(BatchDev bd, unsigned int* __restrict__ queues,
+                                                   uint32_t* __restrict__ status) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (c == 0 && i < 4) queues[i] = 0u;
+  if (c == 0 && i == 0) *status = 0u;
+  const BatchClip& cl = bd.clips[c];
+  if (i < cl.n_out * (2 * cl.w + 1))
+    pose_prep_one(cl.c2w, cl.n_frames, bd.f0[c], cl.w, cl.fx, cl.fy, cl.cx, cl.cy, cl.rel, i);
+}
+
+// Next work item of the workgroup (the whole workgroup calls it).
+__device__ __forceinline__ int64_t next_item(unsigned int* queue, unsigned int* s_item) {
+  if (threadIdx.x == 0 && threadIdx.y == 0) *s_item = atomicAdd(queue, 1u);
+  __syncthreads();
+  const int64_t item = *s_item;
+  __syncthreads();
+  return item;
+}
+
+// slot of work item `item`: the largest k with prefix[k] <= item
+__device__ __forceinline__ int item_slot(const int64_t* __restrict__ prefix, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct TileOf {
+  int clip, fo, x0, y0;
+};
+
+template <int TH>
+__device__ __forceinline__ TileOf batch_tile(const BatchDev& bd, int64_t item) {
+  const int k = item_slot(bd.prefix, bd.n_clips, item);
+  TileOf t;
+  t.clip = bd.order[k];
+  const BatchClip& c = bd.clips[t.clip];
+  const int64_t local = item - bd.prefix[k];
+  const int tiles_x = (c.width + kTileW - 1) / kTileW, tiles_y = (c.height + TH - 1) / TH;
+  t.x0 = static_cast<int>(local % tiles_x) * kTileW;
+  const int64_t rest = local / tiles_x;
+  t.y0 = static_cast<int>(rest % tiles_y) * TH;
+  t.fo = static_cast<int>(rest / tiles_y);
+  return t;
+}
+
+template <int R, int TH, int K>
+__global__ __launch_bounds__(64 * TH) void k_count_batched(BatchDev bd, int64_t* __restrict__ counts,
+                                                           unsigned int* __restrict__ queue) {
+  __shared__ unsigned int s_item;
+  const int64_t n_items = bd.prefix[bd.n_clips];
+  for (;;) {
+    const int64_t item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const TileOf t = batch_tile<TH>(bd, item);
+    const BatchClip& c = bd.clips[t.clip];
+    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
+    if (x < c.width && y < c.height) {
+      const float* relf = c.rel + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+      const int64_t pix = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
+                          static_cast<int64_t>(y) * c.width + x;
+      counts[pix] = count_pixel_k<R, K>(c.depth, relf, c.width, c.height, c.n_frames, bd.f0[t.clip] + t.fo, c.w,
+                                        c.tol, c.z_near, x, y);
+    }
+  }
+}
+
+template <int R, int TH>
+__global__ __launch_bounds__(64 * TH) void k_scatter_batched(BatchDev bd, BatchIo io,
+                                                             unsigned int* __restrict__ queue) {
+  __shared__ ScatterLds<R> lds[TH];
+  __shared__ unsigned int s_item;
+  const int64_t n_items = bd.prefix[bd.n_clips];
+  for (;;) {
+    const int64_t item = next_item(queue, &s_item);
+    if (item >= n_items) break;
+    const TileOf t = batch_tile<TH>(bd, item);
+    const BatchClip& c = bd.clips[t.clip];
+    const int y = t.y0 + threadIdx.y;
+    const float* relf = c.rel + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+    const int64_t pix0 = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
+                         static_cast<int64_t>(y) * c.width + t.x0;
+    scatter_wave<R>(reinterpret_cast<const uint2*>(c.rgbd), c.depth, relf, c.width, c.height, c.n_frames,
+                    bd.f0[t.clip] + t.fo, c.w, c.tol, c.z_near, t.x0, y, pix0, io.offsets, io.ids,
+                    reinterpret_cast<uint2*>(io.crho), io.capacity, io.status, lds[threadIdx.y]);
+  }
+}
+
+constexpr int kBatchFilterPix = 256;  // CSR pixels per filter work item (16 per pass of a workgroup)
+
+template <bool kColour, bool kTime>
+__global__ __launch_bounds__(256) void k_filter_batched(BatchDev bd, BatchIo io, int64_t n_pix,
+                                                        unsigned int* __restrict__ queue) {
+  __shared__ unsigned int s_item;
+  const int g = threadIdx.x / kGroup, lane = threadIdx.x % kGroup;
+  for (;;) {
+    const int64_t item = next_item(queue, &s_item);
+    const int64_t first = item * kBatchFilterPix;
+    if (first >= n_pix) break;
+    for (int r = 0; r < kBatchFilterPix; r += 256 / kGroup) {
+      const int64_t pix = first + r + g;
+      const bool live = pix < n_pix;
+      int c = 0;
+      if (live) c = item_slot(bd.pix_prefix, bd.n_clips, pix);
+      const BatchClip& cl = bd.clips[c];
+      const int64_t plane = static_cast<int64_t>(cl.width) * cl.height;
+      const int64_t local = live ? pix - cl.pix_base : 0;
+      const int fo = static_cast<int>(local / plane);
+      filter_group<kColour, kTime>(reinterpret_cast<const uint2*>(cl.rgbd), cl.width, cl.height,
+                                   bd.f0[c] + fo, cl.w, live, local - fo * plane, pix, lane, io.offsets, io.ids,
+                                   reinterpret_cast<const uint2*>(io.crho), io.capacity, cl.a_d,
+                                   kColour ? cl.a_c : 0.0f, kTime ? cl.a_t : 0.0f, io.out);
     }
   }
 }
@@ -702,6 +917,115 @@ hipError_t launch_filter(const FilterJob& fj, hipStream_t st) {
   else
     SG_FILTER_LAUNCH(false, false);
 #undef SG_FILTER_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_prep(const BatchDev& bd, unsigned int* queues, uint32_t* status, int max_slots,
+                             hipStream_t st) {
+  const dim3 g(static_cast<unsigned>((max_slots + 63) / 64), static_cast<unsigned>(bd.n_clips));
+  hipLaunchKernelGGL(k_batch_prep, g, dim3(64), 0, st, bd, queues, status);
+  return hipGetLastError();
+}
+
+template <int R, int TH>
+static void count_batched_k(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* q,
+                            hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(bl.blocks_count)), b(kTileW, TH);
+  switch (bl.k_count) {
+    case 1: hipLaunchKernelGGL((k_count_batched<R, TH, 1>), g, b, 0, st, bd, io.offsets + 1, q); break;
+    case 2: hipLaunchKernelGGL((k_count_batched<R, TH, 2>), g, b, 0, st, bd, io.offsets + 1, q); break;
+    default: hipLaunchKernelGGL((k_count_batched<R, TH, 4>), g, b, 0, st, bd, io.offsets + 1, q); break;
+  }
+}
+
+template <int R>
+static void count_batched_r(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* q,
+                            hipStream_t st) {
+  switch (bl.th_count) {
+    case 1: count_batched_k<R, 1>(bd, io, bl, q, st); break;
+    case 2: count_batched_k<R, 2>(bd, io, bl, q, st); break;
+    case 4: count_batched_k<R, 4>(bd, io, bl, q, st); break;
+    default: count_batched_k<R, 8>(bd, io, bl, q, st); break;
+  }
+}
+
+hipError_t launch_batch_count(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* queue,
+                              hipStream_t st) {
+  switch (bd.radius) {
+    case 0: count_batched_r<0>(bd, io, bl, queue, st); break;
+    case 1: count_batched_r<1>(bd, io, bl, queue, st); break;
+    case 2: count_batched_r<2>(bd, io, bl, queue, st); break;
+    default: count_batched_r<3>(bd, io, bl, queue, st); break;
+  }
+  return hipGetLastError();
+}
+
+// largest scatter tile height (waves per workgroup) whose LDS fits 160 KB
+template <int R>
+constexpr int scatter_max_th() {
+  constexpr size_t b = sizeof(ScatterLds<R>) + 16;
+  return b * 8 <= 163840 ? 8 : (b * 4 <= 163840 ? 4 : (b * 2 <= 163840 ? 2 : 1));
+}
+
+size_t batch_scatter_lds_bytes(int radius) {
+  switch (radius) {
+    case 0: return sizeof(ScatterLds<0>);
+    case 1: return sizeof(ScatterLds<1>);
+    case 2: return sizeof(ScatterLds<2>);
+    default: return sizeof(ScatterLds<3>);
+  }
+}
+
+int batch_scatter_max_th(int radius) {
+  switch (radius) {
+    case 0: return scatter_max_th<0>();
+    case 1: return scatter_max_th<1>();
+    case 2: return scatter_max_th<2>();
+    default: return scatter_max_th<3>();
+  }
+}
+
+template <int R, int TH>
+static void scatter_batched_th(const BatchDev& bd, const BatchIo& io, dim3 g, unsigned int* q, hipStream_t st) {
+  if constexpr (TH <= scatter_max_th<R>())
+    hipLaunchKernelGGL((k_scatter_batched<R, TH>), g, dim3(kTileW, TH), 0, st, bd, io, q);
+}
+
+template <int R>
+static void scatter_batched_r(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* q,
+                              hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(bl.blocks_scatter));
+  const int th = bl.th_scatter < scatter_max_th<R>() ? bl.th_scatter : scatter_max_th<R>();
+  switch (th) {
+    case 1: scatter_batched_th<R, 1>(bd, io, g, q, st); break;
+    case 2: scatter_batched_th<R, 2>(bd, io, g, q, st); break;
+    case 4: scatter_batched_th<R, 4>(bd, io, g, q, st); break;
+    default: scatter_batched_th<R, 8>(bd, io, g, q, st); break;
+  }
+}
+
+hipError_t launch_batch_scatter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* queue,
+                                hipStream_t st) {
+  switch (bd.radius) {
+    case 0: scatter_batched_r<0>(bd, io, bl, queue, st); break;
+    case 1: scatter_batched_r<1>(bd, io, bl, queue, st); break;
+    case 2: scatter_batched_r<2>(bd, io, bl, queue, st); break;
+    default: scatter_batched_r<3>(bd, io, bl, queue, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, int64_t n_pix,
+                               unsigned int* queue, hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(bl.blocks_filter));
+  if (bl.colour && bl.time)
+    hipLaunchKernelGGL((k_filter_batched<true, true>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+  else if (bl.colour)
+    hipLaunchKernelGGL((k_filter_batched<true, false>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+  else if (bl.time)
+    hipLaunchKernelGGL((k_filter_batched<false, true>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+  else
+    hipLaunchKernelGGL((k_filter_batched<false, false>), g, dim3(256), 0, st, bd, io, n_pix, queue);
   return hipGetLastError();
 }
 

@@ -1,0 +1,44 @@
+// Host-side argument checks shared by the C entry points (no GPU work).
+#ifndef SG_VALIDATE_H
+#define SG_VALIDATE_H
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "scene_gather.h"
+
+namespace sg {
+
+inline bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+inline sg_status check_clip(const sg_clip* c, bool need_depth) {
+  if (c == nullptr) return SG_E_INVALID;
+  if (c->width <= 0 || c->height <= 0 || c->num_frames <= 0) return SG_E_INVALID;
+  if (c->rgbd == nullptr || c->cam_to_world == nullptr) return SG_E_INVALID;
+  if (need_depth && c->depth == nullptr) return SG_E_INVALID;
+  if (!isfinite(c->fx) || !isfinite(c->fy) || c->fx == 0.0 || c->fy == 0.0) return SG_E_INVALID;
+  if (!isfinite(c->cx) || !isfinite(c->cy)) return SG_E_INVALID;
+  if (static_cast<int64_t>(c->width) * c->height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;
+  if (c->num_frames > 65535) return SG_E_UNSUPPORTED;
+  return SG_OK;
+}
+
+inline sg_status check_range(const sg_clip* c, int32_t f0, int32_t f1) {
+  if (f0 < 0 || f1 <= f0 || f1 > c->num_frames) return SG_E_INVALID;
+  return SG_OK;
+}
+
+inline sg_status check_params(const sg_gather_params* p) {
+  if (p == nullptr) return SG_E_INVALID;
+  if (p->window < 0 || p->radius < 0) return SG_E_INVALID;
+  if (!finite_pos(p->tol) || !finite_pos(p->z_near)) return SG_E_INVALID;
+  if (p->window > SG_MAX_WINDOW || p->radius > SG_MAX_RADIUS) return SG_E_UNSUPPORTED;
+  return SG_OK;
+}
+
+inline sg_status hip_status(hipError_t e) { return e == hipSuccess ? SG_OK : SG_E_HIP; }
+
+}  // namespace sg
+
+#endif  // SG_VALIDATE_H

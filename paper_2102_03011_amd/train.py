@@ -16,6 +16,7 @@ clean radiance.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -70,9 +71,10 @@ def init_params(mean, std, seed: int, device="cuda") -> sg.MLPParams:
 class FrameSets:
     """One clip staged on the device and the gathered sets of one output frame."""
 
-    def __init__(self, clip, staged, wl, f):
+    def __init__(self, clip, staged, wl, f, window=None):
         self.clip, self.staged, self.f = clip, staged, f
-        self.params = sg.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
+        w = wl.window if window is None else window
+        self.params = sg.GatherParams(window=w, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
         self.ws = sg.alloc_workspace(staged, f, f + 1, self.params)
         self.sets = sg.scene_gather(staged, f, f + 1, self.params, ws=self.ws)
         self.sets.check()
@@ -80,6 +82,18 @@ class FrameSets:
         self.clean = clip.clean[f].reshape(-1, 3).to(staged.rgbd.device, torch.float32)
         counts = self.sets.offsets[1:] - self.sets.offsets[:-1]
         self.nonempty = torch.nonzero(counts > 0).flatten().to(torch.int32)
+
+
+def training_workload(i: int, noise_mix: bool):
+    """Training clip i; with noise_mix its noise levels and moving objects are drawn
+    per clip (colour sigma 4-12/255, depth noise 1-4 %, outliers 0.5-2 %, 0-3 movers)."""
+    wl = configs.learned_train(i)
+    if noise_mix:
+        g = np.random.default_rng(50_000 + i)
+        wl.spec = dataclasses.replace(wl.spec, colour_sigma=g.uniform(4, 12) / 255.0,
+                                      depth_noise=g.uniform(0.01, 0.04), outlier_frac=g.uniform(0.005, 0.02),
+                                      n_moving=int(g.integers(0, 4)))
+    return wl
 
 
 def make_clip(wl, device="cuda"):
@@ -101,42 +115,47 @@ def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
     return 10.0 * math.log10(1.0 / mse) if mse > 0 else math.inf
 
 
-def evaluate(params: sg.MLPParams, n_clips: int = 20, frames_per_clip: int = 3, seed: int = 7, log=print):
-    """PSNR (input, plain filter, learned filter) on held-out clips."""
+def evaluate(params: sg.MLPParams, n_clips: int = 20, frames_per_clip: int = 3, seed: int = 7, log=print,
+             windows=(30,)):
+    """PSNR (input, plain filter, learned filter) on held-out clips, per window."""
     rng = np.random.default_rng(seed)
-    rows = []
+    rows = {w: [] for w in windows}
     for i in range(n_clips):
         wl = configs.learned_train(i, held_out=True)
         clip, staged = make_clip(wl)
         for f in sorted(rng.choice(clip.n_frames, size=frames_per_clip, replace=False).tolist()):
-            fs = FrameSets(clip, staged, wl, f)
-            plain = sg.scene_filter(staged, fs.sets, sg.FilterParams(sigma_d=wl.sigma_d))[0]
-            learned = sg.scene_filter_learned(staged, fs.sets, fs.params, params, ws=fs.ws)[0]
-            clean = clip.clean[f].to(plain.device)
-            noisy = clip.rgb_u8[f].to(plain.device).double() / 255.0
-            rows.append((psnr(noisy, clean), psnr(plain, clean), psnr(learned, clean)))
+            clean = clip.clean[f].to(staged.rgbd.device)
+            noisy = clip.rgb_u8[f].to(staged.rgbd.device).double() / 255.0
+            for w in windows:
+                fs = FrameSets(clip, staged, wl, f, window=w)
+                plain = sg.scene_filter(staged, fs.sets, sg.FilterParams(sigma_d=wl.sigma_d))[0]
+                learned = sg.scene_filter_learned(staged, fs.sets, fs.params, params, ws=fs.ws)[0]
+                rows[w].append((psnr(noisy, clean), psnr(plain, clean), psnr(learned, clean)))
         del clip, staged
-    r = np.array(rows)
-    out = {"clips": n_clips, "frames": len(rows), "psnr_input": float(r[:, 0].mean()),
-           "psnr_plain": float(r[:, 1].mean()), "psnr_learned": float(r[:, 2].mean()),
-           "learned_minus_plain_min": float((r[:, 2] - r[:, 1]).min()),
-           "learned_beats_plain_frames": int((r[:, 2] > r[:, 1]).sum())}
+    out = {"clips": n_clips, "frames": n_clips * frames_per_clip}
+    for w in windows:
+        r = np.array(rows[w])
+        out[f"w{w}"] = {"psnr_input": float(r[:, 0].mean()), "psnr_plain": float(r[:, 1].mean()),
+                        "psnr_learned": float(r[:, 2].mean()),
+                        "learned_minus_plain_min": float((r[:, 2] - r[:, 1]).min()),
+                        "learned_beats_plain_frames": int((r[:, 2] > r[:, 1]).sum())}
     log(f"eval: {json.dumps(out)}")
     return out
 
 
 def train(n_clips: int = 200, frames_per_clip: int = 4, steps_per_frame: int = 8, batch: int = 4096,
-          lr: float = 2e-3, lr_final: float = 2e-4, stats_clips: int = 8, seed: int = 0, log=print):
+          lr: float = 2e-3, lr_final: float = 2e-4, stats_clips: int = 8, seed: int = 0, log=print,
+          windows=(30,), noise_mix: bool = False):
     t0 = time.time()
     gen = torch.Generator().manual_seed(seed)
     rng = np.random.default_rng(seed)
     # feature statistics over a few clips
     moments = None
     for i in range(stats_clips):
-        wl = configs.learned_train(i)
+        wl = training_workload(i, noise_mix)
         clip, staged = make_clip(wl)
         for f in rng.choice(clip.n_frames, size=2, replace=False).tolist():
-            fs = FrameSets(clip, staged, wl, f)
+            fs = FrameSets(clip, staged, wl, f, window=int(rng.choice(windows)))
             moments = sg.scene_feature_moments(staged, fs.sets, fs.params, sample_pixels(fs, batch, gen),
                                                moments=moments, ws=fs.ws)
     mean, std = sg.standardisation_from_moments(moments)
@@ -146,10 +165,10 @@ def train(n_clips: int = 200, frames_per_clip: int = 4, steps_per_frame: int = 8
     losses = []
     step = 0
     for i in range(n_clips):
-        wl = configs.learned_train(i)
+        wl = training_workload(i, noise_mix)
         clip, staged = make_clip(wl)
         for f in rng.choice(clip.n_frames, size=frames_per_clip, replace=False).tolist():
-            fs = FrameSets(clip, staged, wl, f)
+            fs = FrameSets(clip, staged, wl, f, window=int(rng.choice(windows)))
             for _ in range(steps_per_frame):
                 cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * step / max(total - 1, 1)))
                 idx = sample_pixels(fs, batch, gen)
@@ -162,7 +181,8 @@ def train(n_clips: int = 200, frames_per_clip: int = 4, steps_per_frame: int = 8
             log(f"clip {i + 1}/{n_clips}  step {step}  loss {np.mean(losses[-10 * frames_per_clip:]):.3e}  "
                 f"{time.time() - t0:.0f}s")
     meta = {"clips": n_clips, "frames_per_clip": frames_per_clip, "steps": step, "batch": batch, "lr": lr,
-            "lr_final": lr_final, "seed": seed, "window": 30, "mean": mean.tolist(), "std": std.tolist(),
+            "lr_final": lr_final, "seed": seed, "windows": list(windows), "noise_mix": noise_mix,
+            "mean": mean.tolist(), "std": std.tolist(),
             "final_loss": float(np.mean(losses[-20:])), "seconds": time.time() - t0}
     return state.params, meta
 
@@ -176,14 +196,19 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval-clips", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--windows", default="30", help="comma-separated windows drawn per training frame")
+    ap.add_argument("--noise-mix", action="store_true", help="draw noise levels and movers per clip")
+    ap.add_argument("--eval-windows", default="30")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("training needs a GPU")
+    windows = tuple(int(x) for x in a.windows.split(","))
     params, meta = train(a.clips, a.frames_per_clip, a.steps_per_frame, a.batch, a.lr, a.lr / 10, seed=a.seed,
-                         log=lambda s: print(s, flush=True))
+                         log=lambda s: print(s, flush=True), windows=windows, noise_mix=a.noise_mix)
     if a.eval_clips > 0:
-        meta["eval"] = evaluate(params, a.eval_clips, log=lambda s: print(s, flush=True))
+        meta["eval"] = evaluate(params, a.eval_clips, log=lambda s: print(s, flush=True),
+                                windows=tuple(int(x) for x in a.eval_windows.split(",")))
     save_mlp(a.out, params, meta)
     print(json.dumps({k: v for k, v in meta.items() if k not in ("mean", "std")}), flush=True)
 

@@ -223,3 +223,36 @@ def test_train_step_rejects_bad_arguments(native, case):
         wsb = 8
     assert lib.scene_mlp_train_step(ctypes.byref(c), 2, 4, ctypes.byref(p), ctypes.byref(s), idx, n, clean, stp,
                                     lr, t, ws, wsb, None) == 1, case
+
+
+def test_batch_entry_points_reject_bad_arguments(native):
+    mod, lib = native
+    c = _clip(mod)
+    p = (mod.SgGatherParams * 2)(mod.SgGatherParams(3, 1, 0.01, 0.01), mod.SgGatherParams(3, 2, 0.01, 0.01))
+    fp = (mod.SgFilterParams * 2)(mod.SgFilterParams(0.01, math.inf, math.inf, 0.0),
+                                   mod.SgFilterParams(0.01, math.inf, math.inf, 0.0))
+    clips = (mod.SgClip * 2)(c, c)
+    n_out = (ctypes.c_int32 * 2)(1, 1)
+    h = ctypes.c_void_p()
+    assert lib.sg_batch_create(None, clips, 2, p, fp, n_out) == 1
+    assert lib.sg_batch_create(ctypes.byref(h), clips, 0, p, fp, n_out) == 1
+    assert lib.sg_batch_create(ctypes.byref(h), None, 2, p, fp, n_out) == 1
+    assert lib.sg_batch_create(ctypes.byref(h), clips, 5000, p, fp, n_out) == 4
+    # all clips of a batch share one radius
+    assert lib.sg_batch_create(ctypes.byref(h), clips, 2, p, fp, n_out) == 4
+    bad_n = (ctypes.c_int32 * 2)(1, 0)
+    p[1].radius = 1
+    assert lib.sg_batch_create(ctypes.byref(h), clips, 2, p, fp, bad_n) == 1
+    fp[1].sigma_d = 0.0
+    assert lib.sg_batch_create(ctypes.byref(h), clips, 2, p, fp, n_out) == 1
+    assert h.value is None
+    io = mod.SgBatchIo(0x1000, 0x2000, 0x3000, 10, 0x4000, None)
+    assert lib.scene_gather_batched(None, ctypes.byref(io), None) == 1
+    assert lib.sg_batch_count(None, ctypes.byref(io), None) == 1
+    assert lib.sg_batch_capture(None, ctypes.byref(io), None) == 1
+    assert lib.sg_batch_autotune(None, ctypes.byref(io), None, None) == 1
+    assert lib.sg_batch_set_frames(None, n_out) == 1
+    assert lib.sg_batch_set_config(None, 4, 1, 4) == 1
+    assert lib.sg_batch_get_config(None, n_out) == 1
+    assert lib.sg_batch_pixel_base(None, 0) == -1
+    lib.sg_batch_destroy(None)
