@@ -327,6 +327,10 @@ sg_status sg_batch_capture(sg_batch* b, const sg_batch_io* io, void* stream);
  * Synchronises the stream. */
 sg_status sg_batch_autotune(sg_batch* b, const sg_batch_io* io, void* stream, int32_t* cfg_out);
 
+/* One eager step with events between the passes; ms_out[5] = pose prep, count,
+ * scan, scatter, filter (ms). Synchronises the stream. */
+sg_status sg_batch_time_passes(sg_batch* b, const sg_batch_io* io, void* stream, float* ms_out);
+
 /* Set / read the configuration (count tile height, count unroll, scatter tile
  * height); results do not depend on it. */
 sg_status sg_batch_set_config(sg_batch* b, int32_t th_count, int32_t k_count, int32_t th_scatter);

@@ -516,6 +516,13 @@ class Batch:
         _check(_lib.sg_batch_autotune(self._h, ctypes.byref(st), _stream_handle(), cfg), "sg_batch_autotune")
         return tuple(cfg)
 
+    def time_passes(self, io: BatchIO) -> dict:
+        """One eager step with events between passes -> ms per pass (synchronises)."""
+        ms = (ctypes.c_float * 5)()
+        st = io.c_struct()
+        _check(_lib.sg_batch_time_passes(self._h, ctypes.byref(st), _stream_handle(), ms), "sg_batch_time_passes")
+        return dict(zip(("prep", "count", "scan", "scatter", "filter"), list(ms)))
+
     def set_config(self, th_count: int, k_count: int, th_scatter: int) -> None:
         _check(_lib.sg_batch_set_config(self._h, th_count, k_count, th_scatter), "sg_batch_set_config")
 

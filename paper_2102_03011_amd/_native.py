@@ -104,6 +104,8 @@ SIGNATURES = {
     "sg_batch_capture": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p]),
     "sg_batch_autotune": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p,
                                           ctypes.POINTER(ctypes.c_int32)]),
+    "sg_batch_time_passes": (ctypes.c_int, [c_void_p, ctypes.POINTER(SgBatchIo), c_void_p,
+                                             ctypes.POINTER(ctypes.c_float)]),
     "sg_batch_set_config": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "sg_batch_get_config": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "scene_mlp_train_step": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,

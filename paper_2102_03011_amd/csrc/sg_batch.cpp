@@ -385,6 +385,40 @@ sg_status sg_batch_capture(sg_batch* b, const sg_batch_io* io, void* stream) {
   return SG_OK;
 }
 
+sg_status sg_batch_time_passes(sg_batch* b, const sg_batch_io* io, void* stream, float* ms_out) {
+  sg_status s = check_io(b, io, true);
+  if (s != SG_OK) return s;
+  if (ms_out == nullptr) return SG_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const sg::BatchIo bio = io_of(io);
+  const sg::BatchLaunch l = launch_cfg(*b);
+  hipEvent_t ev[6] = {};
+  for (int i = 0; i < 6; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int k = 0; k < i; ++k) ignore(hipEventDestroy(ev[k]));
+      return SG_E_HIP;
+    }
+  s = hip_status(hipMemcpyAsync(b->d_f0, b->h_f0, sizeof(int) * b->n_clips, hipMemcpyHostToDevice, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[0], st));
+  if (s == SG_OK) s = hip_status(sg::launch_batch_prep(dev_view(*b, 1), b->d_queues, bio.status, l.max_slots, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[1], st));
+  if (s == SG_OK) s = hip_status(sg::launch_batch_count(dev_view(*b, l.th_count), bio, l, b->d_queues, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[2], st));
+  if (s == SG_OK) s = hip_status(sg::launch_scan(bio.offsets, b->total_pix, b->d_partial, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[3], st));
+  if (s == SG_OK)
+    s = hip_status(sg::launch_batch_scatter(dev_view(*b, l.th_scatter), bio, l, b->d_queues + 1, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[4], st));
+  if (s == SG_OK && bio.out != nullptr)
+    s = hip_status(sg::launch_batch_filter(dev_view(*b, 1), bio, l, b->total_pix, b->d_queues + 2, st));
+  if (s == SG_OK) s = hip_status(hipEventRecord(ev[5], st));
+  for (int i = 0; i < 5 && s == SG_OK; ++i) ms_out[i] = elapsed(ev[i], ev[i + 1]);
+  for (int i = 0; i < 6; ++i) ignore(hipEventDestroy(ev[i]));
+  if (s == SG_OK) s = hip_status(hipEventRecord(b->step_done, st));
+  if (s == SG_OK) b->step_recorded = true;
+  return s;
+}
+
 sg_status sg_batch_autotune(sg_batch* b, const sg_batch_io* io, void* stream, int32_t* cfg_out) {
   sg_status s = check_io(b, io, true);
   if (s != SG_OK) return s;

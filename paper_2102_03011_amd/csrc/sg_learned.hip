@@ -124,6 +124,11 @@ __device__ __forceinline__ uint32_t bf16_half_bits(uint16_t b) {
   return __float_as_uint(__uint_as_float(static_cast<uint32_t>(b) << 16) * 0.5f) >> 16;
 }
 
+__device__ __forceinline__ void wave_lds_fence_l() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // ---------------------------------------------------------------------------
 // Per-pixel context and the eight features of one sample.
 
@@ -239,7 +244,113 @@ __device__ __forceinline__ void set_median(const uint2* __restrict__ crho, int64
 // ---------------------------------------------------------------------------
 // a7: learned filter (inference).
 
-constexpr int kLGroup = 16;  // lanes per output pixel
+constexpr int kFlatPix = 16;  // output pixels per wave of the learned filter
+
+// Lower median per channel over records [s, e) when every colour is one of the 256
+// staged codes c / 255 (binary16 bits code[c], increasing in c): binary search over
+// c, 8 steps. Lanes sub = 0 .. kWidth - 1 cooperate.
+template <int kWidth>
+__device__ __forceinline__ void set_median_codes(const uint2* __restrict__ crho, int64_t s, int64_t e, int sub,
+                                                 const uint16_t* __restrict__ code, float* med) {
+  const int64_t n = e - s;
+  med[0] = med[1] = med[2] = 0.0f;
+  if (n <= 0) return;
+  const int need = static_cast<int>((n - 1) / 2 + 1);
+  int lo[3] = {0, 0, 0}, hi[3] = {255, 255, 255};
+  for (int it = 0; it < 8; ++it) {
+    uint32_t t[3];
+    int cnt[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] = code[(lo[c] + hi[c]) >> 1];
+    for (int64_t i = s + sub; i < e; i += kWidth) {
+      const uint2 r = crho[i];
+      cnt[0] += (r.x & 0xFFFFu) <= t[0];
+      cnt[1] += (r.x >> 16) <= t[1];
+      cnt[2] += (r.y & 0xFFFFu) <= t[2];
+    }
+#pragma unroll
+    for (int off = kWidth / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cnt[c] += __shfl_xor(cnt[c], off, kWidth);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int mid = (lo[c] + hi[c]) >> 1;
+      if (cnt[c] >= need) hi[c] = mid; else lo[c] = mid + 1;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) med[c] = h2f(code[lo[c]]);
+}
+
+// The MLP on the wave's 64 samples (features staged in xs[0] (hi) / xs[1] (lo),
+// one uint4 per sample): returns the logit of the lane's own sample.
+__device__ __forceinline__ float mlp_logits_64(const bf16x8 (&a1)[2], const bf16x8 (&a2)[2][4],
+                                               const uint4* xs_hi, const uint4* xs_lo, const float* s_bh,
+                                               const float* s_w3, float b3, int hi32, int col) {
+  float m_own = 0.0f;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    // B operand of layer 1: sample 32u + col, hi parts (hi32 = 0) or lo parts (hi32 = 1)
+    const uint4 xv = (hi32 ? xs_lo : xs_hi)[32 * u + col];
+    const bf16x8 bx = as_bf16x8(u32x4{xv.x, xv.y, xv.z, xv.w});
+    // layer 1 + GELU; element a of tile t is hidden 32t + 8(a/4) + 4 hi32 + a%4
+    uint32_t ph[2][8], pl[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      // y = z/2: the accumulator starts at b/2
+      v16f c;
+#pragma unroll
+      for (int a = 0; a < 16; ++a) c[a] = s_bh[32 * t + 8 * (a / 4) + 4 * hi32 + a % 4];
+      const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[t], bx, c, 0, 0, 0);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) split_pack(gelu_half(d[2 * p]), gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
+    }
+    // layer 2 (hi and lo passes) and the output unit on the vector units
+    float mpart = 0.0f;
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      v16f d;
+#pragma unroll
+      for (int a = 0; a < 16; ++a) d[a] = s_bh[kNH + 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int t = st / 2, p0 = 4 * (st % 2);
+        const u32x4 bh = {ph[t][p0], ph[t][p0 + 1], ph[t][p0 + 2], ph[t][p0 + 3]};
+        const u32x4 bl = {pl[t][p0], pl[t][p0 + 1], pl[t][p0 + 2], pl[t][p0 + 3]};
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bh), d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bl), d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int hid = 32 * t2 + 8 * q4 + 4 * hi32 + r;
+          mpart = fmaf(s_w3[hid], gelu_half(d[4 * q4 + r]), mpart);
+        }
+    }
+    const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
+    if (u == hi32) m_own = msum;
+  }
+  return m_own;
+}
+
+// Per output pixel of a wave, in LDS.
+struct FlatPixel {
+  int64_t s, e;                  // CSR range
+  float x, y, dp, x7;
+  float med[3], cref[3];
+  int f, fo;
+  float run_m, run_z, acc[3];    // online softmax state
+};
+
+// ---------------------------------------------------------------------------
+// a7: learned filter (inference). Each wave owns kFlatPix consecutive output
+// pixels and streams their records, which are contiguous in the CSR arena, 64 at
+// a time: lane l takes record base + l, so every matrix-core column is a real
+// sample except in the wave's last step, whatever the set sizes. The set softmax
+// is a segmented reduction across lanes (records are sorted by pixel): a
+// segmented max scan, then segmented sums of e^(m - max) and e^(m - max) c; the
+// last lane of each pixel's run merges the run into that pixel's online state.
 
 __global__ __launch_bounds__(256) void k_filter_learned(
     const uint2* __restrict__ rgbd, const uint16_t* __restrict__ depth, const float* __restrict__ rel,
@@ -247,28 +358,31 @@ __global__ __launch_bounds__(256) void k_filter_learned(
     int64_t n_pix, const int64_t* __restrict__ offsets, const uint32_t* __restrict__ ids,
     const uint2* __restrict__ crho, int64_t capacity, const uint16_t* __restrict__ mw,
     const float* __restrict__ mb, float* __restrict__ out) {
-  __shared__ float s_b[SG_MLP_NB];
   __shared__ float s_bh[2 * kNH];  // b1 / 2, b2 / 2
   __shared__ float s_w3[kNH];
-  __shared__ uint4 s_x[2][4][64];  // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
-  for (int i = threadIdx.x + threadIdx.y * 64; i < SG_MLP_NB; i += 256) s_b[i] = mb[i];
-  for (int i = threadIdx.x + threadIdx.y * 64; i < 2 * kNH; i += 256) s_bh[i] = 0.5f * mb[i];
-  for (int i = threadIdx.x + threadIdx.y * 64; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
+  __shared__ float s_std[2 * kNF];  // mean, 1 / std
+  __shared__ uint16_t s_code[256];  // binary16 bits of c / 255
+  __shared__ uint4 s_x[2][4][64];   // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
+  __shared__ FlatPixel s_px[4][kFlatPix];
+  const int tid = threadIdx.x + threadIdx.y * 64;
+  for (int i = tid; i < 2 * kNH; i += 256) s_bh[i] = 0.5f * mb[i];
+  for (int i = tid; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
+  for (int i = tid; i < 2 * kNF; i += 256) s_std[i] = mb[kOffMean + i];
+  s_code[tid] = static_cast<uint16_t>(f2h(static_cast<float>(tid) / 255.0f));  // as staged
   __syncthreads();
 
   const int lane = threadIdx.x, wv = threadIdx.y;
-  const int g = lane / kLGroup, sub = lane % kLGroup;
   const int hi32 = lane >> 5, col = lane & 31;
-  const int64_t pix = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * 4 + g;
-  const bool live_pix = pix < n_pix;
-  const size_t plane = static_cast<size_t>(width) * height;
+  const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 4 + wv) * kFlatPix;
+  const int64_t plane = static_cast<int64_t>(width) * height;
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  FlatPixel* px = s_px[wv];
 
   // A operands (rows = hidden units), kept in registers. v_mfma_f32_32x32x16_bf16:
   // lane (hi32, col) holds A[col][8 hi32 + j] and B[8 hi32 + j][col], j = 0..7.
   // Layer 1, tile t: K = 16 = the 8 features' hi parts (hi32 = 0) and lo parts
-  // (hi32 = 1), so both halves hold W1[j][32t + col].
+  // (hi32 = 1), so both halves hold W1[j][32t + col] (halved: y = z/2).
   bf16x8 a1[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -298,35 +412,69 @@ __global__ __launch_bounds__(256) void k_filter_learned(
       }
       a2[t2][st] = as_bf16x8(v);
     }
+  const float b3 = mb[kOffB3];
 
-  int64_t s = 0, e = 0;
-  bool bad = false;
-  PixelCtx px{};
-  float cref[3] = {0.f, 0.f, 0.f};
-  int fo = 0;
-  if (live_pix) {
-    fo = static_cast<int>(pix / static_cast<int64_t>(plane));
-    const int64_t self = pix - static_cast<int64_t>(fo) * plane;
-    const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
-    const size_t pi = static_cast<size_t>(f0 + fo) * pplane + padded_index(x, y, pw);
-    const uint2 ref = rgbd[pi];
-    cref[0] = h2f(ref.x);
-    cref[1] = h2f(ref.x >> 16);
-    cref[2] = h2f(ref.y);
-    px.x = static_cast<float>(x);
-    px.y = static_cast<float>(y);
-    px.dp = h2f(depth[pi]);
-    px.f = f0 + fo;
-    s = offsets[pix];
-    e = offsets[pix + 1];
-    bad = s < 0 || e < s || e > capacity;
-    if (bad) s = e = 0;
-    px.x7 = __logf(1.0f + static_cast<float>(e - s)) / log_norm;
+  // 1. per-pixel context (lane k < kFlatPix: pixel p0 + k)
+  if (lane < kFlatPix) {
+    FlatPixel& q = px[lane];
+    const int64_t pix = p0 + lane;
+    q.run_m = -INFINITY;
+    q.run_z = 0.0f;
+    q.acc[0] = q.acc[1] = q.acc[2] = 0.0f;
+    q.med[0] = q.med[1] = q.med[2] = 0.0f;
+    if (pix < n_pix) {
+      q.fo = static_cast<int>(pix / plane);
+      const int64_t self = pix - q.fo * plane;
+      const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
+      q.f = f0 + q.fo;
+      const size_t pi = static_cast<size_t>(q.f) * pplane + padded_index(x, y, pw);
+      const uint2 ref = rgbd[pi];
+      q.cref[0] = h2f(ref.x);
+      q.cref[1] = h2f(ref.x >> 16);
+      q.cref[2] = h2f(ref.y);
+      q.x = static_cast<float>(x);
+      q.y = static_cast<float>(y);
+      q.dp = h2f(depth[pi]);
+      q.s = offsets[pix];
+      q.e = offsets[pix + 1];
+      q.x7 = __logf(1.0f + static_cast<float>(q.e - q.s)) / log_norm;
+    } else {
+      q.fo = 0;
+      q.f = f0;
+      q.s = q.e = -1;  // not a pixel
+    }
   }
-  set_median<kLGroup>(crho, s, e, sub, px.medr, px.medg, px.medb);
+  wave_lds_fence_l();
+  // The wave's records are [rs, re): the pixels' ranges are consecutive CSR entries.
+  // Offsets that decrease (not produced by a count pass) make every pixel of the
+  // wave NaN; a pixel whose set ends past the arena is NaN, and so are the pixels
+  // after it; nothing outside [0, capacity) is read.
+  const int64_t rs = px[0].s;
+  int last = -1;
+  bool wave_bad = rs < 0 && p0 < n_pix;
+  for (int k = 0; k < kFlatPix; ++k) {
+    if (px[k].s < 0 && px[k].e < 0) break;  // past the last pixel
+    if (px[k].e < px[k].s || px[k].s != (k == 0 ? rs : px[k - 1].e)) wave_bad = true;
+    if (!wave_bad && px[k].e <= capacity) last = k;
+  }
+  if (wave_bad) last = -1;
+  const int64_t re = last >= 0 ? px[last].e : rs;
+
+  // 2. medians: four pixels at a time, 16 lanes each
+  for (int r = 0; r < kFlatPix / 4; ++r) {
+    const int k = 4 * r + lane / 16;
+    const bool ok = k <= last;
+    float med[3];
+    set_median_codes<16>(crho, ok ? px[k].s : 0, ok ? px[k].e : 0, lane % 16, s_code, med);
+    if (ok && lane % 16 == 0) {
+      px[k].med[0] = med[0];
+      px[k].med[1] = med[1];
+      px[k].med[2] = med[2];
+    }
+  }
+  wave_lds_fence_l();
 
   FeatureArgs fa;
-  fa.rel = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
   fa.depth = depth;
   fa.width = width;
   fa.height = height;
@@ -340,122 +488,107 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   fa.cx = cx;
   fa.cy = cy;
 
-  // steps needed by the longest of the wave's four sets
-  int steps = static_cast<int>((e - s + kLGroup - 1) / kLGroup);
+  // 3. stream the records
+  for (int64_t base = rs; base < re; base += 64) {
+    const int64_t idx = base + lane;
+    bool live = idx < re;
+    // pixel of the record: the number of wave pixels whose range ends at or before it
+    int k = 0;
 #pragma unroll
-  for (int off = 16; off < 64; off <<= 1) steps = max(steps, __shfl_xor(steps, off, 64));
-
-  float run_m = -INFINITY, run_z = 0.0f, acc[3] = {0.f, 0.f, 0.f};
-  const float b3 = s_b[kOffB3];
-  for (int st = 0; st < steps; ++st) {
-    const int64_t idx = s + static_cast<int64_t>(st) * kLGroup + sub;
-    bool live = idx < e;
+    for (int j = 0; j < kFlatPix; ++j) k += (j <= last && px[j].e <= idx) ? 1 : 0;
+    if (k > last) live = false;
     uint2 rec = make_uint2(0u, 0u);
     float feat[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (live) {
+      const FlatPixel& q = px[k];
       const uint32_t id = ids[idx];
-      live = id_in_clip(fa, px.f, id);
+      live = id_in_clip(fa, q.f, id);
       if (live) {
         rec = crho[idx];
-        sample_features(fa, px, id, rec, feat);
+        PixelCtx pc;
+        pc.x = q.x;
+        pc.y = q.y;
+        pc.dp = q.dp;
+        pc.f = q.f;
+        pc.medr = q.med[0];
+        pc.medg = q.med[1];
+        pc.medb = q.med[2];
+        pc.x7 = q.x7;
+        FeatureArgs fk = fa;
+        fk.rel = rel + static_cast<size_t>(q.fo) * (2 * w + 1) * kRelStride;
+        sample_features(fk, pc, id, rec, feat);
       }
     }
     uint32_t xh[4], xl[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
-      split_pack((feat[2 * p] - s_b[kOffMean + 2 * p]) * s_b[kOffInvStd + 2 * p],
-                 (feat[2 * p + 1] - s_b[kOffMean + 2 * p + 1]) * s_b[kOffInvStd + 2 * p + 1], xh[p], xl[p]);
+      split_pack((feat[2 * p] - s_std[2 * p]) * s_std[kNF + 2 * p],
+                 (feat[2 * p + 1] - s_std[2 * p + 1]) * s_std[kNF + 2 * p + 1], xh[p], xl[p]);
     s_x[0][wv][lane] = make_uint4(xh[0], xh[1], xh[2], xh[3]);
     s_x[1][wv][lane] = make_uint4(xl[0], xl[1], xl[2], xl[3]);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    float m_own = 0.0f;
+    wave_lds_fence_l();
+    const float m_own = mlp_logits_64(a1, a2, s_x[0][wv], s_x[1][wv], s_bh, s_w3, b3, hi32, col);
+
+    // segmented softmax over the lanes: key = pixel (dead lanes get keys of their own)
+    // (every shuffle runs on all 64 lanes: a lane that skipped one would leave its
+    // value unread by the lanes that take it)
+    const int key = live ? k : kFlatPix + lane;
+    const int key_next = __shfl_down(key, 1, 64);
+    const bool is_last = lane == 63 || key_next != key;
+    const uint64_t last_mask = __ballot(is_last);
+    const int seg_end = lane + __builtin_ctzll(last_mask >> lane);
+    bool same[6];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      // B operand of layer 1: sample 32u + col, hi parts (hi32 = 0) or lo parts (hi32 = 1)
-      const uint4 xs = s_x[hi32][wv][32 * u + col];
-      const bf16x8 bx = as_bf16x8(u32x4{xs.x, xs.y, xs.z, xs.w});
-      // layer 1 + GELU; element a of tile t is hidden 32t + 8(a/4) + 4 hi32 + a%4
-      uint32_t ph[2][8], pl[2][8];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        // y = z/2: the accumulator starts at b/2 (element a: hidden 32t + 8(a/4) + 4 hi32 + a%4)
-        v16f c;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) c[a] = s_bh[32 * t + 8 * (a / 4) + 4 * hi32 + a % 4];
-        const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[t], bx, c, 0, 0, 0);
-#pragma unroll
-        for (int p = 0; p < 8; ++p)
-          split_pack(gelu_half(d[2 * p]), gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
-      }
-      // layer 2 (hi and lo passes) and the output unit on the vector units
-      float mpart = 0.0f;
-#pragma unroll
-      for (int t2 = 0; t2 < 2; ++t2) {
-        v16f d;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) d[a] = s_bh[kOffB2 + 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4];
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int t = st / 2, p0 = 4 * (st % 2);
-          const u32x4 bh = {ph[t][p0], ph[t][p0 + 1], ph[t][p0 + 2], ph[t][p0 + 3]};
-          const u32x4 bl = {pl[t][p0], pl[t][p0 + 1], pl[t][p0 + 2], pl[t][p0 + 3]};
-          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bh), d, 0, 0, 0);
-          d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bl), d, 0, 0, 0);
-        }
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int hid = 32 * t2 + 8 * q4 + 4 * hi32 + r;
-            mpart = fmaf(s_w3[hid], gelu_half(d[4 * q4 + r]), mpart);
-          }
-      }
-      const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
-      if (u == hi32) m_own = msum;
+    for (int l = 0; l < 6; ++l) {
+      const int key_prev = __shfl_up(key, 1 << l, 64);
+      same[l] = lane >= (1 << l) && key_prev == key;
     }
-    __builtin_amdgcn_wave_barrier();
-    if (live) {
-      const float cr = h2f(rec.x), cg = h2f(rec.x >> 16), cb = h2f(rec.y);
-      const float nm = fmaxf(run_m, m_own);
-      const float sc = __builtin_amdgcn_exp2f((run_m - nm) * kLog2e);
-      const float ew = __builtin_amdgcn_exp2f((m_own - nm) * kLog2e);
-      run_z = fmaf(run_z, sc, ew);
-      acc[0] = fmaf(acc[0], sc, ew * cr);
-      acc[1] = fmaf(acc[1], sc, ew * cg);
-      acc[2] = fmaf(acc[2], sc, ew * cb);
-      run_m = nm;
-    }
-  }
-  // merge the 16 lanes of each pixel
+    float mx = live ? m_own : -INFINITY;
 #pragma unroll
-  for (int off = kLGroup / 2; off > 0; off >>= 1) {
-    const float om = __shfl_xor(run_m, off, kLGroup);
-    const float oz = __shfl_xor(run_z, off, kLGroup);
-    const float o0 = __shfl_xor(acc[0], off, kLGroup), o1 = __shfl_xor(acc[1], off, kLGroup),
-                o2 = __shfl_xor(acc[2], off, kLGroup);
-    const float nm = fmaxf(run_m, om);
-    const float sa = run_z > 0.0f ? __builtin_amdgcn_exp2f((run_m - nm) * kLog2e) : 0.0f;
-    const float sb = oz > 0.0f ? __builtin_amdgcn_exp2f((om - nm) * kLog2e) : 0.0f;
-    run_z = run_z * sa + oz * sb;
-    acc[0] = acc[0] * sa + o0 * sb;
-    acc[1] = acc[1] * sa + o1 * sb;
-    acc[2] = acc[2] * sa + o2 * sb;
-    run_m = nm;
+    for (int l = 0; l < 6; ++l) {
+      const float o = __shfl_up(mx, 1 << l, 64);
+      if (same[l]) mx = fmaxf(mx, o);
+    }
+    const float seg_max = __shfl(mx, seg_end, 64);
+    const float ew = live ? __builtin_amdgcn_exp2f((m_own - seg_max) * kLog2e) : 0.0f;
+    float v[4] = {ew, ew * h2f(rec.x), ew * h2f(rec.x >> 16), ew * h2f(rec.y)};
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float o = __shfl_up(v[c], 1 << l, 64);
+        if (same[l]) v[c] += o;
+      }
+    }
+    if (is_last && live) {
+      FlatPixel& q = px[k];
+      const float nm = fmaxf(q.run_m, seg_max);
+      const float so = q.run_z > 0.0f ? __builtin_amdgcn_exp2f((q.run_m - nm) * kLog2e) : 0.0f;
+      const float sn = __builtin_amdgcn_exp2f((seg_max - nm) * kLog2e);
+      q.run_z = q.run_z * so + v[0] * sn;
+      q.acc[0] = q.acc[0] * so + v[1] * sn;
+      q.acc[1] = q.acc[1] * so + v[2] * sn;
+      q.acc[2] = q.acc[2] * so + v[3] * sn;
+      q.run_m = nm;
+    }
+    wave_lds_fence_l();
   }
-  if (live_pix && sub == 0) {
-    float* o = out + static_cast<size_t>(pix) * 3;
-    if (bad) {
+
+  // 4. outputs
+  if (lane < kFlatPix && p0 + lane < n_pix) {
+    const FlatPixel& q = px[lane];
+    float* o = out + static_cast<size_t>(p0 + lane) * 3;
+    if (lane > last) {
       o[0] = o[1] = o[2] = __builtin_nanf("");
-    } else if (run_z > 0.0f) {
-      const float inv = 1.0f / run_z;
-      o[0] = acc[0] * inv;
-      o[1] = acc[1] * inv;
-      o[2] = acc[2] * inv;
+    } else if (q.run_z > 0.0f) {
+      const float inv = 1.0f / q.run_z;
+      o[0] = q.acc[0] * inv;
+      o[1] = q.acc[1] * inv;
+      o[2] = q.acc[2] * inv;
     } else {
-      o[0] = cref[0];
-      o[1] = cref[1];
-      o[2] = cref[2];
+      o[0] = q.cref[0];
+      o[1] = q.cref[1];
+      o[2] = q.cref[2];
     }
   }
 }
@@ -781,7 +914,7 @@ __global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta, double* __
 // launchers
 
 hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st) {
-  const int64_t waves = (lj.n_pix + 3) / 4;
+  const int64_t waves = (lj.n_pix + kFlatPix - 1) / kFlatPix;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_filter_learned, dim3(static_cast<unsigned>(blocks)), dim3(64, 4), 0, st,

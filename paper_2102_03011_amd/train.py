@@ -29,7 +29,7 @@ import paper_2102_03011_amd as sg
 from scenegen import configs, generate
 
 WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
-DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "mlp_640x360_w30.npz")
+DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "mlp_640x360_mix.npz")
 FORMAT_VERSION = 1
 
 
