@@ -267,7 +267,8 @@ sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
  * (scene_gather_batched) runs pose prep, count, scan, scatter and filter for every
  * clip, each pass as one persistent launch whose workgroups draw work items from
  * an atomic queue (gather items: 64 x TH pixel tiles, clips in decreasing order of
- * estimated work; filter items: runs of CSR pixels). Each clip's records and
+ * estimated work; filter items: runs of 64 pixels of one clip; each wave of a
+ * workgroup draws its own items). Each clip's records and
  * filtered colours are bit-identical to those of scene_gather / scene_filter on
  * that clip alone. All clips of a batch share one radius (else SG_E_UNSUPPORTED).
  * The batch object owns only small device buffers (plan, relative maps, scan
@@ -320,8 +321,8 @@ sg_status scene_gather_batched(sg_batch* b, const sg_batch_io* io, void* stream)
  * sg_batch_set_frames through a copy node). Any configuration change drops it. */
 sg_status sg_batch_capture(sg_batch* b, const sg_batch_io* io, void* stream);
 
-/* Autotuner: times every count configuration (tile height 1, 2, 4, 8 waves x
- * source-frame unroll 1, 2, 4) and every scatter tile height that fits LDS on
+/* Autotuner: times every count configuration (rows of 64 pixels per work item 1,
+ * 2, 4, 8 x source-frame unroll 1, 2, 4) and every scatter rows-per-item value on
  * this batch and step, keeps the fastest and writes it to cfg_out[3] (may be
  * NULL). Needs frames set and an arena that holds the step (else SG_E_CAPACITY).
  * Synchronises the stream. */
@@ -331,8 +332,8 @@ sg_status sg_batch_autotune(sg_batch* b, const sg_batch_io* io, void* stream, in
  * scan, scatter, filter (ms). Synchronises the stream. */
 sg_status sg_batch_time_passes(sg_batch* b, const sg_batch_io* io, void* stream, float* ms_out);
 
-/* Set / read the configuration (count tile height, count unroll, scatter tile
- * height); results do not depend on it. */
+/* Set / read the configuration (count rows per item, count unroll, scatter rows
+ * per item); results do not depend on it. */
 sg_status sg_batch_set_config(sg_batch* b, int32_t th_count, int32_t k_count, int32_t th_scatter);
 sg_status sg_batch_get_config(const sg_batch* b, int32_t* cfg);
 

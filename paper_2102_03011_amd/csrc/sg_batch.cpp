@@ -39,6 +39,7 @@ struct sg_batch {
   int* d_order = nullptr;
   int64_t* d_prefix[4] = {nullptr, nullptr, nullptr, nullptr};  // tile heights 1, 2, 4, 8
   int64_t* d_pix_prefix = nullptr;
+  int64_t* d_fprefix = nullptr;     // first filter work item of each clip (clip order), n + 1
   int64_t* d_partial = nullptr;
   unsigned int* d_queues = nullptr;
   int* h_f0 = nullptr;          // pinned: the frames of the next step
@@ -93,10 +94,11 @@ sg::BatchLaunch launch_cfg(const sg_batch& b) {
   l.th_count = b.th_count;
   l.k_count = b.k_count;
   l.th_scatter = b.th_scatter;
-  // persistent grids: enough workgroups to fill every CU, never more than items
-  const int64_t items_c = b.total_pix > 0 ? (b.total_pix + 63) / 64 : 1;
-  l.blocks_count = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(b.cus) * 32 / b.th_count, items_c));
-  const size_t lds = sg::batch_scatter_lds_bytes(b.radius) * static_cast<size_t>(b.th_scatter);
+  // persistent grids of 4-wave workgroups: enough to fill every CU (8 waves per SIMD,
+  // or as many scatter workgroups as LDS holds), never more than there are items
+  const int64_t items_c = b.total_pix > 0 ? (b.total_pix + 255) / 256 : 1;
+  l.blocks_count = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(b.cus) * 8, items_c));
+  const size_t lds = sg::batch_scatter_lds_bytes(b.radius) * 4;
   const int per_cu = std::max<int>(1, static_cast<int>(163840 / std::max<size_t>(lds, 1)));
   l.blocks_scatter = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(b.cus) * std::min(per_cu, 8), items_c));
   l.blocks_filter = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(b.cus) * 8, items_c));
@@ -151,7 +153,7 @@ sg_status enqueue_step(sg_batch* b, const sg::BatchIo& io, hipStream_t st) {
   if ((s = hip_status(sg::launch_batch_scatter(dev_view(*b, l.th_scatter), io, l, b->d_queues + 1, st))) != SG_OK)
     return s;
   if (io.out == nullptr) return SG_OK;
-  return hip_status(sg::launch_batch_filter(dev_view(*b, 1), io, l, b->total_pix, b->d_queues + 2, st));
+  return hip_status(sg::launch_batch_filter(dev_view(*b, 1), io, l, b->d_fprefix, b->d_queues + 2, st));
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -220,6 +222,7 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
   size_t o_prefix[4];
   for (int t = 0; t < 4; ++t) { o_prefix[t] = off; off = align_up(off + (n + 1) * sizeof(int64_t)); }
   const size_t o_pix = off; off = align_up(off + (n + 1) * sizeof(int64_t));
+  const size_t o_fpre = off; off = align_up(off + (n + 1) * sizeof(int64_t));
   const size_t o_part = off; off = align_up(off + nb * sizeof(int64_t));
   const size_t o_q = off; off = align_up(off + 4 * sizeof(unsigned int));
   const size_t o_rel = off; off = align_up(off + rel_floats * sizeof(float));
@@ -234,6 +237,7 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
   b->d_order = reinterpret_cast<int*>(base + o_order);
   for (int t = 0; t < 4; ++t) b->d_prefix[t] = reinterpret_cast<int64_t*>(base + o_prefix[t]);
   b->d_pix_prefix = reinterpret_cast<int64_t*>(base + o_pix);
+  b->d_fprefix = reinterpret_cast<int64_t*>(base + o_fpre);
   b->d_partial = reinterpret_cast<int64_t*>(base + o_part);
   b->d_queues = reinterpret_cast<unsigned int*>(base + o_q);
   float* rel = reinterpret_cast<float*>(base + o_rel);
@@ -266,11 +270,14 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
     d.a_c = isfinite(sc) ? static_cast<float>(-log2e / (2.0 * sc * static_cast<double>(sc))) : 0.0f;
     d.a_t = isfinite(stt) ? static_cast<float>(-log2e / (2.0 * stt * static_cast<double>(stt))) : 0.0f;
   }
-  std::vector<int64_t> prefix(n + 1);
+  std::vector<int64_t> prefix(n + 1), fprefix(n + 1, 0);
+  for (int c = 0; c < n_clips; ++c)
+    fprefix[c + 1] = fprefix[c] + sg::batch_filter_items(b->pix_prefix[c + 1] - b->pix_prefix[c]);
   bool ok = hipMemcpy(b->d_clips, hc.data(), n * sizeof(sg::BatchClip), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(b->d_order, b->order.data(), n * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(b->d_pix_prefix, b->pix_prefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice) ==
-                hipSuccess;
+                hipSuccess &&
+            hipMemcpy(b->d_fprefix, fprefix.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
   for (int t = 0; t < 4 && ok; ++t) {
     const int th = 1 << t;
     prefix[0] = 0;
@@ -410,7 +417,7 @@ sg_status sg_batch_time_passes(sg_batch* b, const sg_batch_io* io, void* stream,
     s = hip_status(sg::launch_batch_scatter(dev_view(*b, l.th_scatter), bio, l, b->d_queues + 1, st));
   if (s == SG_OK) s = hip_status(hipEventRecord(ev[4], st));
   if (s == SG_OK && bio.out != nullptr)
-    s = hip_status(sg::launch_batch_filter(dev_view(*b, 1), bio, l, b->total_pix, b->d_queues + 2, st));
+    s = hip_status(sg::launch_batch_filter(dev_view(*b, 1), bio, l, b->d_fprefix, b->d_queues + 2, st));
   if (s == SG_OK) s = hip_status(hipEventRecord(ev[5], st));
   for (int i = 0; i < 5 && s == SG_OK; ++i) ms_out[i] = elapsed(ev[i], ev[i + 1]);
   for (int i = 0; i < 6; ++i) ignore(hipEventDestroy(ev[i]));

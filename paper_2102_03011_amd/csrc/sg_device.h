@@ -10,6 +10,31 @@
 
 namespace sg {
 
+// Global-memory pointers. A pointer read from a descriptor in memory (not a kernel
+// argument) is generic to the compiler and its accesses become flat instructions;
+// the device functions take pointers of the global address space, and every
+// device buffer of this library is global memory.
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gp<T> to_global(T* p) {
+  return (gp<T>)p;
+}
+
+// 8-byte records through global pointers (the vector type's members take generic
+// references only)
+__device__ __forceinline__ uint2 ld2(gp<const uint2> p) {
+  const uint64_t v = *reinterpret_cast<gp<const uint64_t>>(p);
+  return make_uint2(static_cast<uint32_t>(v), static_cast<uint32_t>(v >> 32));
+}
+__device__ __forceinline__ void st2(gp<uint2> p, uint2 v) {
+  *reinterpret_cast<gp<uint64_t>>(p) = static_cast<uint64_t>(v.x) | (static_cast<uint64_t>(v.y) << 32);
+}
+__device__ __forceinline__ void flag_or(gp<uint32_t> status, uint32_t bits) {
+  __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ float h2f(uint32_t bits16) {
   return __half2float(__ushort_as_half(static_cast<unsigned short>(bits16 & 0xFFFFu)));
 }

@@ -115,13 +115,13 @@ struct BatchIo {
 };
 
 struct BatchLaunch {
-  int th_count, k_count, th_scatter;  // tile heights (waves per workgroup), source-frame unroll
+  int th_count, k_count, th_scatter;  // rows per wave work item, source-frame unroll
   int blocks_count, blocks_scatter, blocks_filter;
   bool colour, time;
   int max_slots;                     // max over clips of n_out (2w + 1)
 };
 
-int batch_scatter_max_th(int radius);         // largest scatter tile height that fits LDS
+int batch_scatter_max_th(int radius);         // largest scatter rows-per-item
 size_t batch_scatter_lds_bytes(int radius);   // LDS of one scatter wave
 hipError_t launch_batch_prep(const BatchDev& bd, unsigned int* queues, uint32_t* status, int max_slots,
                              hipStream_t st);
@@ -129,8 +129,9 @@ hipError_t launch_batch_count(const BatchDev& bd, const BatchIo& io, const Batch
                               unsigned int* queue, hipStream_t st);
 hipError_t launch_batch_scatter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl,
                                 unsigned int* queue, hipStream_t st);
-hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, int64_t n_pix,
-                               unsigned int* queue, hipStream_t st);
+hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl,
+                               const int64_t* fprefix, unsigned int* queue, hipStream_t st);
+int64_t batch_filter_items(int64_t clip_pixels);  // filter work items of a clip
 
 hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st);
 hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st);

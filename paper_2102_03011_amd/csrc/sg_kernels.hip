@@ -33,21 +33,23 @@ namespace sg {
 
 // Block rows are fetched as 8-byte words (four binary16 depths) starting at the
 // row's first column: kRowWords words cover the 2R + 1 columns.
+typedef uint64_t __attribute__((aligned(2))) RowWord;  // 4 binary16 depths, 2-byte aligned
+
 template <int R>
 struct RowLoad {
   static constexpr int kWords = (2 * R + 1 + 3) / 4;
 };
 
 template <int R>
-__device__ __forceinline__ void load_block_depths(const uint16_t* centre, int pw,
+__device__ __forceinline__ void load_block_depths(gp<const uint16_t> centre, int pw,
                                                   uint32_t (&d)[2 * R + 1][2 * R + 1]) {
   constexpr int kW = RowLoad<R>::kWords;
 #pragma unroll
   for (int dy = -R; dy <= R; ++dy) {
-    const uint16_t* rowp = centre + dy * pw - R;
+    gp<const uint16_t> rowp = centre + dy * pw - R;
     uint64_t w[kW];
 #pragma unroll
-    for (int c = 0; c < kW; ++c) __builtin_memcpy(&w[c], rowp + 4 * c, 8);
+    for (int c = 0; c < kW; ++c) w[c] = *reinterpret_cast<gp<const RowWord>>(rowp + 4 * c);
 #pragma unroll
     for (int o = 0; o <= 2 * R; ++o)
       d[dy + R][o] = static_cast<uint32_t>(w[o / 4] >> (16 * (o % 4))) & 0xFFFFu;
@@ -89,13 +91,13 @@ __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
 // One thread per (output frame fo, window slot s): J = f - w + s.
 // Record layout (kRelStride floats): M row-major (9), k (3), unused (4).
 
-__device__ __forceinline__ void pose_prep_one(const double* __restrict__ c2w, int n_frames, int f0, int w,
-                                              double fx, double fy, double cx, double cy,
-                                              float* __restrict__ rel, int i) {
+__device__ __forceinline__ void pose_prep_one(gp<const double> c2w, int n_frames, int f0, int w,
+                                              double fx, double fy, double cx, double cy, gp<float> rel,
+                                              int i) {
   const int slots = 2 * w + 1;
   const int fo = i / slots, s = i - fo * slots;
   const int f = f0 + fo, j = f - w + s;
-  float* out = rel + static_cast<size_t>(i) * kRelStride;
+  gp<float> out = rel + static_cast<size_t>(i) * kRelStride;
   double m[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double kt[3] = {0, 0, 0};
   if (j < 0 || j >= n_frames) {
@@ -103,8 +105,8 @@ __device__ __forceinline__ void pose_prep_one(const double* __restrict__ c2w, in
     return;
   }
   if (j != f) {
-    const double* a = c2w + static_cast<size_t>(f) * 16;   // C^f
-    const double* b = c2w + static_cast<size_t>(j) * 16;   // C^J
+    gp<const double> a = c2w + static_cast<size_t>(f) * 16;   // C^f
+    gp<const double> b = c2w + static_cast<size_t>(j) * 16;   // C^J
     // (C^J)^-1 C^f for rigid maps: R = Rj^T Rf, t = Rj^T (tf - tj)
     double r[9], t[3];
     for (int row = 0; row < 3; ++row) {
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(64) void k_pose_prep(const double* __restrict__ c2w
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && status != nullptr) *status = 0u;
   if (i >= n_out * (2 * w + 1)) return;
-  pose_prep_one(c2w, n_frames, f0, w, fx, fy, cx, cy, rel, i);
+  pose_prep_one(to_global(c2w), n_frames, f0, w, fx, fy, cx, cy, to_global(rel), i);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,7 +189,7 @@ __device__ __forceinline__ bool accept16(uint32_t d16, const Projected& p) {
   return d16 - p.lo16 <= p.range16;
 }
 
-__device__ __forceinline__ bool project(const float* __restrict__ m, float x, float y, float dp,
+__device__ __forceinline__ bool project(gp<const float> m, float x, float y, float dp,
                                         float z_near, float tol, int width, int height, int r,
                                         Projected& o) {
   const float a0 = fmaf(m[0], x, fmaf(m[1], y, m[2]));
@@ -238,7 +240,7 @@ __device__ __forceinline__ Tile tile_of_block(int tiles_x, int tiles_y) {
 
 // Members of output pixel (x, y) of output frame f; relf = the relative maps of f.
 template <int R>
-__device__ __forceinline__ int count_pixel(const uint16_t* __restrict__ depth, const float* __restrict__ relf,
+__device__ __forceinline__ int count_pixel(gp<const uint16_t> depth, gp<const float> relf,
                                            int width, int height, int n_frames, int f, int w, float tol,
                                            float z_near, int x, int y) {
   const int pw = stored_pitch(width);
@@ -268,7 +270,7 @@ __device__ __forceinline__ int count_pixel(const uint16_t* __restrict__ depth, c
 // source frame past the window or whose projection fails loads a valid apron block
 // of frame jlo and contributes nothing, so the count equals count_pixel's.
 template <int R, int K>
-__device__ __forceinline__ int count_pixel_k(const uint16_t* __restrict__ depth, const float* __restrict__ relf,
+__device__ __forceinline__ int count_pixel_k(gp<const uint16_t> depth, gp<const float> relf,
                                              int width, int height, int n_frames, int f, int w, float tol,
                                              float z_near, int x, int y) {
   if (K == 1) return count_pixel<R>(depth, relf, width, height, n_frames, f, w, tol, z_near, x, y);
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
   if (x >= width || y >= height) return;
   const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
   counts[static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x] =
-      count_pixel<R>(depth, relf, width, height, n_frames, f0 + fo, w, tol, z_near, x, y);
+      count_pixel<R>(to_global(depth), to_global(relf), width, height, n_frames, f0 + fo, w, tol, z_near, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +366,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 template <int R>
 __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const uint2* s_rec,
                                            const uint32_t* s_id, int* s_n, int64_t* s_dst,
-                                           uint32_t* __restrict__ ids, uint2* __restrict__ crho) {
+                                           gp<uint32_t> ids, gp<uint2> crho) {
   constexpr int kSlots = ScatterShape<R>::kSlots;
   constexpr int kRun = ScatterShape<R>::kRunLanes;
   constexpr int kPer = 64 / kRun;
@@ -385,7 +387,7 @@ __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const
       const int own = on >> 8, cnt = on & 0xFF;
       if (sub < cnt) {
         const int64_t dst = s_dst[e] + sub;
-        crho[dst] = s_rec[own * kSlots + sub];
+        st2(crho + dst, s_rec[own * kSlots + sub]);
         ids[dst] = s_id[own * kSlots + sub];
       }
     }
@@ -407,12 +409,11 @@ struct ScatterLds {
 // One wave writes the records of the 64 output pixels (x0 + lane, y) of output
 // frame f; pix0 = CSR index of pixel (x0, y). Every lane of the wave calls it.
 template <int R>
-__device__ __forceinline__ void scatter_wave(const uint2* __restrict__ rgbd, const uint16_t* __restrict__ depth,
-                                             const float* __restrict__ relf, int width, int height,
+__device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint16_t> depth,
+                                             gp<const float> relf, int width, int height,
                                              int n_frames, int f, int w, float tol, float z_near, int x0, int y,
-                                             int64_t pix0, const int64_t* __restrict__ offsets,
-                                             uint32_t* __restrict__ ids, uint2* __restrict__ crho,
-                                             int64_t capacity, uint32_t* __restrict__ status,
+                                             int64_t pix0, gp<const int64_t> offsets, gp<uint32_t> ids,
+                                             gp<uint2> crho, int64_t capacity, gp<uint32_t> status,
                                              ScatterLds<R>& lds) {
   using Shape = ScatterShape<R>;
   using Mask = typename Shape::Mask;
@@ -435,9 +436,9 @@ __device__ __forceinline__ void scatter_wave(const uint2* __restrict__ rgbd, con
     start = cur = offsets[pix];
     end = offsets[pix + 1];
     if (cur < 0 || end < cur) {  // offsets not produced by the count pass
-      atomicOr(status, SG_FLAG_INCONSISTENT);
+      flag_or(status, SG_FLAG_INCONSISTENT);
     } else if (end > capacity) {
-      if (end > cur) atomicOr(status, SG_FLAG_CAPACITY);
+      if (end > cur) flag_or(status, SG_FLAG_CAPACITY);
     } else {
       dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
       active = dp > z_near && dp < INFINITY;
@@ -452,12 +453,12 @@ __device__ __forceinline__ void scatter_wave(const uint2* __restrict__ rgbd, con
   for (int j = jlo; j <= jhi; ++j) {
     Projected p;
     if (active && project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) {
-      const uint2* cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
+      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
       uint2 px[kSide][kSide];
 #pragma unroll
       for (int dy = 0; dy < kSide; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = cj[(dy - R) * pw + (dx - R)];
+        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (dy - R) * pw + (dx - R));
       Mask mask = 0;
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k)
@@ -503,7 +504,7 @@ __device__ __forceinline__ void scatter_wave(const uint2* __restrict__ rgbd, con
       flush_runs<R>(fill >= Shape::kMinRun ? fill : 0, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
   }
   if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
-  if (active && found != end - start) atomicOr(status, SG_FLAG_INCONSISTENT);
+  if (active && found != end - start) flag_or(status, SG_FLAG_INCONSISTENT);
 }
 
 template <int R>
@@ -522,8 +523,9 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
   const int fo = tile.fo;
   const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
   const int64_t pix0 = static_cast<int64_t>(fo) * width * height + static_cast<int64_t>(y) * width + x0;
-  scatter_wave<R>(rgbd, depth, relf, width, height, n_frames, f0 + fo, w, tol, z_near, x0, y, pix0, offsets,
-                  ids, crho, capacity, status, lds[threadIdx.y]);
+  scatter_wave<R>(to_global(rgbd), to_global(depth), to_global(relf), width, height, n_frames, f0 + fo, w, tol,
+                  z_near, x0, y, pix0, to_global(offsets), to_global(ids), to_global(crho), capacity,
+                  to_global(status), lds[threadIdx.y]);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,19 +612,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t* __restrict
 // kGroup lanes filter one pixel: pixel `self` (y * W + x) of frame f, whose set is
 // CSR entry `pix` of offsets / out. Every lane of the group calls it (live or not).
 template <bool kColour, bool kTime>
-__device__ __forceinline__ void filter_group(const uint2* __restrict__ rgbd, int width, int height, int f,
+__device__ __forceinline__ void filter_group(gp<const uint2> rgbd, int width, int height, int f,
                                              int w, bool live, int64_t self, int64_t pix, int lane,
-                                             const int64_t* __restrict__ offsets,
-                                             const uint32_t* __restrict__ ids,
-                                             const uint2* __restrict__ crho, int64_t capacity, float a_d,
-                                             float a_c, float a_t, float* __restrict__ out) {
+                                             gp<const int64_t> offsets, gp<const uint32_t> ids,
+                                             gp<const uint2> crho, int64_t capacity, float a_d,
+                                             float a_c, float a_t, gp<float> out) {
   float cr = 0.f, cg = 0.f, cb = 0.f;
   int64_t s = 0, e = 0;
   if (live) {
     const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
     const int pw = stored_pitch(width);
     const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-    const uint2 ref = rgbd[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)];
+    const uint2 ref = ld2(rgbd + static_cast<size_t>(f) * pplane + padded_index(x, y, pw));
     cr = h2f(ref.x);
     cg = h2f(ref.x >> 16);
     cb = h2f(ref.y);
@@ -634,7 +635,7 @@ __device__ __forceinline__ void filter_group(const uint2* __restrict__ rgbd, int
   if (bad) s = e = 0;
   float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
   for (int64_t i = s + lane; i < e; i += kGroup) {
-    const uint2 rec = crho[i];
+    const uint2 rec = ld2(crho + i);
     const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y), rho = h2f(rec.y >> 16);
     float arg = a_d * rho * rho;
     if (kColour) {
@@ -659,7 +660,7 @@ __device__ __forceinline__ void filter_group(const uint2* __restrict__ rgbd, int
     ab += __shfl_xor(ab, off, kGroup);
   }
   if (live && lane == 0) {
-    float* o = out + static_cast<size_t>(pix) * 3;
+    gp<float> o = out + static_cast<size_t>(pix) * 3;
     if (bad) {
       o[0] = o[1] = o[2] = __builtin_nanf("");
     } else if (e > s) {
@@ -689,8 +690,9 @@ __global__ __launch_bounds__(256) void k_filter(const uint2* __restrict__ rgbd, 
   const bool live = pix < n_pix;
   const int64_t plane = static_cast<int64_t>(width) * height;
   const int fo = live ? static_cast<int>(pix / plane) : 0;
-  filter_group<kColour, kTime>(rgbd, width, height, f0 + fo, w, live, pix - fo * plane, pix, lane, offsets,
-                               ids, crho, capacity, a_d, a_c, a_t, out);
+  filter_group<kColour, kTime>(to_global(rgbd), width, height, f0 + fo, w, live, pix - fo * plane, pix, lane,
+                               to_global(offsets), to_global(ids), to_global(crho), capacity, a_d, a_c, a_t,
+                               to_global(out));
 }
 
 // ---------------------------------------------------------------------------
@@ -710,17 +712,25 @@ __global__ __launch_bounds__(64) void k_batch_prep(BatchDev bd, unsigned int* __
   if (c == 0 && i == 0) *status = 0u;
   const BatchClip& cl = bd.clips[c];
   if (i < cl.n_out * (2 * cl.w + 1))
-    pose_prep_one(cl.c2w, cl.n_frames, bd.f0[c], cl.w, cl.fx, cl.fy, cl.cx, cl.cy, cl.rel, i);
+    pose_prep_one(to_global(cl.c2w), cl.n_frames, bd.f0[c], cl.w, cl.fx, cl.fy, cl.cx, cl.cy, to_global(cl.rel), i);
 }
 
-// Next work item of the workgroup (the whole workgroup calls it).
-__device__ __forceinline__ int64_t next_item(unsigned int* queue, unsigned int* s_item) {
-  if (threadIdx.x == 0 && threadIdx.y == 0) *s_item = atomicAdd(queue, 1u);
-  __syncthreads();
-  const int64_t item = *s_item;
-  __syncthreads();
-  return item;
-}
+// Work items of a wave: the atomic for the next item is issued before the current
+// one is processed, so its round trip overlaps the work (every lane calls these).
+struct ItemQueue {
+  unsigned int* queue;
+  uint32_t pending;  // lane 0: the atomic's result, read when the next item is taken
+
+  __device__ __forceinline__ explicit ItemQueue(unsigned int* q) : queue(q), pending(0u) { issue(); }
+  __device__ __forceinline__ void issue() {
+    if (threadIdx.x == 0) pending = atomicAdd(queue, 1u);
+  }
+  __device__ __forceinline__ int64_t take() {
+    const int64_t item = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(pending));
+    issue();
+    return item;
+  }
+};
 
 // slot of work item `item`: the largest k with prefix[k] <= item
 __device__ __forceinline__ int item_slot(const int64_t* __restrict__ prefix, int n, int64_t item) {
@@ -733,90 +743,135 @@ __device__ __forceinline__ int item_slot(const int64_t* __restrict__ prefix, int
 }
 
 struct TileOf {
-  int clip, fo, x0, y0;
+  int fo, x0, y0;
 };
 
+// A clip descriptor read into scalar registers: every word goes through
+// readfirstlane, so the compiler knows the pointers and sizes are uniform (the
+// planes' and maps' addresses then stay scalar in the inner loops).
+__device__ __forceinline__ BatchClip load_clip(const BatchClip* __restrict__ p) {
+  static_assert(sizeof(BatchClip) % 4 == 0, "descriptor is whole words");
+  BatchClip c;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t w[sizeof(BatchClip) / 4];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(BatchClip) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  __builtin_memcpy(&c, w, sizeof(BatchClip));
+  return c;
+}
+
+// Gather item: TH rows of 64 pixels of one output frame of one clip, taken by one
+// wave. Items are numbered per slot (clips in cost order), x fastest.
 template <int TH>
-__device__ __forceinline__ TileOf batch_tile(const BatchDev& bd, int64_t item) {
-  const int k = item_slot(bd.prefix, bd.n_clips, item);
-  TileOf t;
-  t.clip = bd.order[k];
-  const BatchClip& c = bd.clips[t.clip];
-  const int64_t local = item - bd.prefix[k];
+__device__ __forceinline__ TileOf batch_tile(const BatchClip& c, int64_t local) {
   const int tiles_x = (c.width + kTileW - 1) / kTileW, tiles_y = (c.height + TH - 1) / TH;
-  t.x0 = static_cast<int>(local % tiles_x) * kTileW;
+  TileOf t;
+  // 64-bit division is expanded on the vector units: readfirstlane puts the
+  // (uniform) results back in scalar registers, so addresses built from them stay
+  // scalar
+  t.x0 = __builtin_amdgcn_readfirstlane(static_cast<int>(local % tiles_x) * kTileW);
   const int64_t rest = local / tiles_x;
-  t.y0 = static_cast<int>(rest % tiles_y) * TH;
-  t.fo = static_cast<int>(rest / tiles_y);
+  t.y0 = __builtin_amdgcn_readfirstlane(static_cast<int>(rest % tiles_y) * TH);
+  t.fo = __builtin_amdgcn_readfirstlane(static_cast<int>(rest / tiles_y));
   return t;
 }
 
+// Workgroups of 4 independent waves; each wave draws its own items, so no wave
+// waits at a barrier for the slowest row of a tile.
 template <int R, int TH, int K>
-__global__ __launch_bounds__(64 * TH) void k_count_batched(BatchDev bd, int64_t* __restrict__ counts,
-                                                           unsigned int* __restrict__ queue) {
-  __shared__ unsigned int s_item;
+__global__ __launch_bounds__(256) void k_count_batched(BatchDev bd, int64_t* __restrict__ counts,
+                                                       unsigned int* __restrict__ queue) {
   const int64_t n_items = bd.prefix[bd.n_clips];
+  ItemQueue q(queue);
   for (;;) {
-    const int64_t item = next_item(queue, &s_item);
+    const int64_t item = q.take();
     if (item >= n_items) break;
-    const TileOf t = batch_tile<TH>(bd, item);
-    const BatchClip& c = bd.clips[t.clip];
-    const int x = t.x0 + threadIdx.x, y = t.y0 + threadIdx.y;
-    if (x < c.width && y < c.height) {
-      const float* relf = c.rel + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
-      const int64_t pix = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
-                          static_cast<int64_t>(y) * c.width + x;
-      counts[pix] = count_pixel_k<R, K>(c.depth, relf, c.width, c.height, c.n_frames, bd.f0[t.clip] + t.fo, c.w,
-                                        c.tol, c.z_near, x, y);
+    // slot, clip and descriptor are uniform: scalar loads, kept in scalar registers
+    const int slot = item_slot(bd.prefix, bd.n_clips, item);
+    const int clip = bd.order[slot];
+    const BatchClip c = load_clip(bd.clips + clip);
+    const int f0 = bd.f0[clip];
+    const TileOf t = batch_tile<TH>(c, item - bd.prefix[slot]);
+    const int x = t.x0 + threadIdx.x;
+    gp<const float> relf = to_global(static_cast<const float*>(c.rel)) + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+    gp<const uint16_t> depth = to_global(c.depth);
+    const int f = f0 + t.fo;
+    for (int r = 0; r < TH; ++r) {
+      const int y = t.y0 + r;
+      if (x < c.width && y < c.height) {
+        const int64_t pix = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
+                            static_cast<int64_t>(y) * c.width + x;
+        counts[pix] = count_pixel_k<R, K>(depth, relf, c.width, c.height, c.n_frames, f, c.w, c.tol, c.z_near, x, y);
+      }
     }
   }
 }
 
+// The plan arrays come as separate restrict arguments: the kernel's stores then
+// provably miss them, so their loads can go through the scalar cache.
 template <int R, int TH>
-__global__ __launch_bounds__(64 * TH) void k_scatter_batched(BatchDev bd, BatchIo io,
-                                                             unsigned int* __restrict__ queue) {
-  __shared__ ScatterLds<R> lds[TH];
-  __shared__ unsigned int s_item;
-  const int64_t n_items = bd.prefix[bd.n_clips];
+__global__ __launch_bounds__(256) void k_scatter_batched(const BatchClip* __restrict__ clips,
+                                                         const int* __restrict__ f0s, const int* __restrict__ order,
+                                                         const int64_t* __restrict__ prefix, int n_clips,
+                                                         const int64_t* __restrict__ offsets,
+                                                         uint32_t* __restrict__ ids, uint2* __restrict__ crho,
+                                                         int64_t capacity, uint32_t* __restrict__ status,
+                                                         unsigned int* __restrict__ queue) {
+  __shared__ ScatterLds<R> lds[4];
+  const int64_t n_items = prefix[n_clips];
+  ItemQueue q(queue);
   for (;;) {
-    const int64_t item = next_item(queue, &s_item);
+    const int64_t item = q.take();
     if (item >= n_items) break;
-    const TileOf t = batch_tile<TH>(bd, item);
-    const BatchClip& c = bd.clips[t.clip];
-    const int y = t.y0 + threadIdx.y;
-    const float* relf = c.rel + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
-    const int64_t pix0 = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
-                         static_cast<int64_t>(y) * c.width + t.x0;
-    scatter_wave<R>(reinterpret_cast<const uint2*>(c.rgbd), c.depth, relf, c.width, c.height, c.n_frames,
-                    bd.f0[t.clip] + t.fo, c.w, c.tol, c.z_near, t.x0, y, pix0, io.offsets, io.ids,
-                    reinterpret_cast<uint2*>(io.crho), io.capacity, io.status, lds[threadIdx.y]);
+    const int slot = item_slot(prefix, n_clips, item);
+    const int clip = order[slot];
+    const BatchClip c = clips[clip];
+    const int f0 = f0s[clip];
+    const TileOf t = batch_tile<TH>(c, item - prefix[slot]);
+    gp<const float> relf = to_global(static_cast<const float*>(c.rel)) + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+    gp<const uint2> rgbd = to_global(reinterpret_cast<const uint2*>(c.rgbd));
+    gp<const uint16_t> depth = to_global(c.depth);
+    const int f = f0 + t.fo;
+    for (int r = 0; r < TH; ++r) {
+      const int y = t.y0 + r;
+      if (y >= c.height) break;  // uniform over the wave
+      const int64_t pix0 = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
+                           static_cast<int64_t>(y) * c.width + t.x0;
+      scatter_wave<R>(rgbd, depth, relf, c.width, c.height, c.n_frames, f, c.w, c.tol, c.z_near, t.x0, y, pix0,
+                      to_global(offsets), to_global(ids), to_global(crho), capacity, to_global(status),
+                      lds[threadIdx.y]);
+    }
   }
 }
 
-constexpr int kBatchFilterPix = 256;  // CSR pixels per filter work item (16 per pass of a workgroup)
+constexpr int kBatchFilterPix = 64;  // CSR pixels per filter work item (4 per pass of a wave)
 
+// Filter items are runs of 64 pixels of one clip (fprefix: first item of each clip).
 template <bool kColour, bool kTime>
-__global__ __launch_bounds__(256) void k_filter_batched(BatchDev bd, BatchIo io, int64_t n_pix,
+__global__ __launch_bounds__(256) void k_filter_batched(BatchDev bd, BatchIo io, const int64_t* __restrict__ fprefix,
                                                         unsigned int* __restrict__ queue) {
-  __shared__ unsigned int s_item;
   const int g = threadIdx.x / kGroup, lane = threadIdx.x % kGroup;
+  const int64_t n_items = fprefix[bd.n_clips];
+  ItemQueue q(queue);
   for (;;) {
-    const int64_t item = next_item(queue, &s_item);
-    const int64_t first = item * kBatchFilterPix;
-    if (first >= n_pix) break;
-    for (int r = 0; r < kBatchFilterPix; r += 256 / kGroup) {
-      const int64_t pix = first + r + g;
-      const bool live = pix < n_pix;
-      int c = 0;
-      if (live) c = item_slot(bd.pix_prefix, bd.n_clips, pix);
-      const BatchClip& cl = bd.clips[c];
-      const int64_t plane = static_cast<int64_t>(cl.width) * cl.height;
-      const int64_t local = live ? pix - cl.pix_base : 0;
-      const int fo = static_cast<int>(local / plane);
-      filter_group<kColour, kTime>(reinterpret_cast<const uint2*>(cl.rgbd), cl.width, cl.height,
-                                   bd.f0[c] + fo, cl.w, live, local - fo * plane, pix, lane, io.offsets, io.ids,
-                                   reinterpret_cast<const uint2*>(io.crho), io.capacity, cl.a_d,
-                                   kColour ? cl.a_c : 0.0f, kTime ? cl.a_t : 0.0f, io.out);
+    const int64_t item = q.take();
+    if (item >= n_items) break;
+    const int c = item_slot(fprefix, bd.n_clips, item);
+    const BatchClip cl = load_clip(bd.clips + c);
+    const int f0 = bd.f0[c];
+    gp<const uint2> rgbd = to_global(reinterpret_cast<const uint2*>(cl.rgbd));
+    const int64_t plane = static_cast<int64_t>(cl.width) * cl.height;
+    const int64_t n_clip = plane * cl.n_out;
+    const int64_t first = (item - fprefix[c]) * kBatchFilterPix;
+    for (int r = 0; r < kBatchFilterPix; r += 64 / kGroup) {
+      const int64_t local = first + r + g;
+      const bool live = local < n_clip;
+      const int fo = live ? static_cast<int>(local / plane) : 0;
+      filter_group<kColour, kTime>(rgbd, cl.width, cl.height, f0 + fo, cl.w, live, local - fo * plane,
+                                   cl.pix_base + local, lane, to_global(static_cast<const int64_t*>(io.offsets)),
+                                   to_global(static_cast<const uint32_t*>(io.ids)),
+                                   to_global(reinterpret_cast<const uint2*>(io.crho)), io.capacity, cl.a_d,
+                                   kColour ? cl.a_c : 0.0f, kTime ? cl.a_t : 0.0f, to_global(io.out));
     }
   }
 }
@@ -930,7 +985,7 @@ hipError_t launch_batch_prep(const BatchDev& bd, unsigned int* queues, uint32_t*
 template <int R, int TH>
 static void count_batched_k(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* q,
                             hipStream_t st) {
-  const dim3 g(static_cast<unsigned>(bl.blocks_count)), b(kTileW, TH);
+  const dim3 g(static_cast<unsigned>(bl.blocks_count)), b(kTileW, 4);
   switch (bl.k_count) {
     case 1: hipLaunchKernelGGL((k_count_batched<R, TH, 1>), g, b, 0, st, bd, io.offsets + 1, q); break;
     case 2: hipLaunchKernelGGL((k_count_batched<R, TH, 2>), g, b, 0, st, bd, io.offsets + 1, q); break;
@@ -960,13 +1015,6 @@ hipError_t launch_batch_count(const BatchDev& bd, const BatchIo& io, const Batch
   return hipGetLastError();
 }
 
-// largest scatter tile height (waves per workgroup) whose LDS fits 160 KB
-template <int R>
-constexpr int scatter_max_th() {
-  constexpr size_t b = sizeof(ScatterLds<R>) + 16;
-  return b * 8 <= 163840 ? 8 : (b * 4 <= 163840 ? 4 : (b * 2 <= 163840 ? 2 : 1));
-}
-
 size_t batch_scatter_lds_bytes(int radius) {
   switch (radius) {
     case 0: return sizeof(ScatterLds<0>);
@@ -976,32 +1024,23 @@ size_t batch_scatter_lds_bytes(int radius) {
   }
 }
 
-int batch_scatter_max_th(int radius) {
-  switch (radius) {
-    case 0: return scatter_max_th<0>();
-    case 1: return scatter_max_th<1>();
-    case 2: return scatter_max_th<2>();
-    default: return scatter_max_th<3>();
-  }
-}
-
-template <int R, int TH>
-static void scatter_batched_th(const BatchDev& bd, const BatchIo& io, dim3 g, unsigned int* q, hipStream_t st) {
-  if constexpr (TH <= scatter_max_th<R>())
-    hipLaunchKernelGGL((k_scatter_batched<R, TH>), g, dim3(kTileW, TH), 0, st, bd, io, q);
-}
+// every rows-per-item value fits: LDS holds the workgroup's 4 waves' buffers
+int batch_scatter_max_th(int) { return 8; }
 
 template <int R>
 static void scatter_batched_r(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* q,
                               hipStream_t st) {
-  const dim3 g(static_cast<unsigned>(bl.blocks_scatter));
-  const int th = bl.th_scatter < scatter_max_th<R>() ? bl.th_scatter : scatter_max_th<R>();
-  switch (th) {
-    case 1: scatter_batched_th<R, 1>(bd, io, g, q, st); break;
-    case 2: scatter_batched_th<R, 2>(bd, io, g, q, st); break;
-    case 4: scatter_batched_th<R, 4>(bd, io, g, q, st); break;
-    default: scatter_batched_th<R, 8>(bd, io, g, q, st); break;
+  const dim3 g(static_cast<unsigned>(bl.blocks_scatter)), b(kTileW, 4);
+#define SG_SCATTER_BATCHED(TH) \
+  hipLaunchKernelGGL((k_scatter_batched<R, TH>), g, b, 0, st, bd.clips, bd.f0, bd.order, bd.prefix, bd.n_clips, \
+                     io.offsets, io.ids, reinterpret_cast<uint2*>(io.crho), io.capacity, io.status, q)
+  switch (bl.th_scatter) {
+    case 1: SG_SCATTER_BATCHED(1); break;
+    case 2: SG_SCATTER_BATCHED(2); break;
+    case 4: SG_SCATTER_BATCHED(4); break;
+    default: SG_SCATTER_BATCHED(8); break;
   }
+#undef SG_SCATTER_BATCHED
 }
 
 hipError_t launch_batch_scatter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, unsigned int* queue,
@@ -1015,18 +1054,20 @@ hipError_t launch_batch_scatter(const BatchDev& bd, const BatchIo& io, const Bat
   return hipGetLastError();
 }
 
-hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl, int64_t n_pix,
-                               unsigned int* queue, hipStream_t st) {
-  const dim3 g(static_cast<unsigned>(bl.blocks_filter));
+hipError_t launch_batch_filter(const BatchDev& bd, const BatchIo& io, const BatchLaunch& bl,
+                               const int64_t* fprefix, unsigned int* queue, hipStream_t st) {
+  const dim3 g(static_cast<unsigned>(bl.blocks_filter)), b(64, 4);
   if (bl.colour && bl.time)
-    hipLaunchKernelGGL((k_filter_batched<true, true>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+    hipLaunchKernelGGL((k_filter_batched<true, true>), g, b, 0, st, bd, io, fprefix, queue);
   else if (bl.colour)
-    hipLaunchKernelGGL((k_filter_batched<true, false>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+    hipLaunchKernelGGL((k_filter_batched<true, false>), g, b, 0, st, bd, io, fprefix, queue);
   else if (bl.time)
-    hipLaunchKernelGGL((k_filter_batched<false, true>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+    hipLaunchKernelGGL((k_filter_batched<false, true>), g, b, 0, st, bd, io, fprefix, queue);
   else
-    hipLaunchKernelGGL((k_filter_batched<false, false>), g, dim3(256), 0, st, bd, io, n_pix, queue);
+    hipLaunchKernelGGL((k_filter_batched<false, false>), g, b, 0, st, bd, io, fprefix, queue);
   return hipGetLastError();
 }
+
+int64_t batch_filter_items(int64_t clip_pixels) { return (clip_pixels + kBatchFilterPix - 1) / kBatchFilterPix; }
 
 }  // namespace sg

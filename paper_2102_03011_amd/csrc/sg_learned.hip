@@ -140,8 +140,8 @@ struct PixelCtx {
 };
 
 struct FeatureArgs {
-  const float* rel;        // relative maps of this output frame, [2w+1][kRelStride]
-  const uint16_t* depth;   // stored depth planes
+  gp<const float> rel;        // relative maps of this output frame, [2w+1][kRelStride]
+  gp<const uint16_t> depth;   // stored depth planes
   int width, height, n_frames, pw, w;
   size_t pplane;
   float inv_w, fx, fy, cx, cy;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   int qx = q - qy * a.width;
   if (qx < 0) { --qy; qx += a.width; }
   if (qx >= a.width) { ++qy; qx -= a.width; }
-  const float* m = a.rel + slot * kRelStride;
+  gp<const float> m = a.rel + slot * kRelStride;
   const float a0 = fmaf(m[0], px.x, fmaf(m[1], px.y, m[2]));
   const float a1 = fmaf(m[3], px.x, fmaf(m[4], px.y, m[5]));
   const float a2 = fmaf(m[6], px.x, fmaf(m[7], px.y, m[8]));
@@ -186,7 +186,7 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   const float ux = ax * ra - bx * rb, uy = ay * ra - by * rb, uz = az * ra - bz * rb;
   const float one_minus_cos = 0.5f * (ux * ux + uy * uy + uz * uz);
   // depth gradient at q in J (apron neighbours read as invalid)
-  const uint16_t* dq = a.depth + static_cast<size_t>(j) * a.pplane + padded_index(qx, qy, a.pw);
+  gp<const uint16_t> dq = a.depth + static_cast<size_t>(j) * a.pplane + padded_index(qx, qy, a.pw);
   const float d0 = h2f(dq[0]);
   const float dxp = h2f(dq[1]), dxm = h2f(dq[-1]), dyp = h2f(dq[a.pw]), dym = h2f(dq[-a.pw]);
   float gx = 0.0f, gy = 0.0f;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
 // by binary search on binary16 bit patterns (colours are non-negative, so the
 // patterns order like the values). Lanes lane0 .. lane0 + width - 1 cooperate.
 template <int kWidth>
-__device__ __forceinline__ void set_median(const uint2* __restrict__ crho, int64_t s, int64_t e, int sub,
+__device__ __forceinline__ void set_median(gp<const uint2> crho, int64_t s, int64_t e, int sub,
                                            float& mr, float& mg, float& mb) {
   const int64_t n = e - s;
   mr = mg = mb = 0.0f;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void set_median(const uint2* __restrict__ crho, int64
     for (int c = 0; c < 3; ++c) mid[c] = (lo[c] + hi[c]) >> 1;
     int cnt[3] = {0, 0, 0};
     for (int64_t i = s + sub; i < e; i += kWidth) {
-      const uint2 r = crho[i];
+      const uint2 r = ld2(crho + i);
       cnt[0] += (r.x & 0xFFFFu) <= mid[0];
       cnt[1] += (r.x >> 16) <= mid[1];
       cnt[2] += (r.y & 0xFFFFu) <= mid[2];
@@ -250,7 +250,7 @@ constexpr int kFlatPix = 16;  // output pixels per wave of the learned filter
 // staged codes c / 255 (binary16 bits code[c], increasing in c): binary search over
 // c, 8 steps. Lanes sub = 0 .. kWidth - 1 cooperate.
 template <int kWidth>
-__device__ __forceinline__ void set_median_codes(const uint2* __restrict__ crho, int64_t s, int64_t e, int sub,
+__device__ __forceinline__ void set_median_codes(gp<const uint2> crho, int64_t s, int64_t e, int sub,
                                                  const uint16_t* __restrict__ code, float* med) {
   const int64_t n = e - s;
   med[0] = med[1] = med[2] = 0.0f;
@@ -263,7 +263,7 @@ __device__ __forceinline__ void set_median_codes(const uint2* __restrict__ crho,
 #pragma unroll
     for (int c = 0; c < 3; ++c) t[c] = code[(lo[c] + hi[c]) >> 1];
     for (int64_t i = s + sub; i < e; i += kWidth) {
-      const uint2 r = crho[i];
+      const uint2 r = ld2(crho + i);
       cnt[0] += (r.x & 0xFFFFu) <= t[0];
       cnt[1] += (r.x >> 16) <= t[1];
       cnt[2] += (r.y & 0xFFFFu) <= t[2];
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
       const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
       q.f = f0 + q.fo;
       const size_t pi = static_cast<size_t>(q.f) * pplane + padded_index(x, y, pw);
-      const uint2 ref = rgbd[pi];
+      const uint2 ref = ld2(to_global(rgbd) + pi);
       q.cref[0] = h2f(ref.x);
       q.cref[1] = h2f(ref.x >> 16);
       q.cref[2] = h2f(ref.y);
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
     const int k = 4 * r + lane / 16;
     const bool ok = k <= last;
     float med[3];
-    set_median_codes<16>(crho, ok ? px[k].s : 0, ok ? px[k].e : 0, lane % 16, s_code, med);
+    set_median_codes<16>(to_global(crho), ok ? px[k].s : 0, ok ? px[k].e : 0, lane % 16, s_code, med);
     if (ok && lane % 16 == 0) {
       px[k].med[0] = med[0];
       px[k].med[1] = med[1];
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   wave_lds_fence_l();
 
   FeatureArgs fa;
-  fa.depth = depth;
+  fa.depth = to_global(depth);
   fa.width = width;
   fa.height = height;
   fa.n_frames = n_frames;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
       const uint32_t id = ids[idx];
       live = id_in_clip(fa, q.f, id);
       if (live) {
-        rec = crho[idx];
+        rec = ld2(to_global(crho) + idx);
         PixelCtx pc;
         pc.x = q.x;
         pc.y = q.y;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
         pc.medb = q.med[2];
         pc.x7 = q.x7;
         FeatureArgs fk = fa;
-        fk.rel = rel + static_cast<size_t>(q.fo) * (2 * w + 1) * kRelStride;
+        fk.rel = to_global(rel) + static_cast<size_t>(q.fo) * (2 * w + 1) * kRelStride;
         sample_features(fk, pc, id, rec, feat);
       }
     }
@@ -640,7 +640,63 @@ __device__ __forceinline__ float forward_sample(const float* xs, const float* s_
   return m;
 }
 
-__global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
+// The kernels' view of TrainArgs: every pointer in the global address space
+// (pointers inside a by-value argument struct are otherwise generic).
+struct TrainDev {
+  gp<const uint2> rgbd;
+  gp<const uint16_t> depth;
+  gp<const float> rel;
+  int width, height, n_frames, f0, w;
+  float log_norm, fx, fy, cx, cy;
+  gp<const int64_t> offsets;
+  gp<const uint32_t> ids;
+  gp<const uint2> crho;
+  int64_t capacity, n_all;
+  gp<const int32_t> pixel_idx;
+  int n_pix;
+  gp<const float> clean;
+  gp<const uint16_t> mw;
+  gp<const float> mb;
+  gp<float> grad;
+  gp<float> loss;
+};
+
+__device__ __forceinline__ TrainDev dev_args(const TrainArgs& a) {
+  TrainDev d;
+  d.rgbd = to_global(a.rgbd);
+  d.depth = to_global(a.depth);
+  d.rel = to_global(a.rel);
+  d.width = a.width;
+  d.height = a.height;
+  d.n_frames = a.n_frames;
+  d.f0 = a.f0;
+  d.w = a.w;
+  d.log_norm = a.log_norm;
+  d.fx = a.fx;
+  d.fy = a.fy;
+  d.cx = a.cx;
+  d.cy = a.cy;
+  d.offsets = to_global(a.offsets);
+  d.ids = to_global(a.ids);
+  d.crho = to_global(a.crho);
+  d.capacity = a.capacity;
+  d.n_all = a.n_all;
+  d.pixel_idx = to_global(a.pixel_idx);
+  d.n_pix = a.n_pix;
+  d.clean = to_global(a.clean);
+  d.mw = to_global(a.mw);
+  d.mb = to_global(a.mb);
+  d.grad = to_global(a.grad);
+  d.loss = to_global(a.loss);
+  return d;
+}
+
+__device__ __forceinline__ void add_f32(gp<float> p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
+  const TrainDev ta = dev_args(ta_in);
   __shared__ float s_w1[kNF * kNH];
   __shared__ float s_w2[kNH * kNH];
   __shared__ float s_w3[kNH];
@@ -708,7 +764,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
     for (int64_t idx = s + lane; idx < e; idx += 64) {
       const uint32_t id = ta.ids[idx];
       if (!id_in_clip(fa, px.f, id)) continue;
-      const uint2 rec = ta.crho[idx];
+      const uint2 rec = ld2(ta.crho + idx);
       float feat[kNF], xs[kNF];
       sample_features(fa, px, id, rec, feat);
 #pragma unroll
@@ -745,7 +801,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
       l2 = fmaf(d, d, l2);
       dO[c] = 2.0f * d * inv3n;
     }
-    if (lane == 0) atomicAdd(ta.loss, l2 * inv3n);
+    if (lane == 0) add_f32(ta.loss, l2 * inv3n);
 
     // pass 2: backward, 64 samples per chunk
     for (int64_t base = s; base < e; base += 64) {
@@ -754,7 +810,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
       float xs[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float dm = 0.f;
       if (live) {
-        const uint2 rec = ta.crho[idx];
+        const uint2 rec = ld2(ta.crho + idx);
         float feat[kNF];
         sample_features(fa, px, ta.ids[idx], rec, feat);
 #pragma unroll
@@ -806,13 +862,13 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta) {
   }
   // master order: W1 [8][64], W2 [64][64], W3 [64], b1 [64], b2 [64], b3
 #pragma unroll
-  for (int j = 0; j < kNH; ++j) atomicAdd(&ta.grad[kOffW2 + lane * kNH + j], gw2[j]);
+  for (int j = 0; j < kNH; ++j) add_f32(ta.grad + (kOffW2 + lane * kNH + j), gw2[j]);
 #pragma unroll
-  for (int jj = 0; jj < 8; ++jj) atomicAdd(&ta.grad[(lane / 8) * kNH + 8 * (lane % 8) + jj], gw1[jj]);
-  atomicAdd(&ta.grad[kOffW3 + lane], gw3);
-  atomicAdd(&ta.grad[SG_MLP_NW + lane], gb1);
-  atomicAdd(&ta.grad[SG_MLP_NW + kNH + lane], gb2);
-  if (lane == 0) atomicAdd(&ta.grad[SG_MLP_NW + 2 * kNH], gb3);
+  for (int jj = 0; jj < 8; ++jj) add_f32(ta.grad + ((lane / 8) * kNH + 8 * (lane % 8) + jj), gw1[jj]);
+  add_f32(ta.grad + (kOffW3 + lane), gw3);
+  add_f32(ta.grad + (SG_MLP_NW + lane), gb1);
+  add_f32(ta.grad + (SG_MLP_NW + kNH + lane), gb2);
+  if (lane == 0) add_f32(ta.grad + (SG_MLP_NW + 2 * kNH), gb3);
 }
 
 __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ master, float* __restrict__ mm,
@@ -840,7 +896,8 @@ __global__ void k_clear1(float* p) {
 // Feature statistics for the standardisation: adds, over the records of the
 // minibatch pixels, the record count, sum x_k and sum x_k^2 of the raw features
 // into moments[0], [1 + k], [9 + k] (float64). One wave per pixel.
-__global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta, double* __restrict__ moments) {
+__global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta_in, double* __restrict__ moments) {
+  const TrainDev ta = dev_args(ta_in);
   const int lane = threadIdx.x;
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
   const int pw = stored_pitch(ta.width);
@@ -882,7 +939,7 @@ __global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta, double* __
       const uint32_t id = ta.ids[idx];
       if (!id_in_clip(fa, px.f, id)) continue;
       float feat[kNF];
-      sample_features(fa, px, id, ta.crho[idx], feat);
+      sample_features(fa, px, id, ld2(ta.crho + idx), feat);
       cnt += 1.0;
 #pragma unroll
       for (int k = 0; k < kNF; ++k) {
