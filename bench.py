@@ -326,6 +326,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=300, help="clip length (the workload uses 300)")
+    ap.add_argument("--chunk-rays", type=int, default=1 << 20,
+                    help="rays per generation launch (larger = fewer launches, e.g. under a counter profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-row-step", type=int, default=16)
     ap.add_argument("--workload", choices=("full", "batched"), default="full",
@@ -350,7 +352,7 @@ def main() -> int:
     dev = torch.device("cuda:0")
     wl = configs.full_scale(n_frames=args.frames)
     t0 = time.perf_counter()
-    clip = generate(wl.spec, device=dev, chunk_rays=1 << 20)
+    clip = generate(wl.spec, device=dev, chunk_rays=args.chunk_rays)
     torch.cuda.synchronize()
     log(f"generated {wl.name} in {time.perf_counter() - t0:.1f} s")
     n, h, w = clip.n_frames, clip.height, clip.width

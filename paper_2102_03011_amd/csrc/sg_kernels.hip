@@ -634,8 +634,7 @@ __device__ __forceinline__ void filter_group(gp<const uint2> rgbd, int width, in
   const bool bad = live && (s < 0 || e < s || e > capacity);
   if (bad) s = e = 0;
   float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
-  for (int64_t i = s + lane; i < e; i += kGroup) {
-    const uint2 rec = ld2(crho + i);
+  auto accumulate = [&](uint2 rec, uint32_t id) {
     const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y), rho = h2f(rec.y >> 16);
     float arg = a_d * rho * rho;
     if (kColour) {
@@ -643,7 +642,7 @@ __device__ __forceinline__ void filter_group(gp<const uint2> rgbd, int width, in
       arg = fmaf(a_c, fmaf(dr, dr, fmaf(dg, dg, db * db)), arg);
     }
     if (kTime) {
-      const float dj = static_cast<float>(static_cast<int>(ids[i] >> SG_ID_SHIFT) - w);
+      const float dj = static_cast<float>(static_cast<int>(id >> SG_ID_SHIFT) - w);
       arg = fmaf(a_t, dj * dj, arg);
     }
     const float wt = __builtin_amdgcn_exp2f(arg);
@@ -651,7 +650,21 @@ __device__ __forceinline__ void filter_group(gp<const uint2> rgbd, int width, in
     ar = fmaf(wt, r, ar);
     ag = fmaf(wt, g, ag);
     ab = fmaf(wt, b, ab);
+  };
+  // four records per lane in flight; each lane still adds its records in order
+  int64_t i = s + lane;
+  for (; i + 3 * kGroup < e; i += 4 * kGroup) {
+    uint2 rec[4];
+    uint32_t id[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rec[k] = ld2(crho + i + k * kGroup);
+      if (kTime) id[k] = ids[i + k * kGroup];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accumulate(rec[k], id[k]);
   }
+  for (; i < e; i += kGroup) accumulate(ld2(crho + i), kTime ? ids[i] : 0u);
 #pragma unroll
   for (int off = kGroup / 2; off > 0; off >>= 1) {
     wsum += __shfl_xor(wsum, off, kGroup);
