@@ -330,24 +330,23 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
 // stored (r, g, b, depth) pixels in one round trip, decides membership from the
 // depth channel exactly as pass 1 does from the depth plane (same binary16 bits,
 // same test), and appends its accepted records to a per-lane buffer in LDS
-// (kSlots entries, odd stride: conflict-free appends). When some lane's buffer
-// could overflow on the next source frame, the wave flushes every lane holding at
-// least kMinRun records: a group of kRunLanes lanes writes each flushed lane's
-// run, so a store instruction writes 64 / kRunLanes contiguous runs instead of 64
-// scattered 8-byte pieces. Records reach global memory in the order they are
-// found, which is the canonical order.
+// (kSlots entries, odd stride: conflict-free appends). A lane whose buffer cannot
+// take the records of the current source frame writes out what it holds before
+// appending them; the wave does these flushes together: a group of kRunLanes lanes
+// writes each flushing lane's run, so a store instruction writes 64 / kRunLanes
+// contiguous runs instead of 64 scattered 8-byte pieces. Flushing only lanes that
+// must keeps the runs long (whole cache lines more often). Records reach global
+// memory in the order they are found, which is the canonical order.
 
 template <int R>
 struct ScatterShape {
   static constexpr int kCand = (2 * R + 1) * (2 * R + 1);
-  // Odd number of slots per lane (LDS: 12 B per slot, 256 lanes per workgroup).
-  // A flush is triggered when some lane has fewer than kCand free slots and empties
-  // every lane holding >= kMinRun records, so afterwards each lane has room for a
-  // whole block again: kMinRun - 1 <= kSlots - kCand.
+  // Odd number of slots per lane (LDS: 12 B per slot, 256 lanes per workgroup; at
+  // R = 1, 15 slots is the most that keeps three workgroups on a compute unit). An
+  // emptied buffer must take a whole block: kCand <= kSlots.
   static constexpr int kSlots = R == 3 ? 51 : (R == 2 ? 41 : 15);
-  static constexpr int kMinRun = R == 3 ? 2 : (R == 2 ? 12 : 7);
   static constexpr int kRunLanes = kSlots <= 16 ? 16 : 64;  // lanes writing one run
-  static_assert(kMinRun - 1 <= kSlots - kCand, "flush must leave room for one block");
+  static_assert(kCand <= kSlots, "an empty buffer takes one block");
   static_assert((kSlots & 1) == 1, "odd stride keeps LDS accesses conflict-free");
   static_assert(kSlots <= kRunLanes, "a run fits its lane group");
   using Mask = typename std::conditional<(kCand > 32), uint64_t, uint32_t>::type;
@@ -452,14 +451,15 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
   uint32_t* my_id = s_id + lane * kSlots;
   for (int j = jlo; j <= jhi; ++j) {
     Projected p;
+    uint2 px[kSide][kSide];
+    Mask mask = 0;
+    int kept = 0;
     if (active && project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) {
       gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
-      uint2 px[kSide][kSide];
 #pragma unroll
       for (int dy = 0; dy < kSide; ++dy)
 #pragma unroll
         for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (dy - R) * pw + (dx - R));
-      Mask mask = 0;
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k)
         mask |= static_cast<Mask>(accept16(px[k / kSide][k % kSide].y >> 16, p) ? 1 : 0) << k;
@@ -468,7 +468,7 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
       found += n;
       // keep only as many records as the segment has room for (fewer only when
       // the planes changed since the count pass; flagged at the end)
-      int kept = n;
+      kept = n;
       const int64_t room = end - cur - fill;
       if (n > room) {
         Mask keep = 0;
@@ -481,6 +481,12 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
         mask = keep;
         kept = static_cast<int>(room);
       }
+    }
+    // a lane whose buffer cannot take this frame's records writes out what it holds
+    // first; the others keep theirs, so every flushed run is as long as it can be
+    if (__any(fill + kept > kSlots))
+      flush_runs<R>(fill + kept > kSlots ? fill : 0, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
+    if (kept > 0) {
       // id = ((J - f + w) << 22) | q; q < 2^22, so the OR is an add of a
       // per-(p, J) base and a per-candidate constant
       const uint32_t id0 = (static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT) +
@@ -500,8 +506,6 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
       }
       fill += kept;
     }
-    if (__any(fill > kSlots - Shape::kCand))
-      flush_runs<R>(fill >= Shape::kMinRun ? fill : 0, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
   }
   if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
   if (active && found != end - start) flag_or(status, SG_FLAG_INCONSISTENT);
