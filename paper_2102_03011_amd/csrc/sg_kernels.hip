@@ -330,23 +330,31 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
 // stored (r, g, b, depth) pixels in one round trip, decides membership from the
 // depth channel exactly as pass 1 does from the depth plane (same binary16 bits,
 // same test), and appends its accepted records to a per-lane buffer in LDS
-// (kSlots entries, odd stride: conflict-free appends). A lane whose buffer cannot
-// take the records of the current source frame writes out what it holds before
-// appending them; the wave does these flushes together: a group of kRunLanes lanes
+// (kSlots entries of three words: colour + rho, id; odd stride: conflict-free
+// appends). The append is branch-free: every candidate of the block is written to
+// the lane's next free slot, and the slot pointer advances only past the accepted
+// ones, so a rejected candidate's write is overwritten by the next accepted one or
+// lands in the slot after the last record (one slot per lane is kept free for it).
+// A lane whose buffer cannot take the records of the current source frame writes
+// out what it holds before appending them; the wave does these flushes together: a group of kRunLanes lanes
 // writes each flushing lane's run, so a store instruction writes 64 / kRunLanes
 // contiguous runs instead of 64 scattered 8-byte pieces. Flushing only lanes that
 // must keeps the runs long (whole cache lines more often). Records reach global
 // memory in the order they are found, which is the canonical order.
 
+using half2v = _Float16 __attribute__((ext_vector_type(2)));
+
 template <int R>
 struct ScatterShape {
   static constexpr int kCand = (2 * R + 1) * (2 * R + 1);
   // Odd number of slots per lane (LDS: 12 B per slot, 256 lanes per workgroup; at
-  // R = 1, 15 slots is the most that keeps three workgroups on a compute unit). An
-  // emptied buffer must take a whole block: kCand <= kSlots.
+  // R = 1, 15 slots is the most that keeps three workgroups on a compute unit). The
+  // last slot takes the writes of rejected candidates, so a lane holds at most
+  // kSlots - 1 records, and an emptied buffer must take a whole block.
   static constexpr int kSlots = R == 3 ? 51 : (R == 2 ? 41 : 15);
+  static constexpr int kCap = kSlots - 1;                    // records a lane holds
   static constexpr int kRunLanes = kSlots <= 16 ? 16 : 64;  // lanes writing one run
-  static_assert(kCand <= kSlots, "an empty buffer takes one block");
+  static_assert(kCand <= kCap, "an empty buffer takes one block");
   static_assert((kSlots & 1) == 1, "odd stride keeps LDS accesses conflict-free");
   static_assert(kSlots <= kRunLanes, "a run fits its lane group");
   using Mask = typename std::conditional<(kCand > 32), uint64_t, uint32_t>::type;
@@ -363,9 +371,8 @@ __device__ __forceinline__ void wave_lds_fence() {
 // group of kRunLanes lanes writes one list entry's run, so the store instructions
 // stay dense however few lanes flush.
 template <int R>
-__device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const uint2* s_rec,
-                                           const uint32_t* s_id, int* s_n, int64_t* s_dst,
-                                           gp<uint32_t> ids, gp<uint2> crho) {
+__device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const uint32_t* s_buf, int* s_n,
+                                           int64_t* s_dst, gp<uint32_t> ids, gp<uint2> crho) {
   constexpr int kSlots = ScatterShape<R>::kSlots;
   constexpr int kRun = ScatterShape<R>::kRunLanes;
   constexpr int kPer = 64 / kRun;
@@ -386,8 +393,9 @@ __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const
       const int own = on >> 8, cnt = on & 0xFF;
       if (sub < cnt) {
         const int64_t dst = s_dst[e] + sub;
-        st2(crho + dst, s_rec[own * kSlots + sub]);
-        ids[dst] = s_id[own * kSlots + sub];
+        const uint32_t* slot = s_buf + 3 * (own * kSlots + sub);
+        st2(crho + dst, make_uint2(slot[0], slot[1]));
+        ids[dst] = slot[2];
       }
     }
   }
@@ -399,8 +407,7 @@ __device__ __forceinline__ void flush_runs(int n, int64_t& cur, int& fill, const
 // LDS of one scatter wave
 template <int R>
 struct ScatterLds {
-  uint2 rec[kTileW * ScatterShape<R>::kSlots];
-  uint32_t id[kTileW * ScatterShape<R>::kSlots];
+  uint32_t buf[3 * kTileW * ScatterShape<R>::kSlots];  // per slot: colour + rho (2 words), id
   int n[kTileW];
   int64_t dst[kTileW];
 };
@@ -419,8 +426,7 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
   constexpr int kSlots = Shape::kSlots;
   constexpr int kSide = 2 * R + 1;
   const int lane = threadIdx.x;
-  uint2* s_rec = lds.rec;
-  uint32_t* s_id = lds.id;
+  uint32_t* s_buf = lds.buf;
   int* s_n = lds.n;
   int64_t* s_dst = lds.dst;
   const int x = x0 + lane;
@@ -447,8 +453,11 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
   int found = 0;
   const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
   const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
-  uint2* my_rec = s_rec + lane * kSlots;
-  uint32_t* my_id = s_id + lane * kSlots;
+  uint32_t* my_buf = s_buf + 3 * kSlots * lane;
+  // id of candidate (dy, dx) = id of (0, 0) + dy * width + dx
+  uint32_t cand_off[kSide * kSide];
+#pragma unroll
+  for (int k = 0; k < kSide * kSide; ++k) cand_off[k] = static_cast<uint32_t>((k / kSide) * width + k % kSide);
   for (int j = jlo; j <= jhi; ++j) {
     Projected p;
     uint2 px[kSide][kSide];
@@ -484,30 +493,32 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
     }
     // a lane whose buffer cannot take this frame's records writes out what it holds
     // first; the others keep theirs, so every flushed run is as long as it can be
-    if (__any(fill + kept > kSlots))
-      flush_runs<R>(fill + kept > kSlots ? fill : 0, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
+    if (__any(fill + kept > Shape::kCap))
+      flush_runs<R>(fill + kept > Shape::kCap ? fill : 0, cur, fill, s_buf, s_n, s_dst, ids, crho);
     if (kept > 0) {
       // id = ((J - f + w) << 22) | q; q < 2^22, so the OR is an add of a
       // per-(p, J) base and a per-candidate constant
       const uint32_t id0 = (static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT) +
                            static_cast<uint32_t>((p.iv - R) * width + (p.iu - R));
-      uint2* rec = my_rec + fill;
-      uint32_t* idp = my_id + fill;
+      // slots fill .. fill + kept - 1 take the accepted candidates in block order;
+      // every write stays below slot fill + kept <= kCap (the spare slot)
+      uint32_t* slot = my_buf + 3 * fill;
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k) {
-        if ((mask >> k) & 1) {
-          const int dy = k / kSide, dx = k % kSide;
-          const uint2 v = px[dy][dx];
-          // rho = (d - z) / z = d * (1 / z) - 1, d = the record's own stored depth
-          const float rho = fmaf(h2f(v.y >> 16), p.inv, -1.0f);
-          *rec++ = make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16));
-          *idp++ = id0 + static_cast<uint32_t>(dy * width + dx);
-        }
+        const uint2 v = px[k / kSide][k % kSide];
+        // (b, d) -> (b, rho): rho = (d - z) / z = d * (1 / z) - 1 in float32, rounded
+        // to nearest binary16 in place of the record's own stored depth d
+        half2v bd = __builtin_bit_cast(half2v, v.y);
+        bd.y = static_cast<_Float16>(fmaf(static_cast<float>(bd.y), p.inv, -1.0f));
+        slot[0] = v.x;
+        slot[1] = __builtin_bit_cast(uint32_t, bd);
+        slot[2] = id0 + cand_off[k];
+        slot += 3 * __builtin_amdgcn_ubfe(static_cast<uint32_t>(mask >> k), 0, 1);
       }
       fill += kept;
     }
   }
-  if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_rec, s_id, s_n, s_dst, ids, crho);
+  if (__any(fill > 0)) flush_runs<R>(fill, cur, fill, s_buf, s_n, s_dst, ids, crho);
   if (active && found != end - start) flag_or(status, SG_FLAG_INCONSISTENT);
 }
 
