@@ -282,11 +282,16 @@ __device__ __forceinline__ void set_median_codes(gp<const uint2> crho, int64_t s
   for (int c = 0; c < 3; ++c) med[c] = h2f(code[lo[c]]);
 }
 
+// A operands of the matrix products in LDS, one 16-byte entry per lane: entries
+// 0, 1 = layer 1 tiles, 2 + 4 t2 + s = layer 2 output tile t2, K-step s.
+constexpr int kAOps = 10;
+
 // The MLP on the wave's 64 samples (features staged in xs[0] (hi) / xs[1] (lo),
 // one uint4 per sample): returns the logit of the lane's own sample.
-__device__ __forceinline__ float mlp_logits_64(const bf16x8 (&a1)[2], const bf16x8 (&a2)[2][4],
-                                               const uint4* xs_hi, const uint4* xs_lo, const float* s_bh,
-                                               const float* s_w3, float b3, int hi32, int col) {
+__device__ __forceinline__ float mlp_logits_64(const u32x4 (*s_a)[64], const uint4* xs_hi, const uint4* xs_lo,
+                                               const float* s_bh, const float* s_w3, float b3, int hi32,
+                                               int col) {
+  const int lane = 32 * hi32 + col;
   float m_own = 0.0f;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -301,7 +306,7 @@ __device__ __forceinline__ float mlp_logits_64(const bf16x8 (&a1)[2], const bf16
       v16f c;
 #pragma unroll
       for (int a = 0; a < 16; ++a) c[a] = s_bh[32 * t + 8 * (a / 4) + 4 * hi32 + a % 4];
-      const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[t], bx, c, 0, 0, 0);
+      const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s_a[t][lane]), bx, c, 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < 8; ++p) split_pack(gelu_half(d[2 * p]), gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
     }
@@ -317,8 +322,9 @@ __device__ __forceinline__ float mlp_logits_64(const bf16x8 (&a1)[2], const bf16
         const int t = st / 2, p0 = 4 * (st % 2);
         const u32x4 bh = {ph[t][p0], ph[t][p0 + 1], ph[t][p0 + 2], ph[t][p0 + 3]};
         const u32x4 bl = {pl[t][p0], pl[t][p0 + 1], pl[t][p0 + 2], pl[t][p0 + 3]};
-        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bh), d, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t2][st], as_bf16x8(bl), d, 0, 0, 0);
+        const bf16x8 a2 = as_bf16x8(s_a[2 + 4 * t2 + st][lane]);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, as_bf16x8(bh), d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, as_bf16x8(bl), d, 0, 0, 0);
       }
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4)
@@ -330,6 +336,9 @@ __device__ __forceinline__ float mlp_logits_64(const bf16x8 (&a1)[2], const bf16
     }
     const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
     if (u == hi32) m_own = msum;
+    // the two halves run one after the other: interleaving them (the compiler's
+    // choice) keeps eight 16-register accumulators live and halves the waves per SIMD
+    __builtin_amdgcn_sched_barrier(0);
   }
   return m_own;
 }
@@ -364,12 +373,12 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   __shared__ uint16_t s_code[256];  // binary16 bits of c / 255
   __shared__ uint4 s_x[2][4][64];   // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
   __shared__ FlatPixel s_px[4][kFlatPix];
+  __shared__ u32x4 s_a[kAOps][64];
   const int tid = threadIdx.x + threadIdx.y * 64;
   for (int i = tid; i < 2 * kNH; i += 256) s_bh[i] = 0.5f * mb[i];
   for (int i = tid; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
   for (int i = tid; i < 2 * kNF; i += 256) s_std[i] = mb[kOffMean + i];
   s_code[tid] = static_cast<uint16_t>(f2h(static_cast<float>(tid) / 255.0f));  // as staged
-  __syncthreads();
 
   const int lane = threadIdx.x, wv = threadIdx.y;
   const int hi32 = lane >> 5, col = lane & 31;
@@ -379,24 +388,26 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
   FlatPixel* px = s_px[wv];
 
-  // A operands (rows = hidden units), kept in registers. v_mfma_f32_32x32x16_bf16:
+  // A operands (rows = hidden units), the same for every wave: staged once per
+  // workgroup in LDS (registers are the kernel's occupancy limit). v_mfma_f32_32x32x16_bf16:
   // lane (hi32, col) holds A[col][8 hi32 + j] and B[8 hi32 + j][col], j = 0..7.
   // Layer 1, tile t: K = 16 = the 8 features' hi parts (hi32 = 0) and lo parts
   // (hi32 = 1), so both halves hold W1[j][32t + col] (halved: y = z/2).
-  bf16x8 a1[2];
+  if (wv == 0) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    u32x4 v;
+    for (int t = 0; t < 2; ++t) {
+      u32x4 v;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-      v[p] = bf16_half_bits(mw[(2 * p) * kNH + 32 * t + col]) |
-             (bf16_half_bits(mw[(2 * p + 1) * kNH + 32 * t + col]) << 16);
-    a1[t] = as_bf16x8(v);
+      for (int p = 0; p < 4; ++p)
+        v[p] = bf16_half_bits(mw[(2 * p) * kNH + 32 * t + col]) |
+               (bf16_half_bits(mw[(2 * p + 1) * kNH + 32 * t + col]) << 16);
+      s_a[t][lane] = v;
+    }
   }
   // Layer 2, output tile t2, K-step s (hi and lo passes share it): k = 8 hi32 + j is
   // input hidden unit 32(s/2) + 8(2(s%2) + j/4) + 4 hi32 + j%4, which is element
   // 8(s%2) + j of this lane's layer-1 tile s/2 (no data movement between lanes).
-  bf16x8 a2[2][4];
+  if (wv == 1) {
 #pragma unroll
   for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
@@ -410,8 +421,10 @@ __global__ __launch_bounds__(256) void k_filter_learned(
         v[p] = bf16_half_bits(mw[kOffW2 + h0 * kNH + 32 * t2 + col]) |
                (bf16_half_bits(mw[kOffW2 + h1 * kNH + 32 * t2 + col]) << 16);
       }
-      a2[t2][st] = as_bf16x8(v);
+      s_a[2 + 4 * t2 + st][lane] = v;
     }
+  }
+  __syncthreads();
   const float b3 = mb[kOffB3];
 
   // 1. per-pixel context (lane k < kFlatPix: pixel p0 + k)
@@ -527,7 +540,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
     s_x[0][wv][lane] = make_uint4(xh[0], xh[1], xh[2], xh[3]);
     s_x[1][wv][lane] = make_uint4(xl[0], xl[1], xl[2], xl[3]);
     wave_lds_fence_l();
-    const float m_own = mlp_logits_64(a1, a2, s_x[0][wv], s_x[1][wv], s_bh, s_w3, b3, hi32, col);
+    const float m_own = mlp_logits_64(s_a, s_x[0][wv], s_x[1][wv], s_bh, s_w3, b3, hi32, col);
 
     // segmented softmax over the lanes: key = pixel (dead lanes get keys of their own)
     // (every shuffle runs on all 64 lanes: a lane that skipped one would leave its
