@@ -5,21 +5,23 @@
 // replacement of the hand-set Gaussian of Sec. 5.1 Eq. 4):
 //   O(p) = sum_s softmax(m)_s c_s,  m_s = MLP(standardised features of s).
 //
-// Inference (k_filter_learned): a wave serves 4 output pixels with 16 lanes each,
-// so every step feeds 64 samples through the MLP on the matrix cores
-// (v_mfma_f32_32x32x16_bf16: bfloat16 weights, operands as bfloat16 hi/lo pairs,
-// float32 accumulate). The layers are
-// evaluated transposed, H^T = W^T X^T (rows = hidden units, columns = samples):
-// then the accumulator layout of layer 1 is exactly the B-operand layout of
-// layer 2 (per lane: four consecutive hidden units of one sample), so the hidden
-// activations never leave registers. The softmax is evaluated online per lane and
-// merged over the pixel's 16 lanes.
+// Inference (k_filter_learned): a wave owns 16 consecutive output pixels and
+// streams their records (contiguous in the CSR arena) 64 at a time through the MLP
+// on the matrix cores (v_mfma_f32_32x32x16_bf16: bfloat16 weights, operands as
+// bfloat16 hi/lo pairs, float32 accumulate). The layers are evaluated transposed,
+// H^T = W^T X^T (rows = hidden units, columns = samples): then the accumulator
+// layout of layer 1 is exactly the B-operand layout of layer 2 (per lane: four
+// consecutive hidden units of one sample), so the hidden activations never leave
+// registers. The set softmax is a segmented reduction across the wave's lanes.
 //
-// Training (k_mlp_train_grad): float32 on the vector units, one wave per pixel of
-// the minibatch: a forward pass over the set gives the softmax statistics and O(p);
-// a second pass recomputes each sample's forward pass, back-propagates
-// dL/dm_s = a_s (c_s - O) . dL/dO through the MLP and accumulates weight gradients
-// through LDS; k_mlp_adam applies Adam to the float32 masters.
+// Training (k_mlp_train_grad): one wave per pixel of the minibatch, on the matrix
+// cores as well: a forward pass over the set gives the softmax statistics and
+// O(p); a second pass recomputes the forward pass, back-propagates
+// dL/dm_s = a_s (c_s - O) . dL/dO through the MLP (dz1 = W2 dz2 on the matrix
+// cores, again without moving data between lanes), and accumulates dW2 = H1^T DZ2
+// over the records with the operands read transposed from LDS; the small
+// gradients (W1, W3, biases) stay on the vector units. k_mlp_adam applies Adam to
+// the float32 masters.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,7 +35,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kNF = 8, kNH = 64;
 constexpr int kOffW2 = kNF * kNH;            // W2 inside the bfloat16 weight block
 constexpr int kOffW3 = kOffW2 + kNH * kNH;   // W3
-constexpr int kOffB2 = kNH, kOffB3 = 2 * kNH, kOffMean = 2 * kNH + 4, kOffInvStd = kOffMean + kNF;
+constexpr int kOffB3 = 2 * kNH, kOffMean = 2 * kNH + 4;  // inside the float32 block: b1, b2, b3, pad, mean, 1 / std
 
 __device__ __forceinline__ uint32_t bf16_bits(float v) {  // round to nearest even
   const uint32_t u = __float_as_uint(v);
@@ -286,6 +288,38 @@ __device__ __forceinline__ void set_median_codes(gp<const uint2> crho, int64_t s
 // 0, 1 = layer 1 tiles, 2 + 4 t2 + s = layer 2 output tile t2, K-step s.
 constexpr int kAOps = 10;
 
+// v_mfma_f32_32x32x16_bf16: lane (hi32, col) holds A[col][8 hi32 + j] and
+// B[8 hi32 + j][col], j = 0..7. Layer 2 (and its backward) take their B operand
+// straight from the accumulator of the layer before: K element (hi32, j) of K-step
+// s is hidden unit 32(s/2) + 8(2(s%2) + j/4) + 4 hi32 + j%4, which is element
+// 8(s%2) + j of this lane's accumulator tile s/2 (no data movement between lanes).
+__device__ __forceinline__ int kstep_unit(int s, int hi32, int j) {
+  return 32 * (s / 2) + 8 * (2 * (s % 2) + j / 4) + 4 * hi32 + j % 4;
+}
+
+// Layer 1, tile t: K = 16 = the 8 features' hi parts (hi32 = 0) and lo parts
+// (hi32 = 1), so both halves hold W1[j][32t + col], halved (y = z/2).
+template <typename P>
+__device__ __forceinline__ u32x4 a_operand_l1(P mw, int t, int col) {
+  u32x4 v;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+    v[p] = bf16_half_bits(mw[(2 * p) * kNH + 32 * t + col]) |
+           (bf16_half_bits(mw[(2 * p + 1) * kNH + 32 * t + col]) << 16);
+  return v;
+}
+
+// Layer 2, output tile t2, K-step s: W2[kstep_unit(s, hi32, j)][32 t2 + col], halved.
+template <typename P>
+__device__ __forceinline__ u32x4 a_operand_l2(P mw, int t2, int s, int hi32, int col) {
+  u32x4 v;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+    v[p] = bf16_half_bits(mw[kOffW2 + kstep_unit(s, hi32, 2 * p) * kNH + 32 * t2 + col]) |
+           (bf16_half_bits(mw[kOffW2 + kstep_unit(s, hi32, 2 * p + 1) * kNH + 32 * t2 + col]) << 16);
+  return v;
+}
+
 // The MLP on the wave's 64 samples (features staged in xs[0] (hi) / xs[1] (lo),
 // one uint4 per sample): returns the logit of the lane's own sample.
 __device__ __forceinline__ float mlp_logits_64(const u32x4 (*s_a)[64], const uint4* xs_hi, const uint4* xs_lo,
@@ -389,40 +423,17 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   FlatPixel* px = s_px[wv];
 
   // A operands (rows = hidden units), the same for every wave: staged once per
-  // workgroup in LDS (registers are the kernel's occupancy limit). v_mfma_f32_32x32x16_bf16:
-  // lane (hi32, col) holds A[col][8 hi32 + j] and B[8 hi32 + j][col], j = 0..7.
-  // Layer 1, tile t: K = 16 = the 8 features' hi parts (hi32 = 0) and lo parts
-  // (hi32 = 1), so both halves hold W1[j][32t + col] (halved: y = z/2).
+  // workgroup in LDS (registers are the kernel's occupancy limit).
   if (wv == 0) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      u32x4 v;
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        v[p] = bf16_half_bits(mw[(2 * p) * kNH + 32 * t + col]) |
-               (bf16_half_bits(mw[(2 * p + 1) * kNH + 32 * t + col]) << 16);
-      s_a[t][lane] = v;
-    }
+    for (int t = 0; t < 2; ++t) s_a[t][lane] = a_operand_l1(mw, t, col);
   }
-  // Layer 2, output tile t2, K-step s (hi and lo passes share it): k = 8 hi32 + j is
-  // input hidden unit 32(s/2) + 8(2(s%2) + j/4) + 4 hi32 + j%4, which is element
-  // 8(s%2) + j of this lane's layer-1 tile s/2 (no data movement between lanes).
+  // Layer 2: output tile t2, K-step s (the hi and lo passes share it).
   if (wv == 1) {
 #pragma unroll
-  for (int t2 = 0; t2 < 2; ++t2)
+    for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      u32x4 v;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int j0 = 2 * p, j1 = 2 * p + 1;
-        const int h0 = 32 * (st / 2) + 8 * (2 * (st % 2) + j0 / 4) + 4 * hi32 + j0 % 4;
-        const int h1 = 32 * (st / 2) + 8 * (2 * (st % 2) + j1 / 4) + 4 * hi32 + j1 % 4;
-        v[p] = bf16_half_bits(mw[kOffW2 + h0 * kNH + 32 * t2 + col]) |
-               (bf16_half_bits(mw[kOffW2 + h1 * kNH + 32 * t2 + col]) << 16);
-      }
-      s_a[2 + 4 * t2 + st][lane] = v;
-    }
+      for (int st = 0; st < 4; ++st) s_a[2 + 4 * t2 + st][lane] = a_operand_l2(mw, t2, st, hi32, col);
   }
   __syncthreads();
   const float b3 = mb[kOffB3];
@@ -630,29 +641,6 @@ struct TrainArgs {
   float* loss;
 };
 
-// forward of one sample in float32, h1 carried as the hi + lo pair of the
-// inference kernel; leaves h1 in h1out, z2 in z2out; returns the logit.
-__device__ __forceinline__ float forward_sample(const float* xs, const float* s_w1, const float* s_w2,
-                                                const float* s_w3, const float* s_b, float* h1out,
-                                                float* z2out) {
-#pragma unroll 4
-  for (int i = 0; i < kNH; ++i) {
-    float z = s_b[i];
-#pragma unroll
-    for (int k = 0; k < kNF; ++k) z = fmaf(xs[k], s_w1[k * kNH + i], z);
-    h1out[i] = split_value(gelu(z));
-  }
-  float m = s_b[kOffB3];
-  for (int j = 0; j < kNH; ++j) {
-    float z = s_b[kOffB2 + j];
-#pragma unroll 8
-    for (int i = 0; i < kNH; ++i) z = fmaf(h1out[i], s_w2[i * kNH + j], z);
-    z2out[j] = z;
-    m = fmaf(s_w3[j], gelu(z), m);
-  }
-  return m;
-}
-
 // The kernels' view of TrainArgs: every pointer in the global address space
 // (pointers inside a by-value argument struct are otherwise generic).
 struct TrainDev {
@@ -708,24 +696,72 @@ __device__ __forceinline__ void add_f32(gp<float> p, float v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Backward A operand, rows = layer-1 unit i = 32 t1 + col, K-step s over layer-2
+// units in the accumulator order: W2[i][kstep_unit(s, hi32, j)] (not halved).
+template <typename P>
+__device__ __forceinline__ u32x4 a_operand_back(P mw, int t1, int s, int hi32, int col) {
+  u32x4 v;
+  const int row = kOffW2 + (32 * t1 + col) * kNH;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+    v[p] = static_cast<uint32_t>(mw[row + kstep_unit(s, hi32, 2 * p)]) |
+           (static_cast<uint32_t>(mw[row + kstep_unit(s, hi32, 2 * p + 1)]) << 16);
+  return v;
+}
+
+// 8 float32 values as bfloat16 hi / lo operand halves
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) split_pack(v[2 * p], v[2 * p + 1], h[p], l[p]);
+  hi = as_bf16x8(u32x4{h[0], h[1], h[2], h[3]});
+  lo = as_bf16x8(u32x4{l[0], l[1], l[2], l[3]});
+}
+
+// One wave per minibatch pixel at a time, 64 of its records per step (lane =
+// record). Pass 1: the inference kernel's matrix-core forward gives the logits,
+// an online softmax per lane and a merge over the wave give O(p), the loss and
+// dL/dO. Pass 2, per step and per 32-record half: layer 1 and layer 2 forward on
+// the matrix cores (transposed: rows = hidden units, columns = records), then
+//   dm_s   = a_s (c_s - O) . dL/dO               (a_s = softmax weight)
+//   dz2_s  = dm_s w3 * GELU'(z2_s)
+//   dz1^T  = W2 dz2^T * GELU'(z1)                 (matrix cores, hi / lo dz2)
+// and, with the step's h1, dz2, dz1, h2, x in LDS as [record][unit] rows,
+//   dW2   += H1^T DZ2 over the step's 64 records   (matrix cores: operands read
+//            transposed from LDS, hi*hi + hi*lo + lo*hi products, float32
+//            accumulators held for the whole kernel)
+//   dW1, dW3, db1, db2, db3 on the vector units (lane = unit).
+// The gradients are summed into ta.grad (float32 atomics) at the end.
 __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
   const TrainDev ta = dev_args(ta_in);
-  __shared__ float s_w1[kNF * kNH];
-  __shared__ float s_w2[kNH * kNH];
+  __shared__ float s_bh[2 * kNH];  // b1 / 2, b2 / 2
   __shared__ float s_w3[kNH];
-  __shared__ float s_b[SG_MLP_NB];
-  __shared__ float s_h1[64 * kTS];
+  __shared__ float s_std[2 * kNF];  // mean, 1 / std
+  __shared__ u32x4 s_a[kAOps][64];  // forward A operands
+  __shared__ u32x4 s_ab[8][64];     // backward A operands, entry 4 t1 + s
+  __shared__ uint4 s_x[2][64];      // hi / lo feature parts of the step's records
+  __shared__ float s_h1[64 * kTS];  // [record][unit]
   __shared__ float s_dz2[64 * kTS];
   __shared__ float s_dz1[64 * kTS];
-  __shared__ float s_x[64 * 9];
+  __shared__ float s_h2[64 * kTS];
+  __shared__ float s_xf[64 * 9];    // standardised features (hi + lo values)
   __shared__ float s_dm[64];
-  __shared__ float s_h2w[64 * kTS];
   const int lane = threadIdx.x;
-  for (int i = lane; i < kNF * kNH; i += 64) s_w1[i] = bf16_to_f(ta.mw[i]);
-  for (int i = lane; i < kNH * kNH; i += 64) s_w2[i] = bf16_to_f(ta.mw[kOffW2 + i]);
+  const int hi32 = lane >> 5, col = lane & 31;
+  for (int i = lane; i < 2 * kNH; i += 64) s_bh[i] = 0.5f * ta.mb[i];
   s_w3[lane] = bf16_to_f(ta.mw[kOffW3 + lane]);
-  for (int i = lane; i < SG_MLP_NB; i += 64) s_b[i] = ta.mb[i];
+  if (lane < 2 * kNF) s_std[lane] = ta.mb[kOffMean + lane];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) s_a[t][lane] = a_operand_l1(ta.mw, t, col);
+#pragma unroll
+  for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      s_a[2 + 4 * t2 + st][lane] = a_operand_l2(ta.mw, t2, st, hi32, col);
+      s_ab[4 * t2 + st][lane] = a_operand_back(ta.mw, t2, st, hi32, col);
+    }
   __syncthreads();
+  const float b3 = ta.mb[kOffB3];
 
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
   const int pw = stored_pitch(ta.width);
@@ -744,11 +780,15 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
   fa.cx = ta.cx;
   fa.cy = ta.cy;
 
-  // per-lane gradient accumulators: dW2 row `lane`, dW1 entries (k = lane/8, j = 8*(lane%8)+..),
-  // dW3[lane], db1[lane], db2[lane], db3 (lane 0)
-  float gw2[kNH];
+  // dW2 accumulators: tile (ti, tj), element a = dW2[32 ti + 8(a/4) + 4 hi32 + a%4][32 tj + col]
+  v16f gw2[2][2];
 #pragma unroll
-  for (int j = 0; j < kNH; ++j) gw2[j] = 0.0f;
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int a = 0; a < 16; ++a) gw2[ti][tj][a] = 0.0f;
+  // lane = unit: dW1 entries (k = lane/8, j = 8(lane%8) + jj), dW3[lane], db1[lane], db2[lane], db3
   float gw1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float gw3 = 0.f, gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;
   const float inv3n = 1.0f / (3.0f * static_cast<float>(ta.n_pix));
@@ -760,7 +800,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
     const int64_t self = pix - static_cast<int64_t>(fo) * plane;
     const int y = static_cast<int>(self / ta.width), x = static_cast<int>(self - static_cast<int64_t>(y) * ta.width);
     const size_t pi = static_cast<size_t>(ta.f0 + fo) * pplane + padded_index(x, y, pw);
-    int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
+    const int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
     if (s < 0 || e <= s || e > ta.capacity) continue;
     PixelCtx px;
     px.x = static_cast<float>(x);
@@ -771,25 +811,49 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
     set_median<64>(ta.crho, s, e, lane, px.medr, px.medg, px.medb);
     fa.rel = ta.rel + static_cast<size_t>(fo) * (2 * ta.w + 1) * kRelStride;
 
-    float h1[kNH], z2[kNH];
+    // features of record base + lane into s_x (hi / lo) and, if asked, s_xf;
+    // a record outside the set or the clip is dead (features 0, no weight)
+    auto stage = [&](int64_t base, bool keep_f32, uint2& rec) -> bool {
+      const int64_t idx = base + lane;
+      const bool live = idx < e && id_in_clip(fa, px.f, ta.ids[idx]);
+      float xs[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      rec = make_uint2(0u, 0u);
+      if (live) {
+        rec = ld2(ta.crho + idx);
+        float feat[kNF];
+        sample_features(fa, px, ta.ids[idx], rec, feat);
+#pragma unroll
+        for (int k = 0; k < kNF; ++k) xs[k] = (feat[k] - s_std[k]) * s_std[kNF + k];
+      }
+      uint32_t xh[4], xl[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) split_pack(xs[2 * q], xs[2 * q + 1], xh[q], xl[q]);
+      s_x[0][lane] = make_uint4(xh[0], xh[1], xh[2], xh[3]);
+      s_x[1][lane] = make_uint4(xl[0], xl[1], xl[2], xl[3]);
+      if (keep_f32) {
+#pragma unroll
+        for (int k = 0; k < kNF; ++k) s_xf[lane * 9 + k] = split_value(xs[k]);
+      }
+      return live;
+    };
+
     // pass 1: softmax statistics and O(p)
     float run_m = -INFINITY, run_z = 0.f, acc[3] = {0.f, 0.f, 0.f};
-    for (int64_t idx = s + lane; idx < e; idx += 64) {
-      const uint32_t id = ta.ids[idx];
-      if (!id_in_clip(fa, px.f, id)) continue;
-      const uint2 rec = ld2(ta.crho + idx);
-      float feat[kNF], xs[kNF];
-      sample_features(fa, px, id, rec, feat);
-#pragma unroll
-      for (int k = 0; k < kNF; ++k) xs[k] = split_value((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
-      const float m = forward_sample(xs, s_w1, s_w2, s_w3, s_b, h1, z2);
-      const float nm = fmaxf(run_m, m);
-      const float sc = __expf(run_m - nm), ew = __expf(m - nm);
-      run_z = fmaf(run_z, sc, ew);
-      acc[0] = fmaf(acc[0], sc, ew * h2f(rec.x));
-      acc[1] = fmaf(acc[1], sc, ew * h2f(rec.x >> 16));
-      acc[2] = fmaf(acc[2], sc, ew * h2f(rec.y));
-      run_m = nm;
+    for (int64_t base = s; base < e; base += 64) {
+      uint2 rec;
+      const bool live = stage(base, false, rec);
+      wave_lds_fence_l();
+      const float m = mlp_logits_64(s_a, s_x[0], s_x[1], s_bh, s_w3, b3, hi32, col);
+      wave_lds_fence_l();
+      if (live) {
+        const float nm = fmaxf(run_m, m);
+        const float sc = __expf(run_m - nm), ew = __expf(m - nm);
+        run_z = fmaf(run_z, sc, ew);
+        acc[0] = fmaf(acc[0], sc, ew * h2f(rec.x));
+        acc[1] = fmaf(acc[1], sc, ew * h2f(rec.x >> 16));
+        acc[2] = fmaf(acc[2], sc, ew * h2f(rec.y));
+        run_m = nm;
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -816,66 +880,161 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
     }
     if (lane == 0) add_f32(ta.loss, l2 * inv3n);
 
-    // pass 2: backward, 64 samples per chunk
+    // pass 2: backward, 64 records per step
     for (int64_t base = s; base < e; base += 64) {
-      const int64_t idx = base + lane;
-      const bool live = idx < e && id_in_clip(fa, px.f, ta.ids[idx]);
-      float xs[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float dm = 0.f;
-      if (live) {
-        const uint2 rec = ld2(ta.crho + idx);
-        float feat[kNF];
-        sample_features(fa, px, ta.ids[idx], rec, feat);
+      uint2 rec;
+      const bool live = stage(base, true, rec);
+      wave_lds_fence_l();
 #pragma unroll
-        for (int k = 0; k < kNF; ++k) xs[k] = split_value((feat[k] - s_b[kOffMean + k]) * s_b[kOffInvStd + k]);
-        const float m = forward_sample(xs, s_w1, s_w2, s_w3, s_b, h1, z2);
-        const float a = __expf(m - run_m) * zinv;
-        dm = a * ((h2f(rec.x) - o[0]) * dO[0] + (h2f(rec.x >> 16) - o[1]) * dO[1] +
-                  (h2f(rec.y) - o[2]) * dO[2]);
-      } else {
+      for (int u = 0; u < 2; ++u) {
+        const int rs = 32 * u + col;  // record (within the step) of this lane's column
+        // layer 1: y1 = z1 / 2, tile t element a = unit 32t + 8(a/4) + 4 hi32 + a%4
+        const uint4 xv = (hi32 ? s_x[1] : s_x[0])[rs];
+        const bf16x8 bx = as_bf16x8(u32x4{xv.x, xv.y, xv.z, xv.w});
+        v16f y1[2];
+        uint32_t ph[2][8], pl[2][8];
 #pragma unroll
-        for (int i = 0; i < kNH; ++i) h1[i] = z2[i] = 0.f;
+        for (int t = 0; t < 2; ++t) {
+          v16f c;
+#pragma unroll
+          for (int a = 0; a < 16; ++a) c[a] = s_bh[32 * t + 8 * (a / 4) + 4 * hi32 + a % 4];
+          y1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s_a[t][lane]), bx, c, 0, 0, 0);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            split_pack(gelu_half(y1[t][2 * q]), gelu_half(y1[t][2 * q + 1]), ph[t][q], pl[t][q]);
+            // h1 = hi + lo, as the matrix cores see it
+            const int a0 = 2 * q;  // elements 2q, 2q + 1: units r0, r0 + 1
+            const int r0 = 32 * t + 8 * (a0 / 4) + 4 * hi32 + a0 % 4, r1 = r0 + 1;
+            s_h1[rs * kTS + r0] = __uint_as_float(ph[t][q] << 16) + __uint_as_float(pl[t][q] << 16);
+            s_h1[rs * kTS + r1] =
+                __uint_as_float(ph[t][q] & 0xFFFF0000u) + __uint_as_float(pl[t][q] & 0xFFFF0000u);
+          }
+        }
+        // layer 2: y2 = z2 / 2, same element layout
+        v16f y2[2];
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2) {
+#pragma unroll
+          for (int a = 0; a < 16; ++a) y2[t2][a] = s_bh[kNH + 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4];
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const int t = st / 2, p0 = 4 * (st % 2);
+            const u32x4 bh = {ph[t][p0], ph[t][p0 + 1], ph[t][p0 + 2], ph[t][p0 + 3]};
+            const u32x4 bl = {pl[t][p0], pl[t][p0 + 1], pl[t][p0 + 2], pl[t][p0 + 3]};
+            const bf16x8 a2 = as_bf16x8(s_a[2 + 4 * t2 + st][lane]);
+            y2[t2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, as_bf16x8(bh), y2[t2], 0, 0, 0);
+            y2[t2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, as_bf16x8(bl), y2[t2], 0, 0, 0);
+          }
+        }
+        // logit of record rs, then dm for it (its colour and liveness from lane rs)
+        float mpart = 0.0f;
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+          for (int a = 0; a < 16; ++a) {
+            const int j = 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4;
+            const float h2 = gelu_half(y2[t2][a]);
+            s_h2[rs * kTS + j] = h2;
+            mpart = fmaf(s_w3[j], h2, mpart);
+          }
+        const float m = mpart + __shfl_xor(mpart, 32, 64) + b3;
+        const uint32_t rx = __shfl(rec.x, rs, 64), ry = __shfl(rec.y, rs, 64);
+        const int live_rs = __shfl(live ? 1 : 0, rs, 64);
+        float dm = 0.0f;
+        if (live_rs) {
+          const float a = __expf(m - run_m) * zinv;
+          dm = a * ((h2f(rx) - o[0]) * dO[0] + (h2f(rx >> 16) - o[1]) * dO[1] + (h2f(ry) - o[2]) * dO[2]);
+        }
+        if (hi32 == 0) s_dm[rs] = dm;
+        // dz2 = dm w3 GELU'(z2), z2 = 2 y2; as hi / lo B operands of the backward product
+        uint32_t dh[2][8], dl[2][8];
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float g[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int a = 2 * q + h;
+              const int j = 32 * t2 + 8 * (a / 4) + 4 * hi32 + a % 4;
+              g[h] = dm * s_w3[j] * gelu_grad(2.0f * y2[t2][a]);
+              s_dz2[rs * kTS + j] = g[h];
+            }
+            split_pack(g[0], g[1], dh[t2][q], dl[t2][q]);
+          }
+        // dz1^T = W2 dz2^T, then * GELU'(z1), z1 = 2 y1
+#pragma unroll
+        for (int t1 = 0; t1 < 2; ++t1) {
+          v16f d1;
+#pragma unroll
+          for (int a = 0; a < 16; ++a) d1[a] = 0.0f;
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const int t = st / 2, p0 = 4 * (st % 2);
+            const u32x4 bh = {dh[t][p0], dh[t][p0 + 1], dh[t][p0 + 2], dh[t][p0 + 3]};
+            const u32x4 bl = {dl[t][p0], dl[t][p0 + 1], dl[t][p0 + 2], dl[t][p0 + 3]};
+            const bf16x8 ab = as_bf16x8(s_ab[4 * t1 + st][lane]);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, as_bf16x8(bh), d1, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, as_bf16x8(bl), d1, 0, 0, 0);
+          }
+#pragma unroll
+          for (int a = 0; a < 16; ++a) {
+            const int i = 32 * t1 + 8 * (a / 4) + 4 * hi32 + a % 4;
+            s_dz1[rs * kTS + i] = d1[a] * gelu_grad(2.0f * y1[t1][a]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
-      // dz2, h2; then dh1 -> dz1
-#pragma unroll 4
-      for (int j = 0; j < kNH; ++j) {
-        s_h2w[lane * kTS + j] = live ? gelu(z2[j]) : 0.f;
-        s_dz2[lane * kTS + j] = live ? dm * s_w3[j] * gelu_grad(z2[j]) : 0.f;
-        s_h1[lane * kTS + j] = h1[j];
-      }
-#pragma unroll 2
-      for (int i = 0; i < kNH; ++i) {
-        float dh = 0.f;
-#pragma unroll 8
-        for (int j = 0; j < kNH; ++j) dh = fmaf(s_w2[i * kNH + j], s_dz2[lane * kTS + j], dh);
-        float z1 = s_b[i];
+      wave_lds_fence_l();
+      // dW2 += H1^T DZ2 over the step's records: K = record, 16 per product
 #pragma unroll
-        for (int k = 0; k < kNF; ++k) z1 = fmaf(xs[k], s_w1[k * kNH + i], z1);
-        s_dz1[lane * kTS + i] = live ? dh * gelu_grad(z1) : 0.f;
-      }
+      for (int ks = 0; ks < 4; ++ks) {
+        bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-      for (int k = 0; k < kNF; ++k) s_x[lane * 9 + k] = xs[k];
-      s_dm[lane] = dm;
-      __syncthreads();
-      // weight gradients of this chunk
+        for (int t = 0; t < 2; ++t) {
+          float va[8], vb[8];
+#pragma unroll
+          for (int jj = 0; jj < 8; ++jj) {
+            const int r = 16 * ks + 8 * hi32 + jj;
+            va[jj] = s_h1[r * kTS + 32 * t + col];
+            vb[jj] = s_dz2[r * kTS + 32 * t + col];
+          }
+          split8(va, ah[t], al[t]);
+          split8(vb, bh[t], bl[t]);
+        }
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 2; ++tj) {
+            gw2[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ti], bh[tj], gw2[ti][tj], 0, 0, 0);
+            gw2[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ti], bl[tj], gw2[ti][tj], 0, 0, 0);
+            gw2[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ti], bh[tj], gw2[ti][tj], 0, 0, 0);
+          }
+      }
+      // the small gradients on the vector units, lane = unit
       for (int r = 0; r < 64; ++r) {
-        const float h1v = s_h1[r * kTS + lane];
-#pragma unroll
-        for (int j = 0; j < kNH; ++j) gw2[j] = fmaf(h1v, s_dz2[r * kTS + j], gw2[j]);
-        const float xk = s_x[r * 9 + lane / 8];
+        const float xk = s_xf[r * 9 + lane / 8];
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) gw1[jj] = fmaf(xk, s_dz1[r * kTS + 8 * (lane % 8) + jj], gw1[jj]);
-        gw3 = fmaf(s_dm[r], s_h2w[r * kTS + lane], gw3);
+        const float dmr = s_dm[r];
+        gw3 = fmaf(dmr, s_h2[r * kTS + lane], gw3);
         gb1 += s_dz1[r * kTS + lane];
         gb2 += s_dz2[r * kTS + lane];
-        gb3 += s_dm[r];
+        gb3 += dmr;
       }
-      __syncthreads();
+      wave_lds_fence_l();
     }
   }
   // master order: W1 [8][64], W2 [64][64], W3 [64], b1 [64], b2 [64], b3
 #pragma unroll
-  for (int j = 0; j < kNH; ++j) add_f32(ta.grad + (kOffW2 + lane * kNH + j), gw2[j]);
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        const int i = 32 * ti + 8 * (a / 4) + 4 * hi32 + a % 4, j = 32 * tj + col;
+        add_f32(ta.grad + (kOffW2 + i * kNH + j), gw2[ti][tj][a]);
+      }
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj) add_f32(ta.grad + ((lane / 8) * kNH + 8 * (lane % 8) + jj), gw1[jj]);
   add_f32(ta.grad + (kOffW3 + lane), gw3);
