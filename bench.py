@@ -94,7 +94,7 @@ MLP_FLOP_PER_SAMPLE = 2 * (8 * 64 + 64 * 64 + 64)   # 8 -> 64 -> 64 -> 1, multip
 BF16_DENSE_PEAK_TFLOPS = 2500.0
 
 
-def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int) -> dict:
+def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int, with_curve: bool = True) -> dict:
     """The learned-weight filter on the same gathers (window +-w), timed like the plain
     step; PSNR of plain and learned on a few spread frames; and the learned path at
     the largest smaller window whose whole step is no slower than the plain step."""
@@ -178,7 +178,7 @@ def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: i
     # equal time: the largest window whose learned step fits the plain step's time;
     # the whole window / time / PSNR curve is reported
     curve = []
-    for wq in (40, 30, 20, 12, 8, 6, 4, 3, 2, 1):
+    for wq in (40, 30, 20, 12, 8, 6, 4, 3, 2, 1) if with_curve else ():
         if wq >= params.window:
             continue
         pq = sg.GatherParams(window=wq, radius=params.radius, tol=params.tol, z_near=params.z_near)
@@ -334,6 +334,8 @@ def main() -> int:
                     help="full: the 1080p +-50 headline workload; batched: 32 uneven clips per step")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--no-curve", action="store_true",
+                    help="learned leg at the workload's window only (no smaller-window curve)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run one plain 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
@@ -468,7 +470,7 @@ def main() -> int:
     }
     if not args.no_learned:
         res["learned"] = learned_leg(sg, clip, staged, wl, params, fparams, frames[args.warmup:], ms_step,
-                                     args.learned_steps)
+                                     args.learned_steps, with_curve=not args.no_curve)
     if args.copy_probe:
         x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
