@@ -288,6 +288,27 @@ def batched_main(args) -> int:
     stop.record()
     torch.cuda.synchronize()
     solo_ms = start.elapsed_time(stop) / args.steps
+    # per-pass split of the single-clip path (one more step, events between passes)
+    solo_passes = {"count": 0.0, "scatter": 0.0, "filter": 0.0}
+    evs = []
+    for c in range(len(wls)):
+        a, ws, out = arenas[c]
+        fc = frames[args.warmup][c]
+        sets = sg.SampleSets(fc, fc + 1, params[c].window, a.offsets, a.ids, a.crho, a.status)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        sg.scene_gather_count(staged[c], fc, fc + 1, params[c], sets, ws)
+        e[1].record()
+        sg.scene_gather_scatter(staged[c], fc, fc + 1, params[c], sets, ws)
+        e[2].record()
+        sg.scene_filter(staged[c], sets, fparams[c], out=out)
+        e[3].record()
+        evs.append(e)
+    torch.cuda.synchronize()
+    for e in evs:
+        solo_passes["count"] += e[0].elapsed_time(e[1])   # count includes the scan
+        solo_passes["scatter"] += e[1].elapsed_time(e[2])
+        solo_passes["filter"] += e[2].elapsed_time(e[3])
     pix = b.total_pixels
     res = {
         "metric": "gathered samples/s (32 uneven clips per step, one persistent launch per pass, graph replay)",
@@ -312,6 +333,7 @@ def batched_main(args) -> int:
         "samples_per_step": samples,
         "pass_ms_eager": passes,
         "solo_ms_per_step": solo_ms,
+        "solo_pass_ms": solo_passes,
         "speedup_vs_solo": solo_ms / ms_step,
         "gpu": torch.cuda.get_device_name(0),
     }

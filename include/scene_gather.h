@@ -295,7 +295,10 @@ typedef struct sg_batch_io {
 
 /* Plan a batch: clips[c] (stored planes, device poses, intrinsics), params[c],
  * fparams[c] (sigmas, as scene_filter) and n_out[c] >= 1 output frames per step.
- * The descriptors' device pointers must stay valid for the batch's lifetime. */
+ * The descriptors' device pointers must stay valid for the batch's lifetime.
+ * SG_E_UNSUPPORTED: more than SG_MAX_BATCH_CLIPS clips, clips with different radii,
+ * or more than 2^31 - 1 relative-map floats in total (sum over clips of
+ * n_out[c] * (2 window + 1) * 16). */
 sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
                           const sg_gather_params* params, const sg_filter_params* fparams,
                           const int32_t* n_out);

@@ -42,6 +42,7 @@ struct sg_batch {
   int64_t* d_fprefix = nullptr;     // first filter work item of each clip (clip order), n + 1
   int64_t* d_partial = nullptr;
   unsigned int* d_queues = nullptr;
+  float* d_rel = nullptr;
   int* h_f0 = nullptr;          // pinned: the frames of the next step
   hipEvent_t step_done = nullptr;
   bool step_recorded = false;
@@ -84,6 +85,7 @@ sg::BatchDev dev_view(const sg_batch& b, int th) {
   d.order = b.d_order;
   d.prefix = b.d_prefix[th_index(th)];
   d.pix_prefix = b.d_pix_prefix;
+  d.rel = b.d_rel;
   d.n_clips = b.n_clips;
   d.radius = b.radius;
   return d;
@@ -173,6 +175,7 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
   if (clips == nullptr || params == nullptr || fparams == nullptr || n_out == nullptr) return SG_E_INVALID;
   if (n_clips <= 0) return SG_E_INVALID;
   if (n_clips > SG_MAX_BATCH_CLIPS) return SG_E_UNSUPPORTED;
+  size_t maps = 0;  // relative-map floats of all clips: the kernels index them with int offsets
   for (int c = 0; c < n_clips; ++c) {
     sg_status s = sg::check_clip(&clips[c], true);
     if (s != SG_OK) return s;
@@ -181,7 +184,9 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
     if (n_out[c] < 1 || n_out[c] > clips[c].num_frames) return SG_E_INVALID;
     const float sd = fparams[c].sigma_d, sc = fparams[c].sigma_c, stt = fparams[c].sigma_t;
     if (!(sd > 0.0f) || !(sc > 0.0f) || !(stt > 0.0f)) return SG_E_INVALID;
+    maps += static_cast<size_t>(n_out[c]) * (2 * static_cast<size_t>(params[c].window) + 1) * sg::kRelStride;
   }
+  if (maps > static_cast<size_t>(INT32_MAX)) return SG_E_UNSUPPORTED;
   sg_batch* b = new (std::nothrow) sg_batch();
   if (b == nullptr) return SG_E_HIP;
   b->n_clips = n_clips;
@@ -241,6 +246,7 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
   b->d_partial = reinterpret_cast<int64_t*>(base + o_part);
   b->d_queues = reinterpret_cast<unsigned int*>(base + o_q);
   float* rel = reinterpret_cast<float*>(base + o_rel);
+  b->d_rel = rel;
   const double log2e = 1.4426950408889634;
   std::vector<sg::BatchClip> hc(n);
   size_t rel_at = 0;
@@ -251,6 +257,7 @@ sg_status sg_batch_create(sg_batch** out, const sg_clip* clips, int32_t n_clips,
     d.depth = clips[c].depth;
     d.c2w = clips[c].cam_to_world;
     d.rel = rel + rel_at;
+    d.rel_at = static_cast<int>(rel_at);
     rel_at += static_cast<size_t>(n_out[c]) * (2 * params[c].window + 1) * sg::kRelStride;
     d.width = clips[c].width;
     d.height = clips[c].height;

@@ -86,7 +86,8 @@ struct BatchClip {
   const uint16_t* depth;
   const double* c2w;
   float* rel;            // n_out x (2w+1) x kRelStride floats, owned by the batch
-  int width, height, n_frames, n_out, w, pad0;
+  int width, height, n_frames, n_out, w;
+  int rel_at;            // rel - BatchDev::rel, in floats
   float tol, z_near;
   double fx, fy, cx, cy;
   int64_t pix_base;      // CSR index of the clip's first output pixel
@@ -101,6 +102,7 @@ struct BatchDev {
   const int* order;          // [n_clips]: clip of each slot
   const int64_t* prefix;     // [n_clips + 1] first work item of each slot (tile height th)
   const int64_t* pix_prefix; // [n_clips + 1] CSR base of each clip (clip order)
+  const float* rel;          // all clips' relative maps; each BatchClip::rel points into it
   int n_clips;
   int radius;
 };

@@ -835,12 +835,15 @@ __global__ __launch_bounds__(256) void k_count_batched(BatchDev bd, int64_t* __r
   }
 }
 
-// The plan arrays come as separate restrict arguments: the kernel's stores then
-// provably miss them, so their loads can go through the scalar cache.
+// The plan arrays and the relative maps come as separate restrict arguments: the
+// kernel's stores then provably miss them, so their loads can go through the
+// scalar cache (each clip's maps are addressed from rel_all, not from the pointer
+// in its descriptor, which the compiler could not separate from the stores).
 template <int R, int TH>
 __global__ __launch_bounds__(256) void k_scatter_batched(const BatchClip* __restrict__ clips,
                                                          const int* __restrict__ f0s, const int* __restrict__ order,
                                                          const int64_t* __restrict__ prefix, int n_clips,
+                                                         const float* __restrict__ rel_all,
                                                          const int64_t* __restrict__ offsets,
                                                          uint32_t* __restrict__ ids, uint2* __restrict__ crho,
                                                          int64_t capacity, uint32_t* __restrict__ status,
@@ -853,10 +856,11 @@ __global__ __launch_bounds__(256) void k_scatter_batched(const BatchClip* __rest
     if (item >= n_items) break;
     const int slot = item_slot(prefix, n_clips, item);
     const int clip = order[slot];
-    const BatchClip c = clips[clip];
+    const BatchClip c = load_clip(clips + clip);
     const int f0 = f0s[clip];
     const TileOf t = batch_tile<TH>(c, item - prefix[slot]);
-    gp<const float> relf = to_global(static_cast<const float*>(c.rel)) + static_cast<size_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+    const int64_t rel_at = static_cast<int64_t>(c.rel_at) + static_cast<int64_t>(t.fo) * (2 * c.w + 1) * kRelStride;
+    gp<const float> relf = to_global(rel_all) + rel_at;
     gp<const uint2> rgbd = to_global(reinterpret_cast<const uint2*>(c.rgbd));
     gp<const uint16_t> depth = to_global(c.depth);
     const int f = f0 + t.fo;
@@ -1061,7 +1065,7 @@ static void scatter_batched_r(const BatchDev& bd, const BatchIo& io, const Batch
   const dim3 g(static_cast<unsigned>(bl.blocks_scatter)), b(kTileW, 4);
 #define SG_SCATTER_BATCHED(TH) \
   hipLaunchKernelGGL((k_scatter_batched<R, TH>), g, b, 0, st, bd.clips, bd.f0, bd.order, bd.prefix, bd.n_clips, \
-                     io.offsets, io.ids, reinterpret_cast<uint2*>(io.crho), io.capacity, io.status, q)
+                     bd.rel, io.offsets, io.ids, reinterpret_cast<uint2*>(io.crho), io.capacity, io.status, q)
   switch (bl.th_scatter) {
     case 1: SG_SCATTER_BATCHED(1); break;
     case 2: SG_SCATTER_BATCHED(2); break;
