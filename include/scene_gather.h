@@ -238,8 +238,10 @@ typedef struct sg_mlp_train {
  * int32, indices into [0, P)); clean_rgb device [n_pix][3] float32 is the ground
  * truth G of those pixels, row i for pixel_idx[i]. An index outside [0, P) is
  * skipped. Forward uses the bfloat16 copy in state->w_bf16 / b_f32 (the previous step's
- * result, or the caller's initial copy); the backward pass is float32. Requires the
- * workspace of a gather of [f0, f1) with `params` (relative maps recomputed here). */
+ * result, or the caller's initial copy); forward and backward run on the matrix cores
+ * with bfloat16 hi/lo operands and float32 accumulation (the W1, W3 and bias
+ * gradients on the vector units in float32). Requires the workspace of a gather of
+ * [f0, f1) with `params` (relative maps recomputed here). */
 sg_status scene_mlp_train_step(const sg_clip* clip, int32_t f0, int32_t f1,
                                const sg_gather_params* params, const sg_sample_sets* sets,
                                const int32_t* pixel_idx, int32_t n_pix, const float* clean_rgb,
