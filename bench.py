@@ -362,8 +362,8 @@ def main() -> int:
                     help="after timing, run one plain 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(output frames shard without exchange; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(output frames would shard across GPUs without any exchange)", file=sys.stderr)
         return 2
 
     if args.workload == "batched":
