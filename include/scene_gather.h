@@ -45,9 +45,12 @@ extern "C" {
  * into 22 bits, so W * H <= 2^22 and 2w + 1 <= 1024. */
 #define SG_MAX_PIXELS_PER_FRAME (1 << 22)
 /* Stored planes carry an apron: SG_APRON rows above and below the image and
- * SG_APRON columns on its left (>= SG_MAX_RADIUS), SG_APRON_RIGHT columns on its
- * right (room for whole 8-byte reads of a block row). */
-#define SG_APRON 3
+ * SG_APRON columns on its left, SG_APRON_RIGHT columns on its right. A projection
+ * is kept when its block centre lies at most r pixels outside the image, so the
+ * block reaches 2r beyond it: SG_APRON >= 2 SG_MAX_RADIUS, and the right apron
+ * also holds the fourth value of an 8-byte read of a block row of depths
+ * (SG_APRON_RIGHT >= 2 SG_MAX_RADIUS + 1). */
+#define SG_APRON 6
 #define SG_APRON_RIGHT 7
 #define SG_MAX_WINDOW 511
 #define SG_MAX_RADIUS 3

@@ -15,7 +15,7 @@ SG_FLAG_CAPACITY, SG_FLAG_INCONSISTENT = 1, 2
 SG_ID_SHIFT = 22
 SG_MAX_WINDOW = 511
 SG_MAX_RADIUS = 3
-SG_APRON = 3
+SG_APRON = 6
 SG_APRON_RIGHT = 7
 
 c_void_p = ctypes.c_void_p

@@ -46,7 +46,11 @@ __device__ __forceinline__ uint32_t f2h(float v) {
 constexpr uint32_t kInvalidDepth16 = 0x7E00u;  // binary16 quiet NaN
 
 // Stored planes: SG_APRON rows above and below, SG_APRON columns left and
-// SG_APRON_RIGHT columns right of the image.
+// SG_APRON_RIGHT columns right of the image. Every block read of the gather stays
+// inside the plane: centres at most r outside the image, blocks 2r + 1 wide, block
+// rows of depths read as 4 values.
+static_assert(SG_APRON >= 2 * SG_MAX_RADIUS, "apron must hold a block centred r outside the image");
+static_assert(SG_APRON_RIGHT >= 2 * SG_MAX_RADIUS + 1, "right apron must hold an 8-byte block-row read");
 __host__ __device__ __forceinline__ int stored_pitch(int width) {
   return width + SG_APRON + SG_APRON_RIGHT;
 }

@@ -36,6 +36,21 @@ def test_header_functions_are_exported(native):
         assert n in mod.SIGNATURES, n
 
 
+def test_header_constants_match_binding_and_bound_the_gather_reads():
+    """The binding's copies of the header's limits and layout constants agree, and
+    the apron holds every block the gather reads: a projection is kept when its
+    block centre is at most r outside the image, so blocks reach 2r beyond it
+    (and a block row of depths is read as 4 values, one more on the right)."""
+    from paper_2102_03011_amd import _native
+    text = open(HEADER).read()
+    defs = {k: int(v, 0) for k, v in re.findall(r"^#define (SG_[A-Z_]+) \(?([0-9x]+)", text, flags=re.M)}
+    for name in ("SG_APRON", "SG_APRON_RIGHT", "SG_MAX_RADIUS", "SG_MAX_WINDOW", "SG_ID_SHIFT"):
+        assert getattr(_native, name) == defs[name], name
+    r = defs["SG_MAX_RADIUS"]
+    assert defs["SG_APRON"] >= 2 * r
+    assert defs["SG_APRON_RIGHT"] >= 2 * r + 1
+
+
 def test_version_and_status_strings(native):
     mod, lib = native
     assert lib.sg_version() == 1
