@@ -47,9 +47,9 @@ extern "C" {
 /* Stored planes carry an apron: SG_APRON rows above and below the image and
  * SG_APRON columns on its left, SG_APRON_RIGHT columns on its right. A projection
  * is kept when its block centre lies at most r pixels outside the image, so the
- * block reaches 2r beyond it: SG_APRON >= 2 SG_MAX_RADIUS, and the right apron
- * also holds the fourth value of an 8-byte read of a block row of depths
- * (SG_APRON_RIGHT >= 2 SG_MAX_RADIUS + 1). */
+ * block reaches 2r beyond it: SG_APRON >= 2 SG_MAX_RADIUS. A block row of depths
+ * is read as whole 8-byte words (4 values) from its first column, so the right
+ * apron holds 4 ceil((2r + 1) / 4) - 1 columns for every r <= SG_MAX_RADIUS. */
 #define SG_APRON 6
 #define SG_APRON_RIGHT 7
 #define SG_MAX_WINDOW 511

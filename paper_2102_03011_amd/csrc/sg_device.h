@@ -48,9 +48,13 @@ constexpr uint32_t kInvalidDepth16 = 0x7E00u;  // binary16 quiet NaN
 // Stored planes: SG_APRON rows above and below, SG_APRON columns left and
 // SG_APRON_RIGHT columns right of the image. Every block read of the gather stays
 // inside the plane: centres at most r outside the image, blocks 2r + 1 wide, block
-// rows of depths read as 4 values.
+// rows of depths read as whole 8-byte words (4 values) from their first column.
+constexpr int right_apron_needed(int r) { return 4 * ((2 * r + 1 + 3) / 4) - 1; }
 static_assert(SG_APRON >= 2 * SG_MAX_RADIUS, "apron must hold a block centred r outside the image");
-static_assert(SG_APRON_RIGHT >= 2 * SG_MAX_RADIUS + 1, "right apron must hold an 8-byte block-row read");
+static_assert(SG_APRON_RIGHT >= right_apron_needed(0) && SG_APRON_RIGHT >= right_apron_needed(1) &&
+                  SG_APRON_RIGHT >= right_apron_needed(2) && SG_APRON_RIGHT >= right_apron_needed(3) &&
+                  SG_MAX_RADIUS <= 3,
+              "right apron must hold the 8-byte block-row reads of every radius");
 __host__ __device__ __forceinline__ int stored_pitch(int width) {
   return width + SG_APRON + SG_APRON_RIGHT;
 }
