@@ -45,16 +45,28 @@ def _alg_bytes(n_pix: int, n_src: int, samples: int) -> dict:
     }
 
 
+GATHER_SOURCES = ("paper_2102_03011_amd/csrc/sg_kernels.hip", "paper_2102_03011_amd/csrc/sg_device.h",
+                  "paper_2102_03011_amd/csrc/sg_internal.h", "include/scene_gather.h")
+
+
+def gather_source_sha256() -> str:
+    """Hash of every source the gather and filter kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in GATHER_SOURCES:
+        h.update(rel.encode())
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def _measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
     or None when the kernel source changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2102_03011_amd", "csrc", "sg_kernels.hip")
     try:
         rec = json.load(open(path))["kernels"][kernel]
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = gather_source_sha256()
     except (OSError, KeyError, ValueError):
         return None
     if rec.get("source_sha256") != sha:
