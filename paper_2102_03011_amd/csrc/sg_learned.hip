@@ -483,6 +483,11 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   }
   if (wave_bad) last = -1;
   const int64_t re = last >= 0 ? px[last].e : rs;
+  // run ends relative to rs (a wave's records number far below 2^31), wave-uniform
+  int rend[kFlatPix];
+#pragma unroll
+  for (int j = 0; j < kFlatPix; ++j)
+    rend[j] = __builtin_amdgcn_readfirstlane(j <= last ? static_cast<int>(px[j].e - rs) : 0x7FFFFFFF);
 
   // 2. medians: four pixels at a time, 16 lanes each
   for (int r = 0; r < kFlatPix / 4; ++r) {
@@ -516,10 +521,12 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   for (int64_t base = rs; base < re; base += 64) {
     const int64_t idx = base + lane;
     bool live = idx < re;
-    // pixel of the record: the number of wave pixels whose range ends at or before it
+    // pixel of the record: the number of wave pixels whose range ends at or before
+    // it (32-bit compares against scalar registers)
     int k = 0;
+    const int ri = static_cast<int>(idx - rs);
 #pragma unroll
-    for (int j = 0; j < kFlatPix; ++j) k += (j <= last && px[j].e <= idx) ? 1 : 0;
+    for (int j = 0; j < kFlatPix; ++j) k += rend[j] <= ri ? 1 : 0;
     if (k > last) live = false;
     uint2 rec = make_uint2(0u, 0u);
     float feat[kNF] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
