@@ -4,7 +4,9 @@
 1280x720 with +-30 (120 frames, 40 + 3 moving boxes), generated on the GPU from
 their seeds. The HIP path runs in the benchmark's launch configuration (one
 output frame per call: count, size the arena, scatter, filter); the oracle
-computes the sampled pixels one by one.
+computes the sampled pixels one by one. At 1080p the learned-weight filter
+(shipped weights) also runs on the same sets and is checked against the float64
+oracle on the device's records of the sampled pixels.
 """
 import numpy as np
 import pytest
@@ -14,7 +16,7 @@ from oracle import filters as ofilters
 from oracle import gather as ogather
 from oracle import staging as ostaging
 from scenegen import configs, generate
-from tests import parity
+from tests import learned_ref, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +28,7 @@ def _window_planes(clip, f, w):
     return lo, col, dep
 
 
-def _check(wl, clip, staged, f, pixels, report):
+def _check(wl, clip, staged, f, pixels, report, learned=False):
     import paper_2102_03011_amd as sg
     params = sg.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
     sets = sg.scene_gather(staged, f, f + 1, params)
@@ -46,6 +48,20 @@ def _check(wl, clip, staged, f, pixels, report):
     band = parity.pixels_with_band_cases(orc)
     err = np.abs(got - want).max(axis=1)
     assert err[~band].max() <= parity.COLOUR_TOL
+    learned_err = None
+    if learned:
+        from paper_2102_03011_amd import train
+        mlp, _ = train.load_mlp()
+        lout = sg.scene_filter_learned(staged, sets, params, mlp)
+        torch.cuda.synchronize()
+        lgot = lout[0].reshape(-1, 3).cpu().numpy().astype(np.float64)[pixels]
+        off, ids, crho = learned_ref.records_subset(g_off, g_ids, g_crho, pixels)
+        x, lcol = learned_ref.raw_features(off, ids, crho, pixels, f - lo, dep, cams, clip.fx, clip.fy, clip.cx,
+                                           clip.cy, wl.window, wl.radius)
+        lwant = learned_ref.learned_filter(x, lcol, off, col[f - lo].reshape(-1, 3)[pixels],
+                                           learned_ref.oracle_mlp_from_device(mlp))
+        learned_err = float(np.abs(lgot - lwant).max())
+        assert learned_err <= parity.COLOUR_TOL, learned_err
     # mode F (unquantised inputs): reported, not gated
     colf = ostaging.colour_f(clip.rgb_u8[lo:lo + col.shape[0]].cpu().numpy())
     depf = ostaging.depth_f(clip.depth[lo:lo + col.shape[0]].cpu().numpy())
@@ -61,6 +77,7 @@ def _check(wl, clip, staged, f, pixels, report):
         "band_pixels": int(band.sum()), "max_colour_err_q": float(err[~band].max()),
         "modeF_membership_diff": len(key_g ^ key_f), "modeF_members": len(key_f),
         "modeF_colour_err_max": float(errf.max()), "modeF_colour_err_mean": float(errf.mean()),
+        "learned_colour_err_max": learned_err,
     })
     return sets
 
@@ -96,7 +113,7 @@ def test_full_scale_1080p_w50_sampled(report, full_clip, f):
     wl, clip, staged = full_clip
     rng = np.random.default_rng(f)
     pixels = np.sort(rng.choice(clip.width * clip.height, 2500, replace=False))
-    sets = _check(wl, clip, staged, f, pixels, report)
+    sets = _check(wl, clip, staged, f, pixels, report, learned=True)
     assert sets.total() > (1e8 if f == 150 else 5e7)
 
 
