@@ -4,6 +4,8 @@ One step = one output frame through the whole plain path: stage the frame that
 enters the window (u8/f32 -> binary16), pose prep + count + scan, scatter, filter.
 Inputs are synthetic (seeded ray-cast clip, 300 frames) and resident in HBM
 before timing starts; the sample arena is sized by an untimed planning count.
+The same frames also go through the fused gather + filter (no stored sets) and,
+unless --no-learned, the learned-weight filter.
 
 Prints ONE JSON line (rank 0, one GPU).
 """
@@ -104,6 +106,52 @@ def cpu_baseline(clip, wl, f: int, row_step: int) -> dict:
 
 MLP_FLOP_PER_SAMPLE = 2 * (8 * 64 + 64 * 64 + 64)   # 8 -> 64 -> 64 -> 1, multiply-adds x 2
 BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, stored_out, n_src) -> dict:
+    """scene_gather_filter on the same output frames as the timed plain steps (the
+    frame entering the window staged first, as there): whole step and kernel times,
+    the fused kernel's roofline (it reads every source pixel of the window's blocks
+    and writes the output: 8 B x sources x P + 8 B x P + 12 B x P), and its largest
+    difference from the stored path's output on the last frame."""
+    import torch
+    n, h, w = clip.n_frames, clip.height, clip.width
+    n_pix = h * w
+    ws = sg.alloc_workspace(staged, 0, 1, params)
+    out = torch.empty((1, h, w, 3), dtype=torch.float32, device=staged.rgbd.device)
+
+    def step(f, ev=None):
+        g = min(n - 1, f + wl.window)
+        sg.scene_stage_into(staged, clip.rgb_u8[g], clip.depth[g], g)
+        if ev is not None:
+            ev[0].record()
+        sg.scene_gather_filter(staged, f, f + 1, params, fparams, out=out, ws=ws)
+        if ev is not None:
+            ev[1].record()
+
+    step(timed[0])
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in timed]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for k, f in enumerate(timed):
+        step(f, evs[k])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / len(timed)
+    kms = sum(e[0].elapsed_time(e[1]) for e in evs) / len(timed)
+    samples = sum(totals[f] for f in timed) / len(timed)
+    alg = 8 * n_src * n_pix + 8 * n_pix + 12 * n_pix
+    diff = (out.double() - stored_out.double()).abs().max().item()
+    res = {"ms_per_step": ms, "kernel_ms": kms, "samples_per_s": samples / (ms / 1e3),
+           "output_mpix_per_s": n_pix / (ms / 1e3) / 1e6,
+           "roofline": {"bound": "hbm", "kernel": "gather_filter", "achieved": alg / (kms / 1e3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                        "alg_bytes_per_launch": alg},
+           "max_abs_diff_vs_stored_path": diff}
+    log(f"fused gather + filter: {ms:.3f} ms/step (kernel {kms:.3f}), {res['output_mpix_per_s']:.0f} Mpix/s, "
+        f"max |fused - stored| {diff:.2e}")
+    return res
 
 
 def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int, with_curve: bool = True) -> dict:
@@ -368,6 +416,7 @@ def main() -> int:
                     help="full: the 1080p +-50 headline workload; batched: 32 uneven clips per step")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--no-fused", action="store_true", help="skip the fused gather + filter leg")
     ap.add_argument("--no-curve", action="store_true",
                     help="learned leg at the workload's window only (no smaller-window curve)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -502,6 +551,8 @@ def main() -> int:
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if not args.no_fused:
+        res["fused"] = fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, out, n_src)
     if not args.no_learned:
         res["learned"] = learned_leg(sg, clip, staged, wl, params, fparams, frames[args.warmup:], ms_step,
                                      args.learned_steps, with_curve=not args.no_curve)

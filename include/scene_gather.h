@@ -183,6 +183,17 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
                        const sg_sample_sets* sets, const sg_filter_params* params,
                        float* out_rgb, void* stream);
 
+/* Gather + filter in one pass, without storing the sets (the paper's own flow,
+ * Sec. 4-5: samples are weighted as they are found). For output frames [f0, f1):
+ * the same projection, block and membership test as scene_gather, each member
+ * weighted as scene_filter weights its record (rho rounded to binary16 as a
+ * record stores it), so out_rgb (device [P][3] float32) equals scene_gather +
+ * scene_filter up to the order of the float32 additions; an empty set gives I^f(p).
+ * workspace: as for scene_gather (only the relative maps are written). */
+sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1,
+                              const sg_gather_params* params, const sg_filter_params* fparams,
+                              float* out_rgb, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Learned per-sample weights (replacing the hand-set weight of Sec. 5.1 Eq. 4 in
  * the weighted mean of Sec. 5 Eq. 3): O(p) = sum_s softmax(m)_s c_s over the set of

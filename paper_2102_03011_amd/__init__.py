@@ -276,6 +276,26 @@ def scene_filter(clip: StagedClip, sets: SampleSets, params: FilterParams, out: 
     return out
 
 
+def scene_gather_filter(clip: StagedClip, f0: int, f1: int, params: GatherParams, fparams: FilterParams,
+                        out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Gather + plain filter in one pass, no stored sets -> [f1 - f0, H, W, 3] float32
+    (equal to scene_filter(scene_gather(...)) up to float32 addition order)."""
+    shape = (f1 - f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    if ws is None:
+        ws = alloc_workspace(clip, f0, f1, params)
+    _need_gpu(ws, "ws")
+    cc, pp, fp = clip.c_struct(), params.c_struct(), fparams.c_struct()
+    _check(_lib.scene_gather_filter(ctypes.byref(cc), f0, f1, ctypes.byref(pp), ctypes.byref(fp), out.data_ptr(),
+                                    ws.data_ptr(), ws.numel() * ws.element_size(), _stream_handle()),
+           "scene_gather_filter")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # learned per-sample weights
 

@@ -86,6 +86,9 @@ SIGNATURES = {
     "scene_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(SgSampleSets), ctypes.POINTER(SgFilterParams),
                                      c_void_p, c_void_p]),
+    "scene_gather_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgFilterParams),
+                                            c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),

@@ -76,6 +76,21 @@ sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_p
   return SG_OK;
 }
 
+// Filter weights as exp2 arguments: a = -log2(e) / (2 sigma^2); each sigma must be
+// > 0 (+inf allowed, disabling its term).
+sg_status filter_scales(const sg_filter_params* params, sg::FilterJob* fj) {
+  const float sd = params->sigma_d, sc = params->sigma_c, stt = params->sigma_t;
+  if (!(sd > 0.0f) || !(sc > 0.0f) || !(stt > 0.0f)) return SG_E_INVALID;
+  const bool use_c = isfinite(sc), use_t = isfinite(stt);
+  const double log2e = 1.4426950408889634;
+  fj->a_d = isfinite(sd) ? static_cast<float>(-log2e / (2.0 * sd * static_cast<double>(sd))) : 0.0f;
+  fj->a_c = use_c ? static_cast<float>(-log2e / (2.0 * sc * static_cast<double>(sc))) : 0.0f;
+  fj->a_t = use_t ? static_cast<float>(-log2e / (2.0 * stt * static_cast<double>(stt))) : 0.0f;
+  fj->use_colour = use_c;
+  fj->use_time = use_t;
+  return SG_OK;
+}
+
 sg_status run_count(const sg::GatherJob& jb, hipStream_t st) {
   sg_status s = hip_status(sg::launch_pose_prep(jb, st));
   if (s != SG_OK) return s;
@@ -162,14 +177,10 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
   if (window > SG_MAX_WINDOW) return SG_E_UNSUPPORTED;
   if (sets == nullptr || sets->offsets == nullptr || params == nullptr || out_rgb == nullptr)
     return SG_E_INVALID;
-  const float sd = params->sigma_d, sc = params->sigma_c, stt = params->sigma_t;
-  // each sigma must be > 0 (+inf allowed, disabling its term)
-  if (!(sd > 0.0f) || !(sc > 0.0f) || !(stt > 0.0f)) return SG_E_INVALID;
-  const bool use_c = isfinite(sc), use_t = isfinite(stt);
-  if (sets->capacity < 0 || (sets->capacity > 0 && sets->crho == nullptr)) return SG_E_INVALID;
-  if (use_t && sets->capacity > 0 && sets->ids == nullptr) return SG_E_INVALID;
-  const double log2e = 1.4426950408889634;
   sg::FilterJob fj{};
+  if ((s = filter_scales(params, &fj)) != SG_OK) return s;
+  if (sets->capacity < 0 || (sets->capacity > 0 && sets->crho == nullptr)) return SG_E_INVALID;
+  if (fj.use_time && sets->capacity > 0 && sets->ids == nullptr) return SG_E_INVALID;
   fj.width = clip->width;
   fj.height = clip->height;
   fj.f0 = f0;
@@ -180,13 +191,44 @@ sg_status scene_filter(const sg_clip* clip, int32_t f0, int32_t f1, int32_t wind
   fj.ids = sets->ids;
   fj.crho = sets->crho;
   fj.capacity = sets->capacity;
-  fj.a_d = isfinite(sd) ? static_cast<float>(-log2e / (2.0 * sd * static_cast<double>(sd))) : 0.0f;
-  fj.a_c = use_c ? static_cast<float>(-log2e / (2.0 * sc * static_cast<double>(sc))) : 0.0f;
-  fj.a_t = use_t ? static_cast<float>(-log2e / (2.0 * stt * static_cast<double>(stt))) : 0.0f;
-  fj.use_colour = use_c;
-  fj.use_time = use_t;
   fj.out = out_rgb;
   return hip_status(sg::launch_filter(fj, static_cast<hipStream_t>(stream)));
+}
+
+sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                              const sg_filter_params* fparams, float* out_rgb, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  sg_status s = check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if ((s = check_params(params)) != SG_OK) return s;
+  if (fparams == nullptr || out_rgb == nullptr || workspace == nullptr) return SG_E_INVALID;
+  sg::FilterJob fj{};
+  if ((s = filter_scales(fparams, &fj)) != SG_OK) return s;
+  const Layout l = layout(clip, f0, f1, params);
+  if (workspace_bytes < l.total) return SG_E_INVALID;
+  sg::GatherJob jb{};
+  jb.width = clip->width;
+  jb.height = clip->height;
+  jb.n_frames = clip->num_frames;
+  jb.f0 = f0;
+  jb.n_out = f1 - f0;
+  jb.w = params->window;
+  jb.radius = params->radius;
+  jb.tol = params->tol;
+  jb.z_near = params->z_near;
+  jb.fx = clip->fx;
+  jb.fy = clip->fy;
+  jb.cx = clip->cx;
+  jb.cy = clip->cy;
+  jb.c2w = clip->cam_to_world;
+  jb.rgbd = clip->rgbd;
+  jb.depth = clip->depth;
+  jb.rel = reinterpret_cast<float*>(static_cast<char*>(workspace) + l.rel_off);
+  fj.out = out_rgb;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = hip_status(sg::launch_pose_prep(jb, st))) != SG_OK) return s;
+  return hip_status(sg::launch_gather_filter(jb, fj, st));
 }
 
 static sg_status learned_prepare(const sg_clip* clip, int32_t f0, int32_t f1,

@@ -147,6 +147,7 @@ hipError_t launch_count(const GatherJob& jb, hipStream_t st);
 hipError_t launch_scan(int64_t* offsets, int64_t n, int64_t* partial, hipStream_t st);
 hipError_t launch_scatter(const GatherJob& jb, hipStream_t st);
 hipError_t launch_filter(const FilterJob& fj, hipStream_t st);
+hipError_t launch_gather_filter(const GatherJob& jb, const FilterJob& fj, hipStream_t st);
 
 }  // namespace sg
 

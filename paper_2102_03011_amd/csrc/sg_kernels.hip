@@ -544,6 +544,82 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
 }
 
 // ---------------------------------------------------------------------------
+// Fused gather + plain filter (no record arena): each lane walks its output
+// pixel's window like the gather passes (same projection, same block, same
+// membership test) and accumulates the filter's weighted sums directly, with rho
+// rounded to binary16 exactly as a stored record holds it. The result equals
+// scene_gather + scene_filter up to the order of the float32 additions.
+template <int R, bool kColour, bool kTime>
+__global__ __launch_bounds__(256) void k_gather_filter(const uint2* __restrict__ rgbd_, const float* __restrict__ rel,
+                                                       int width, int height, int n_frames, int f0, int w,
+                                                       float tol, float z_near, float a_d, float a_c, float a_t,
+                                                       float* __restrict__ out) {
+  constexpr int kSide = 2 * R + 1;
+  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
+  const int x = tile.tx * kTileW + threadIdx.x;
+  const int y = tile.ty * kTileH + threadIdx.y;
+  const int fo = tile.fo;
+  if (x >= width || y >= height) return;
+  gp<const uint2> rgbd = to_global(rgbd_);
+  gp<const float> relf = to_global(rel) + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
+  const int f = f0 + fo;
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const uint2 ref = ld2(rgbd + static_cast<size_t>(f) * pplane + padded_index(x, y, pw));
+  const float cr = h2f(ref.x), cg = h2f(ref.x >> 16), cb = h2f(ref.y);
+  const float dp = h2f(ref.y >> 16);  // the depth channel holds the depth plane's binary16
+  float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+  int n = 0;
+  if (dp > z_near && dp < INFINITY) {
+    const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
+    const float fxp = static_cast<float>(x), fyp = static_cast<float>(y);
+    for (int j = jlo; j <= jhi; ++j) {
+      Projected p;
+      if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) continue;
+      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
+      uint2 px[kSide][kSide];
+#pragma unroll
+      for (int dy = 0; dy < kSide; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (dy - R) * pw + (dx - R));
+      const float dj = static_cast<float>(j - f);
+#pragma unroll
+      for (int k = 0; k < kSide * kSide; ++k) {
+        const uint2 v = px[k / kSide][k % kSide];
+        if (!accept16(v.y >> 16, p)) continue;
+        // rho exactly as the scatter stores it
+        half2v bd = __builtin_bit_cast(half2v, v.y);
+        const float rho = static_cast<float>(static_cast<_Float16>(fmaf(static_cast<float>(bd.y), p.inv, -1.0f)));
+        const float r = h2f(v.x), g = h2f(v.x >> 16), b = h2f(v.y);
+        float arg = a_d * rho * rho;
+        if (kColour) {
+          const float er = r - cr, eg = g - cg, eb = b - cb;
+          arg = fmaf(a_c, fmaf(er, er, fmaf(eg, eg, eb * eb)), arg);
+        }
+        if (kTime) arg = fmaf(a_t, dj * dj, arg);
+        const float wt = __builtin_amdgcn_exp2f(arg);
+        wsum += wt;
+        ar = fmaf(wt, r, ar);
+        ag = fmaf(wt, g, ag);
+        ab = fmaf(wt, b, ab);
+        ++n;
+      }
+    }
+  }
+  gp<float> o = to_global(out) + (static_cast<size_t>(fo) * width * height + static_cast<size_t>(y) * width + x) * 3;
+  if (n > 0) {
+    const float inv = 1.0f / wsum;
+    o[0] = ar * inv;
+    o[1] = ag * inv;
+    o[2] = ab * inv;
+  } else {
+    o[0] = cr;
+    o[1] = cg;
+    o[2] = cb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a4: scan. counts live in offsets[1..P]; three phases turn them into an
 // inclusive scan in place, and offsets[0] = 0.
 
@@ -981,6 +1057,34 @@ hipError_t launch_scatter(const GatherJob& jb, hipStream_t st) {
     case 1: scatter_r<1>(jb, g, st); break;
     case 2: scatter_r<2>(jb, g, st); break;
     default: scatter_r<3>(jb, g, st); break;
+  }
+  return hipGetLastError();
+}
+
+template <int R>
+static void gather_filter_r(const GatherJob& jb, const FilterJob& fj, dim3 g, hipStream_t st) {
+  const uint2* rgbd = reinterpret_cast<const uint2*>(jb.rgbd);
+#define SG_FUSED(C, T)                                                                                     \
+  hipLaunchKernelGGL((k_gather_filter<R, C, T>), g, dim3(kTileW, kTileH), 0, st, rgbd, jb.rel, jb.width,    \
+                     jb.height, jb.n_frames, jb.f0, jb.w, jb.tol, jb.z_near, fj.a_d, fj.a_c, fj.a_t, fj.out)
+  if (fj.use_colour && fj.use_time)
+    SG_FUSED(true, true);
+  else if (fj.use_colour)
+    SG_FUSED(true, false);
+  else if (fj.use_time)
+    SG_FUSED(false, true);
+  else
+    SG_FUSED(false, false);
+#undef SG_FUSED
+}
+
+hipError_t launch_gather_filter(const GatherJob& jb, const FilterJob& fj, hipStream_t st) {
+  const dim3 g = gather_grid(jb);
+  switch (jb.radius) {
+    case 0: gather_filter_r<0>(jb, fj, g, st); break;
+    case 1: gather_filter_r<1>(jb, fj, g, st); break;
+    case 2: gather_filter_r<2>(jb, fj, g, st); break;
+    default: gather_filter_r<3>(jb, fj, g, st); break;
   }
   return hipGetLastError();
 }

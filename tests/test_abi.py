@@ -162,6 +162,36 @@ def test_filter_rejects_bad_arguments(native, case):
     assert lib.scene_filter(ctypes.byref(c), f0, f1, w, sp, ctypes.byref(fp), out, None) == 1
 
 
+@pytest.mark.parametrize("case", ["null_clip", "bad_range", "big_radius", "null_fparams", "sigma_zero", "null_out",
+                                  "null_ws", "small_ws"])
+def test_gather_filter_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    fp = mod.SgFilterParams(0.01, math.inf, math.inf, 0.0)
+    f0, f1 = 0, 2
+    need = ctypes.c_size_t(0)
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), f0, f1, ctypes.byref(p), ctypes.byref(need)) == 0
+    cp, fpp, out, ws, wsb, expect = ctypes.byref(c), ctypes.byref(fp), 0x90000, 0xA0000, need.value, 1
+    if case == "null_clip":
+        cp = None
+    elif case == "bad_range":
+        f1 = 0
+    elif case == "big_radius":
+        p.radius, expect = 4, 4
+    elif case == "null_fparams":
+        fpp = None
+    elif case == "sigma_zero":
+        fp.sigma_d = 0.0
+    elif case == "null_out":
+        out = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb -= 1
+    assert lib.scene_gather_filter(cp, f0, f1, ctypes.byref(p), fpp, out, ws, wsb, None) == expect, case
+
+
 def test_stage_rejects_bad_arguments(native):
     mod, lib = native
     assert lib.scene_stage(None, 0x1000, 10, 64, 32, 0x2000, 0x3000, None) == 1

@@ -48,6 +48,10 @@ def _check(wl, clip, staged, f, pixels, report, learned=False):
     band = parity.pixels_with_band_cases(orc)
     err = np.abs(got - want).max(axis=1)
     assert err[~band].max() <= parity.COLOUR_TOL
+    # the fused gather + filter (no stored sets) equals the stored path up to float32 addition order
+    fused = sg.scene_gather_filter(staged, f, f + 1, params, sg.FilterParams(sigma_d=wl.sigma_d))
+    fused_diff = float((fused[0].double() - out[0].double()).abs().max().item())
+    assert fused_diff <= parity.FILTER_ARITH_TOL, fused_diff
     learned_err = None
     if learned:
         from paper_2102_03011_amd import train
@@ -77,7 +81,7 @@ def _check(wl, clip, staged, f, pixels, report, learned=False):
         "band_pixels": int(band.sum()), "max_colour_err_q": float(err[~band].max()),
         "modeF_membership_diff": len(key_g ^ key_f), "modeF_members": len(key_f),
         "modeF_colour_err_max": float(errf.max()), "modeF_colour_err_mean": float(errf.mean()),
-        "learned_colour_err_max": learned_err,
+        "learned_colour_err_max": learned_err, "fused_vs_stored_max": fused_diff,
     })
     return sets
 

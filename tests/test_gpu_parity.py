@@ -232,3 +232,61 @@ def test_wide_frame_at_pixel_limit():
     rng = np.random.default_rng(0)
     pix = np.sort(rng.choice(4096 * 1024, 3000, replace=False))
     _check_frames(wl, clip, staged, col, dep, rgbd, 1, 2, params, pixels=pix)
+
+
+# ---------------------------------------------------------------------------
+# fused gather + filter (no stored sets)
+
+def _fused_vs_stored(staged, f0, f1, params, fparams):
+    sg = _sg()
+    sets = sg.scene_gather(staged, f0, f1, params)
+    stored = sg.scene_filter(staged, sets, fparams)
+    fused = sg.scene_gather_filter(staged, f0, f1, params, fparams)
+    torch.cuda.synchronize()
+    sets.check()
+    a = fused.cpu().numpy().astype(np.float64)
+    b = stored.cpu().numpy().astype(np.float64)
+    # same members, same weights: only the order of the float32 additions differs
+    assert np.isfinite(a).all()
+    assert np.abs(a - b).max() <= parity.FILTER_ARITH_TOL, np.abs(a - b).max()
+    empty = (np.diff(sets.offsets.cpu().numpy()) == 0).reshape(a.shape[:3])
+    assert np.array_equal(a[empty], b[empty])   # the output pixel's own colour, exactly
+    return a, empty
+
+
+@pytest.mark.parametrize("radius,window,preset", [(1, 23, "depth"), (1, 23, "paper"), (0, 3, "depth"),
+                                                   (2, 2, "paper"), (3, 1, "depth")])
+def test_fused_gather_filter_equals_stored_path_and_oracle(small, radius, window, preset):
+    wl, clip, staged, col, dep, rgbd = small
+    sg = _sg()
+    params = sg.GatherParams(window=window, radius=radius, tol=wl.tol if radius == 1 else 0.02, z_near=wl.z_near)
+    fparams = (sg.FilterParams(sigma_d=0.01) if preset == "depth"
+               else sg.FilterParams(sigma_d=0.01, sigma_c=40.0 / 255.0, sigma_t=6.0))
+    f0, f1 = 5, 8
+    fused, _ = _fused_vs_stored(staged, f0, f1, params, fparams)
+    # end to end against the oracle's own sets for one of the frames (band pixels excluded)
+    oprm = ogather.GatherParams(window=window, radius=radius, tol=params.tol, z_near=params.z_near)
+    f = 6
+    orc = ogather.gather_frame(col, dep, clip.cam_to_world.numpy(), clip.fx, clip.fy, clip.cx, clip.cy, f, oprm)
+    want = ofilters.filter_sets(orc, col[f], window, fparams.sigma_d, fparams.sigma_c, fparams.sigma_t)
+    band = parity.pixels_with_band_cases(orc)
+    err = np.abs(fused[f - f0].reshape(-1, 3) - want).max(axis=1)
+    assert err[~band].max() <= parity.COLOUR_TOL
+
+
+def test_fused_gather_filter_ragged_and_invalid_depths():
+    wl = configs.tiny(seed=9, width=100, height=37, n_frames=7, window=3, pose_rot_deg=1.0, pose_trans_m=0.03)
+    clip = generate(wl.spec)
+    d = clip.depth.clone()
+    g = torch.Generator().manual_seed(5)
+    m = torch.rand(d.shape, generator=g)
+    d[m < 0.03] = float("nan")
+    d[(m >= 0.03) & (m < 0.05)] = 0.0
+    d[(m >= 0.05) & (m < 0.06)] = float("inf")
+    d[(m >= 0.06) & (m < 0.07)] = 0.005
+    clip.depth = d
+    staged = _stage(clip)
+    sg = _sg()
+    params = sg.GatherParams(window=3, radius=1, tol=0.01, z_near=0.01)
+    _, empty = _fused_vs_stored(staged, 0, 7, params, sg.FilterParams(sigma_d=0.01))
+    assert empty.sum() > 100
