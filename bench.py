@@ -556,6 +556,13 @@ def main() -> int:
     if not args.no_learned:
         res["learned"] = learned_leg(sg, clip, staged, wl, params, fparams, frames[args.warmup:], ms_step,
                                      args.learned_steps, with_curve=not args.no_curve)
+    if "fused" in res and "learned" in res and "curve" in res["learned"]:
+        # the learned path against the fused plain path's time as well: the largest
+        # window whose learned step is no slower (None if none is)
+        fit = [r for r in res["learned"]["curve"] if r["ms_per_step"] <= res["fused"]["ms_per_step"]]
+        res["learned"]["equal_time_vs_fused_plain"] = (
+            {**max(fit, key=lambda r: r["window"]), "fused_plain_ms_per_step": res["fused"]["ms_per_step"]}
+            if fit else None)
     if args.copy_probe:
         x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
