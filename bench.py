@@ -147,7 +147,7 @@ def fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, stored_out, 
            "output_mpix_per_s": n_pix / (ms / 1e3) / 1e6,
            "roofline": {"bound": "hbm", "kernel": "gather_filter", "achieved": alg / (kms / 1e3) / 1e9,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                        "alg_bytes_per_launch": alg},
+                        "alg_bytes_per_launch": alg, "traffic": _measured_traffic("gather_filter")},
            "max_abs_diff_vs_stored_path": diff}
     log(f"fused gather + filter: {ms:.3f} ms/step (kernel {kms:.3f}), {res['output_mpix_per_s']:.0f} Mpix/s, "
         f"max |fused - stored| {diff:.2e}")
