@@ -54,6 +54,10 @@ extern "C" {
 #define SG_APRON_RIGHT 7
 #define SG_MAX_WINDOW 511
 #define SG_MAX_RADIUS 3
+/* One call's output frames f0 .. f1 - 1 are gathered as one launch of workgroups
+ * of 256 pixels (64 x 4 tiles, 16 x 16 in scene_gather_filter): the number of
+ * tiles, (f1 - f0) ceil(W / 64) ceil(H / 4) and (f1 - f0) ceil(W / 16) ceil(H / 16),
+ * must stay below 2^31, else SG_E_UNSUPPORTED (split the range into calls). */
 #define SG_ID_SHIFT 22
 
 /* Device status bits (OR-ed into sg_sample_sets.status). */

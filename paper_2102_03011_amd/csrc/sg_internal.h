@@ -12,6 +12,8 @@ namespace sg {
 constexpr int kRelStride = 16;    // floats per (output frame, source frame) map record
 constexpr int kTileW = 64;        // gather tile: one wave per 64-pixel row segment
 constexpr int kTileH = 4;         // four waves per workgroup
+constexpr int kFuseW = 16;        // fused gather + filter tile: 16 x 16 pixels,
+constexpr int kFuseH = 16;        //   four waves of 16 x 4
 constexpr int kScanThreads = 256;
 constexpr int kScanTile = 4096;   // elements per scan block (16 per thread)
 constexpr int kGroup = 16;        // filter lanes per output pixel

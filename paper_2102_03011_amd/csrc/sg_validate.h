@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "scene_gather.h"
+#include "sg_internal.h"
 
 namespace sg {
 
@@ -24,8 +25,16 @@ inline sg_status check_clip(const sg_clip* c, bool need_depth) {
   return SG_OK;
 }
 
+// Workgroups of one gather launch over n_out output frames with tw x th tiles.
+inline int64_t gather_tiles(const sg_clip* c, int64_t n_out, int tw, int th) {
+  return n_out * ((c->width + tw - 1) / tw) * ((c->height + th - 1) / th);
+}
+
 inline sg_status check_range(const sg_clip* c, int32_t f0, int32_t f1) {
   if (f0 < 0 || f1 <= f0 || f1 > c->num_frames) return SG_E_INVALID;
+  // the kernels index their 1-D grid with int
+  if (gather_tiles(c, f1 - f0, kTileW, kTileH) > INT32_MAX || gather_tiles(c, f1 - f0, kFuseW, kFuseH) > INT32_MAX)
+    return SG_E_UNSUPPORTED;
   return SG_OK;
 }
 

@@ -192,6 +192,20 @@ def test_gather_filter_rejects_bad_arguments(native, case):
     assert lib.scene_gather_filter(cp, f0, f1, ctypes.byref(p), fpp, out, ws, wsb, None) == expect, case
 
 
+def test_range_beyond_the_int_grid_is_unsupported(native):
+    # 1 x 2^22 frames: 2^20 tiles of 64 x 4 per output frame, so 2047 output frames
+    # fit an int-indexed grid and 2048 (2^31 tiles) do not
+    mod, lib = native
+    c = _clip(mod, w=1, h=1 << 22, n=4096)
+    p = mod.SgGatherParams(1, 1, 0.01, 0.01)
+    fp = mod.SgFilterParams(0.01, math.inf, math.inf, 0.0)
+    need = ctypes.c_size_t(0)
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), 0, 2047, ctypes.byref(p), ctypes.byref(need)) == 0
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), 0, 2048, ctypes.byref(p), ctypes.byref(need)) == 4
+    assert lib.scene_gather_filter(ctypes.byref(c), 0, 2048, ctypes.byref(p), ctypes.byref(fp), 0x90000, 0xA0000,
+                                   1 << 40, None) == 4
+
+
 def test_stage_rejects_bad_arguments(native):
     mod, lib = native
     assert lib.scene_stage(None, 0x1000, 10, 64, 32, 0x2000, 0x3000, None) == 1
