@@ -16,7 +16,9 @@ Video Processing):
   poses      -- camera matrices C^f, their inverses and relative products (Sec. 3, Sec. 4 Eq. 1-2)
   gather     -- sample sets S^f(p) with the depth-guided frustum test (Sec. 4)
   filters    -- weighted mean O(p) = sum w(s) s_rgb / W (Sec. 5 Eq. 3) with the
-                Gaussian denoising weight around the reference sample (Sec. 5.1 Eq. 4)
+                Gaussian denoising weight around the reference sample (Sec. 5.1 Eq. 4);
+                the per-frame factors of deblurring (Sec. 6 Eq. 5) and computational
+                shutters (Eq. 10); inpainting by masked mean-shift (Eq. 8-9)
   bruteforce -- all-pairs twin of `gather` for tiny inputs (pure Python loops)
   metrics    -- PSNR (Sec. 5.1, denoising PSNR figure)
 

@@ -59,3 +59,87 @@ def sample_weight_sum(sets: OracleSets, sigma_d: float) -> np.ndarray:
     n = sets.offsets.size - 1
     seg = np.repeat(np.arange(n), np.diff(sets.offsets))
     return np.bincount(seg, weights=_factor(sets.rho ** 2, sigma_d), minlength=n)
+
+
+# ---------------------------------------------------------------------------
+# The paper's other filters over the same sets (Sec. 6).
+
+def frame_weighted_mean(sets: OracleSets, colour_f: np.ndarray, window: int, frame_w: np.ndarray,
+                        sigma_d: float, sigma_c: float = math.inf, sigma_t: float = math.inf) -> np.ndarray:
+    """Eq. 3 with the weight of Eq. 4 multiplied by a per-source-frame factor
+    frame_w[J] (J = the frame the sample came from, absolute index):
+      deblurring (Sec. 6, Eq. 5): frame_w[J] = B(J), the frame's summed gradient magnitude;
+      computational shutter (Sec. 6, Eq. 10): frame_w[J] = xi(J) with every sigma +inf.
+    Reading: a set whose weights sum to zero (empty, or every sample on a frame of
+    factor 0) returns the input colour I^f(p). Returns [n, 3] float64."""
+    n = sets.offsets.size - 1
+    counts = np.diff(sets.offsets)
+    seg = np.repeat(np.arange(n), counts)
+    c_ref = colour_f.reshape(-1, 3)[sets.pixels]
+    dj = (sets.ids.astype(np.int64) >> ID_SHIFT) - window
+    src_frame = sets.frame + dj
+    dc2 = np.sum((sets.colour - c_ref[seg]) ** 2, axis=1)
+    w = (_factor(sets.rho * sets.rho, sigma_d) * _factor(dc2, sigma_c) * _factor(dj.astype(np.float64) ** 2, sigma_t)
+         * np.asarray(frame_w, dtype=np.float64)[src_frame])
+    wsum = np.bincount(seg, weights=w, minlength=n)
+    out = np.empty((n, 3))
+    for ch in range(3):
+        out[:, ch] = np.bincount(seg, weights=w * sets.colour[:, ch], minlength=n)
+    none = wsum == 0.0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        out = out / wsum[:, None]
+    out[none] = c_ref[none]
+    return out
+
+
+def frame_sharpness(colour: np.ndarray) -> np.ndarray:
+    """B(J) of Eq. 5: the sum over the pixels q of frame J of |grad I^J(q)|.
+    Reading (the paper names the gradient operator only): forward differences
+    gx = I(x + 1, y) - I(x, y), gy = I(x, y + 1) - I(x, y) of each colour channel,
+    |grad I(q)| = sqrt(sum over channels of gx^2 + gy^2), summed over the pixels
+    whose right and lower neighbours lie in the image. colour [N, H, W, 3] -> [N]."""
+    c = np.asarray(colour, dtype=np.float64)
+    gx = c[:, :-1, 1:, :] - c[:, :-1, :-1, :]
+    gy = c[:, 1:, :-1, :] - c[:, :-1, :-1, :]
+    mag = np.sqrt(np.sum(gx * gx + gy * gy, axis=3))
+    return mag.reshape(c.shape[0], -1).sum(axis=1)
+
+
+def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask: np.ndarray,
+                       sigma_rgb: float, steps: int = 2) -> np.ndarray:
+    """Inpainting (Sec. 6, Eq. 8-9) for the output pixels of frame sets.frame.
+
+    mask [N, H, W] bool: M^J(q), True = the pixel shows content to remove.
+    For an output pixel with M^f(p) = 1: s_ref starts as the mean colour of all
+    samples of S(p) (Eq. 8); each step replaces it with the weighted mean of the
+    samples, weight exp(-|s_ref - c_s|^2 / (2 sigma_rgb^2)) for a sample whose
+    source pixel is unmasked and 0 for a masked one (Eq. 9); the output is s_ref
+    after `steps` steps (the paper uses two). Readings: only the colour dimensions
+    are used (the paper gives sigma_rgb alone); the initial mean takes every sample,
+    masked ones included, as Eq. 8 is written; an unmasked output pixel, an empty
+    set, or a step whose weights sum to zero returns I^f(p). Returns [n, 3] float64."""
+    h, w_img = colour_f.shape[:2]
+    c_ref = colour_f.reshape(-1, 3)[sets.pixels]
+    dj = (sets.ids.astype(np.int64) >> ID_SHIFT) - window
+    q = (sets.ids.astype(np.int64) & ((1 << ID_SHIFT) - 1))
+    src_masked = np.asarray(mask, dtype=bool).reshape(mask.shape[0], -1)[sets.frame + dj, q]
+    out_masked = np.asarray(mask, dtype=bool)[sets.frame].reshape(-1)[sets.pixels]
+    out = c_ref.copy()
+    for i in range(sets.pixels.size):
+        a, b = sets.offsets[i], sets.offsets[i + 1]
+        if not out_masked[i] or b == a:
+            continue
+        cs = sets.colour[a:b]
+        keep = ~src_masked[a:b]
+        s_ref = cs.mean(axis=0)
+        ok = True
+        for _ in range(steps):
+            wgt = np.where(keep, np.exp(-np.sum((cs - s_ref) ** 2, axis=1) / (2.0 * sigma_rgb * sigma_rgb)), 0.0)
+            tot = wgt.sum()
+            if tot == 0.0:
+                ok = False
+                break
+            s_ref = (wgt[:, None] * cs).sum(axis=0) / tot
+        if ok:
+            out[i] = s_ref
+    return out
