@@ -4,7 +4,8 @@ One step = one output frame through the whole plain path: stage the frame that
 enters the window (u8/f32 -> binary16), pose prep + count + scan, scatter, filter.
 Inputs are synthetic (seeded ray-cast clip, 300 frames) and resident in HBM
 before timing starts; the sample arena is sized by an untimed planning count.
-The same frames also go through the fused gather + filter (no stored sets) and,
+The same frames also go through the fused gather + filter (no stored sets), the
+last frame's sets through the paper's deblurring and inpainting filters, and,
 unless --no-learned, the learned-weight filter.
 
 Prints ONE JSON line (rank 0, one GPU).
@@ -151,6 +152,57 @@ def fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, stored_out, 
            "max_abs_diff_vs_stored_path": diff}
     log(f"fused gather + filter: {ms:.3f} ms/step (kernel {kms:.3f}), {res['output_mpix_per_s']:.0f} Mpix/s, "
         f"max |fused - stored| {diff:.2e}")
+    return res
+
+
+def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
+    """The paper's other filters on the stored sets of output frame f (the last
+    timed frame): the frame sharpness B(J) over the whole clip once, then `reps`
+    calls each of the plain filter, the deblurring filter (Eq. 5: B(J) times the
+    Eq. 4 weight with the paper's colour and frame sigmas) and inpainting (Eq. 8-9,
+    two steps, sigma 55/255) under a moving box mask over ~10 % of each frame.
+    HIP event times on the stream the kernels run on; algorithmic bytes of the
+    frame filters: 12 B per record (colour + rho, id) + 28 B per pixel (offsets,
+    own colour, output)."""
+    import torch
+    n, h, w = clip.n_frames, clip.height, clip.width
+    dev = staged.rgbd.device
+    sets = sg.SampleSets(f, f + 1, wl.window, arena.offsets, arena.ids, arena.crho, arena.status)
+    n_rec = sets.total()
+    out = torch.empty((1, h, w, 3), dtype=torch.float32, device=dev)
+    mask = torch.zeros((n, h, w), dtype=torch.uint8, device=dev)
+    bw, bh = w // 3, h // 3   # ~11 % of the frame, moving right 4 px per frame
+    for j in range(n):
+        xa = min(w, w // 6 + 4 * j)
+        mask[j, h // 3:h // 3 + bh, xa:min(w, xa + bw)] = 1
+    deblur = sg.FilterParams(sigma_d=fparams.sigma_d, sigma_c=200.0 / 255.0, sigma_t=20.0)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    bj = torch.empty((n,), dtype=torch.float32, device=dev)
+    ms_sharp = timed(lambda: sg.scene_frame_sharpness(staged, out=bj), 3)
+    ms_plain = timed(lambda: sg.scene_filter(staged, sets, fparams, out=out), reps)
+    ms_deblur = timed(lambda: sg.scene_filter_frames(staged, sets, deblur, bj, out=out), reps)
+    ms_inpaint = timed(lambda: sg.scene_inpaint(staged, sets, mask, 55.0 / 255.0, 2, out=out), reps)
+    alg = 12 * n_rec + 28 * h * w
+    res = {"output_frame": f, "records": n_rec, "frames": n,
+           "frame_sharpness_ms_per_clip": ms_sharp,
+           "plain_filter_ms": ms_plain, "deblur_filter_ms": ms_deblur,
+           "deblur_roofline": {"bound": "hbm", "achieved": alg / (ms_deblur / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": alg / (ms_deblur / 1e3) / 1e9 / HBM_PEAK_GBS,
+                               "alg_bytes_per_launch": alg},
+           "inpaint_ms": ms_inpaint, "inpaint_masked_fraction": float(mask[f].float().mean().item())}
+    log(f"filters: B(J) {ms_sharp:.3f} ms/clip, plain {ms_plain:.3f}, deblur {ms_deblur:.3f}, "
+        f"inpaint {ms_inpaint:.3f} ms/frame")
     return res
 
 
@@ -417,6 +469,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-fused", action="store_true", help="skip the fused gather + filter leg")
+    ap.add_argument("--no-filters", action="store_true",
+                    help="skip the deblurring / inpainting filters leg")
     ap.add_argument("--no-curve", action="store_true",
                     help="learned leg at the workload's window only (no smaller-window curve)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -551,6 +605,8 @@ def main() -> int:
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if not args.no_filters:
+        res["filters"] = filters_leg(sg, clip, staged, wl, arena, timed[-1], fparams, max(3, args.steps))
     if not args.no_fused:
         res["fused"] = fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, out, n_src)
     if not args.no_learned:

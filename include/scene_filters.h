@@ -1,0 +1,70 @@
+/* scene_filters.h -- the paper's other filters over stored sample sets (HIP, gfx950).
+ *
+ * Klose et al., Sampling Based Scene-Space Video Processing, Sec. 6: deblurring
+ * (Eq. 5), computational scene-space shutters (Eq. 10) and inpainting (Eq. 8-9)
+ * reduce the same sample sets S(p) as the denoising filter of scene_gather.h with
+ * other weights. The sets, clip and status conventions are those of
+ * scene_gather.h: every pointer named "device" is device memory owned by the
+ * caller and borrowed for the call on `stream` (a hipStream_t, NULL = the null
+ * stream); arguments are checked on the host before any GPU work, and a failed
+ * check returns SG_E_INVALID or SG_E_UNSUPPORTED without enqueuing anything; a
+ * failing HIP call returns SG_E_HIP. No call allocates device memory.
+ */
+#ifndef SCENE_FILTERS_H
+#define SCENE_FILTERS_H
+
+#include "scene_gather.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_MAX_INPAINT_STEPS 16
+
+/* Blurriness measure of Eq. 5 for every frame J of the clip:
+ *   B(J) = sum over pixels q of |grad I^J(q)|,
+ * from the stored binary16 colours, with forward differences
+ * gx = I(x + 1, y) - I(x, y), gy = I(x, y + 1) - I(x, y) per channel and
+ * |grad I(q)| = sqrt(sum over r, g, b of gx^2 + gy^2), over the pixels whose right
+ * and lower neighbours lie in the image (the paper names the operator only).
+ * Magnitudes in float32, sums in float64 in a fixed order (bit-reproducible).
+ * out_b: device [num_frames] float32, every entry written.
+ * Needs clip->rgbd only (depth, poses and intrinsics are not read but must pass
+ * the usual clip checks). */
+sg_status scene_frame_sharpness(const sg_clip* clip, float* out_b, void* stream);
+
+/* Filter with a per-source-frame factor (Eq. 3 with the weight of Eq. 4 times
+ * frame_w[J], J = the frame the sample came from):
+ *   deblurring, Eq. 5: frame_w = B from scene_frame_sharpness, sigmas of Eq. 4;
+ *   computational shutter, Eq. 10: frame_w[J] = xi(J), every sigma +INFINITY
+ *   (a box, impulse train or decaying tail over absolute frame times).
+ * frame_w: device [num_frames] float32, each finite and >= 0 (not checked on the
+ * host: the caller's table). Sets, window and out_rgb as for scene_filter, and
+ * sets->ids must be non-NULL when capacity > 0. An
+ * output pixel whose weights sum to zero (empty set, or every sample on a frame of
+ * factor 0) gets I^f(p); a set that did not fit the arena (SG_FLAG_CAPACITY) gets
+ * NaN. */
+sg_status scene_filter_frames(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                              const sg_sample_sets* sets, const sg_filter_params* params,
+                              const float* frame_w, float* out_rgb, void* stream);
+
+/* Inpainting, Eq. 8-9. mask: device [num_frames][H][W] uint8, nonzero where the
+ * pixel shows content to remove (M = 1). For an output pixel with M^f(p) = 1:
+ * s_ref starts as the mean colour of all samples of its set (Eq. 8), and each of
+ * `steps` steps (the paper uses 2) replaces it with the mean of the samples
+ * weighted by exp(-|s_ref - c_s|^2 / (2 sigma_rgb^2)) for samples from unmasked
+ * source pixels and 0 for masked ones (Eq. 9; colour dimensions only). The output
+ * is the last s_ref. Unmasked output pixels, empty sets and pixels where a step's
+ * weights sum to zero get I^f(p); a set that did not fit the arena gets NaN.
+ * sigma_rgb > 0 and finite, on the stored colours' scale (full scale 1: the
+ * paper's 55 of 255 is 55 / 255 here); 1 <= steps <= SG_MAX_INPAINT_STEPS (more:
+ * SG_E_UNSUPPORTED). sets->ids must be non-NULL when capacity > 0. */
+sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                        const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, int32_t steps,
+                        float* out_rgb, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCENE_FILTERS_H */

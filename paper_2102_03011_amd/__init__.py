@@ -297,6 +297,64 @@ def scene_gather_filter(clip: StagedClip, f0: int, f1: int, params: GatherParams
 
 
 # ---------------------------------------------------------------------------
+# the paper's other filters over the same sets: deblurring, shutters, inpainting
+
+SG_MAX_INPAINT_STEPS = _native.SG_MAX_INPAINT_STEPS
+
+
+def scene_frame_sharpness(clip: StagedClip, out: torch.Tensor | None = None) -> torch.Tensor:
+    """B(J) of the deblurring weight (summed gradient magnitude of each stored
+    frame) -> [N] float32."""
+    if out is None:
+        out = torch.empty((clip.num_frames,), dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    if tuple(out.shape) != (clip.num_frames,):
+        raise SceneGatherError(f"out must have shape ({clip.num_frames},)")
+    cc = clip.c_struct()
+    _check(_lib.scene_frame_sharpness(ctypes.byref(cc), out.data_ptr(), _stream_handle()), "scene_frame_sharpness")
+    return out
+
+
+def scene_filter_frames(clip: StagedClip, sets: SampleSets, params: FilterParams, frame_w: torch.Tensor,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """Weighted mean with a per-source-frame factor frame_w [N] float32 (deblurring:
+    scene_frame_sharpness; shutter: xi(J) with every sigma inf) -> [f1 - f0, H, W, 3]."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    _need_gpu(frame_w, "frame_w", torch.float32)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    if tuple(frame_w.shape) != (clip.num_frames,):
+        raise SceneGatherError(f"frame_w must have shape ({clip.num_frames},)")
+    cc, ss, pp = clip.c_struct(), sets.c_struct(), params.c_struct()
+    _check(_lib.scene_filter_frames(ctypes.byref(cc), sets.f0, sets.f1, sets.window, ctypes.byref(ss),
+                                    ctypes.byref(pp), frame_w.data_ptr(), out.data_ptr(), _stream_handle()),
+           "scene_filter_frames")
+    return out
+
+
+def scene_inpaint(clip: StagedClip, sets: SampleSets, mask: torch.Tensor, sigma_rgb: float, steps: int = 2,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """Masked mean-shift inpainting; mask [N, H, W] uint8 (nonzero = remove),
+    sigma_rgb on the 0..1 colour scale -> [f1 - f0, H, W, 3] float32."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    _need_gpu(mask, "mask", torch.uint8)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    if tuple(mask.shape) != (clip.num_frames, clip.height, clip.width):
+        raise SceneGatherError(f"mask must have shape ({clip.num_frames}, {clip.height}, {clip.width})")
+    cc, ss = clip.c_struct(), sets.c_struct()
+    _check(_lib.scene_inpaint(ctypes.byref(cc), sets.f0, sets.f1, sets.window, ctypes.byref(ss), mask.data_ptr(),
+                              float(sigma_rgb), int(steps), out.data_ptr(), _stream_handle()), "scene_inpaint")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # learned per-sample weights
 
 SG_MLP_NW, SG_MLP_NB, SG_MLP_NPARAM = _native.SG_MLP_NW, _native.SG_MLP_NB, _native.SG_MLP_NPARAM

@@ -1,4 +1,4 @@
-"""ctypes declarations of the C ABI in include/scene_gather.h.
+"""ctypes declarations of the C ABI in include/scene_gather.h and include/scene_filters.h.
 
 Loads the in-tree libscenegather.so. There is no fallback: if the library is
 missing or fails to load, import of the binding raises.
@@ -17,6 +17,7 @@ SG_MAX_WINDOW = 511
 SG_MAX_RADIUS = 3
 SG_APRON = 6
 SG_APRON_RIGHT = 7
+SG_MAX_INPAINT_STEPS = 16
 
 c_void_p = ctypes.c_void_p
 
@@ -89,6 +90,13 @@ SIGNATURES = {
     "scene_gather_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgFilterParams),
                                             c_void_p, c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_frame_sharpness": (ctypes.c_int, [ctypes.POINTER(SgClip), c_void_p, c_void_p]),
+    "scene_filter_frames": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(SgSampleSets), ctypes.POINTER(SgFilterParams),
+                                            c_void_p, c_void_p, c_void_p]),
+    "scene_inpaint": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_float, ctypes.c_int32,
+                                      c_void_p, c_void_p]),
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),

@@ -13,6 +13,7 @@ namespace {
 using sg::check_clip;
 using sg::check_params;
 using sg::check_range;
+using sg::filter_scales;
 using sg::hip_status;
 
 constexpr size_t kAlign = 256;
@@ -73,21 +74,6 @@ sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_p
   jb->crho = sets->crho;
   jb->capacity = sets->capacity;
   jb->status = sets->status;
-  return SG_OK;
-}
-
-// Filter weights as exp2 arguments: a = -log2(e) / (2 sigma^2); each sigma must be
-// > 0 (+inf allowed, disabling its term).
-sg_status filter_scales(const sg_filter_params* params, sg::FilterJob* fj) {
-  const float sd = params->sigma_d, sc = params->sigma_c, stt = params->sigma_t;
-  if (!(sd > 0.0f) || !(sc > 0.0f) || !(stt > 0.0f)) return SG_E_INVALID;
-  const bool use_c = isfinite(sc), use_t = isfinite(stt);
-  const double log2e = 1.4426950408889634;
-  fj->a_d = isfinite(sd) ? static_cast<float>(-log2e / (2.0 * sd * static_cast<double>(sd))) : 0.0f;
-  fj->a_c = use_c ? static_cast<float>(-log2e / (2.0 * sc * static_cast<double>(sc))) : 0.0f;
-  fj->a_t = use_t ? static_cast<float>(-log2e / (2.0 * stt * static_cast<double>(stt))) : 0.0f;
-  fj->use_colour = use_c;
-  fj->use_time = use_t;
   return SG_OK;
 }
 

@@ -1,0 +1,365 @@
+// The paper's other filters over stored sample sets (Sec. 6): the per-frame
+// factor of deblurring (Eq. 5) and computational shutters (Eq. 10), the frame
+// sharpness B(J) that deblurring weights by, and inpainting by masked mean-shift
+// (Eq. 8-9). Same record layout and lane organisation as the denoising filter:
+// 16 lanes per output pixel stride through its CSR segment, each in a fixed
+// order, then a fixed butterfly combines them.
+//
+// Every table lookup made from a record's id (frame factor, source mask) is
+// bounds-checked: an id whose source frame or pixel lies outside the clip (sets
+// gathered with another window, or not produced by the gather) makes its output
+// pixel NaN, never a read outside the table.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "scene_filters.h"
+#include "sg_device.h"
+#include "sg_validate.h"
+
+namespace sg {
+namespace {
+
+constexpr int kLanes = 16;           // lanes per output pixel
+constexpr int kFilterThreads = 256;  // 16 pixels per workgroup
+constexpr uint32_t kQMask = (1u << SG_ID_SHIFT) - 1u;
+
+// ---------------------------------------------------------------------------
+// B(J) of Eq. 5: one workgroup per frame. Each thread walks columns x, x + 1024,
+// ... top to bottom, carrying the current row's pixel and its right neighbour and
+// loading kSharpRows rows below at a time (all in flight together); magnitudes in
+// float32, per-thread sums in float64, then a fixed tree over the workgroup.
+
+constexpr int kSharpThreads = 1024;
+constexpr int kSharpRows = 8;
+
+__device__ __forceinline__ float grad_magnitude(uint2 c, uint2 right, uint2 down) {
+  const float c0 = h2f(c.x), c1 = h2f(c.x >> 16), c2 = h2f(c.y);
+  const float x0 = h2f(right.x) - c0, x1 = h2f(right.x >> 16) - c1, x2 = h2f(right.y) - c2;
+  const float y0 = h2f(down.x) - c0, y1 = h2f(down.x >> 16) - c1, y2 = h2f(down.y) - c2;
+  return sqrtf(x0 * x0 + x1 * x1 + x2 * x2 + y0 * y0 + y1 * y1 + y2 * y2);
+}
+
+__global__ __launch_bounds__(kSharpThreads) void k_frame_sharpness(const uint2* __restrict__ rgbd_, int width,
+                                                                   int height, float* __restrict__ out) {
+  const int j = blockIdx.x;
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  gp<const uint2> plane = to_global(rgbd_) + static_cast<size_t>(j) * pplane;
+  double acc = 0.0;
+  for (int x = threadIdx.x; x + 1 < width; x += kSharpThreads) {
+    gp<const uint2> col = plane + padded_index(x, 0, pw);  // (x, 0); x + 1 is in the image
+    uint2 c = ld2(col), right = ld2(col + 1);
+    for (int y = 0; y + 1 < height; y += kSharpRows) {
+      uint2 d[kSharpRows], dr[kSharpRows];
+#pragma unroll
+      for (int k = 0; k < kSharpRows; ++k) {
+        // rows past the image's last are replaced by the last (read, not counted)
+        const int yy = min(y + 1 + k, height - 1);
+        d[k] = ld2(col + static_cast<size_t>(yy) * pw);
+        dr[k] = ld2(col + static_cast<size_t>(yy) * pw + 1);
+      }
+#pragma unroll
+      for (int k = 0; k < kSharpRows; ++k) {
+        if (y + k + 1 < height) acc += static_cast<double>(grad_magnitude(c, right, d[k]));
+        c = d[k];
+        right = dr[k];
+      }
+    }
+  }
+  __shared__ double part[kSharpThreads];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kSharpThreads / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = static_cast<float>(part[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Output pixel of a 16-lane group and its set.
+
+struct PixelSet {
+  bool live;     // the group has an output pixel
+  bool bad;      // its set lies outside the arena (or malformed offsets)
+  int f;         // output frame
+  int64_t self;  // y * W + x within the frame
+  int64_t s, e;  // record range
+  float cr, cg, cb;
+};
+
+__device__ __forceinline__ PixelSet pixel_set(gp<const uint2> rgbd, int width, int height, int f0, int64_t n_pix,
+                                              gp<const int64_t> offsets, int64_t capacity, int64_t pix) {
+  PixelSet p{};
+  p.live = pix < n_pix;
+  if (!p.live) return p;
+  const int64_t frame_px = static_cast<int64_t>(width) * height;
+  const int64_t fo = pix / frame_px;
+  p.f = f0 + static_cast<int>(fo);
+  p.self = pix - fo * frame_px;
+  const int y = static_cast<int>(p.self / width), x = static_cast<int>(p.self - static_cast<int64_t>(y) * width);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const uint2 ref = ld2(rgbd + static_cast<size_t>(p.f) * pplane + padded_index(x, y, pw));
+  p.cr = h2f(ref.x);
+  p.cg = h2f(ref.x >> 16);
+  p.cb = h2f(ref.y);
+  p.s = offsets[pix];
+  p.e = offsets[pix + 1];
+  p.bad = p.s < 0 || p.e < p.s || p.e > capacity;
+  if (p.bad) p.s = p.e = 0;
+  return p;
+}
+
+// sum over the 16 lanes of a group, the same value in every lane
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int off = kLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
+  return v;
+}
+__device__ __forceinline__ int group_or(int v) {
+#pragma unroll
+  for (int off = kLanes / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kLanes);
+  return v;
+}
+
+__device__ __forceinline__ void store_rgb(gp<float> out, int64_t pix, float r, float g, float b) {
+  gp<float> o = out + static_cast<size_t>(pix) * 3;
+  o[0] = r;
+  o[1] = g;
+  o[2] = b;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 3 with the Eq. 4 weight times frame_w[J].
+
+template <bool kColour, bool kTime>
+__global__ __launch_bounds__(kFilterThreads) void k_filter_frames(
+    const uint2* __restrict__ rgbd_, int width, int height, int n_frames, int f0, int w, int64_t n_pix,
+    const int64_t* __restrict__ offsets_, const uint32_t* __restrict__ ids_, const uint2* __restrict__ crho_,
+    int64_t capacity, float a_d, float a_c, float a_t, const float* __restrict__ frame_w_, float* __restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFilterThreads + threadIdx.x;
+  const int64_t pix = t / kLanes;
+  const int lane = static_cast<int>(t % kLanes);
+  gp<const uint32_t> ids = to_global(ids_);
+  gp<const uint2> crho = to_global(crho_);
+  gp<const float> frame_w = to_global(frame_w_);
+  const PixelSet p = pixel_set(to_global(rgbd_), width, height, f0, n_pix, to_global(offsets_), capacity, pix);
+  const int jbase = p.f - w;  // J = jbase + (id >> SG_ID_SHIFT)
+  float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+  int bad_id = 0;
+  for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
+    const uint2 rec = ld2(crho + i);
+    const uint32_t id = ids[i];
+    const int dj = static_cast<int>(id >> SG_ID_SHIFT) - w;
+    const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
+    if (j < 0 || j >= n_frames) {
+      bad_id = 1;
+      continue;
+    }
+    const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y), rho = h2f(rec.y >> 16);
+    float arg = a_d * rho * rho;
+    if (kColour) {
+      const float er = r - p.cr, eg = g - p.cg, eb = b - p.cb;
+      arg = fmaf(a_c, fmaf(er, er, fmaf(eg, eg, eb * eb)), arg);
+    }
+    if (kTime) {
+      const float fdj = static_cast<float>(dj);
+      arg = fmaf(a_t, fdj * fdj, arg);
+    }
+    const float wt = __builtin_amdgcn_exp2f(arg) * frame_w[j];
+    wsum += wt;
+    ar = fmaf(wt, r, ar);
+    ag = fmaf(wt, g, ag);
+    ab = fmaf(wt, b, ab);
+  }
+  wsum = group_sum(wsum);
+  ar = group_sum(ar);
+  ag = group_sum(ag);
+  ab = group_sum(ab);
+  bad_id = group_or(bad_id);
+  if (p.live && lane == 0) {
+    if (p.bad || bad_id) {
+      const float nan = __builtin_nanf("");
+      store_rgb(to_global(out), pix, nan, nan, nan);
+    } else if (wsum > 0.f) {
+      const float inv = 1.0f / wsum;
+      store_rgb(to_global(out), pix, ar * inv, ag * inv, ab * inv);
+    } else {
+      store_rgb(to_global(out), pix, p.cr, p.cg, p.cb);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inpainting: mean of the set, then `steps` weighted means around the current
+// estimate with masked source pixels left out.
+
+__global__ __launch_bounds__(kFilterThreads) void k_inpaint(
+    const uint2* __restrict__ rgbd_, int width, int height, int n_frames, int f0, int w, int64_t n_pix,
+    const int64_t* __restrict__ offsets_, const uint32_t* __restrict__ ids_, const uint2* __restrict__ crho_,
+    int64_t capacity, const uint8_t* __restrict__ mask_, float a_c, int steps, float* __restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFilterThreads + threadIdx.x;
+  const int64_t pix = t / kLanes;
+  const int lane = static_cast<int>(t % kLanes);
+  gp<const uint32_t> ids = to_global(ids_);
+  gp<const uint2> crho = to_global(crho_);
+  gp<const uint8_t> mask = to_global(mask_);
+  const PixelSet p = pixel_set(to_global(rgbd_), width, height, f0, n_pix, to_global(offsets_), capacity, pix);
+  const int64_t frame_px = static_cast<int64_t>(width) * height;
+  // the same decision in all 16 lanes of the group
+  const bool run = p.live && !p.bad && p.e > p.s && mask[static_cast<size_t>(p.f) * frame_px + p.self] != 0;
+  float sr = p.cr, sg = p.cg, sb = p.cb;
+  bool ok = false;
+  int bad_id = 0;
+  if (run) {
+    float ar = 0.f, ag = 0.f, ab = 0.f;
+    for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
+      const uint2 rec = ld2(crho + i);
+      ar += h2f(rec.x);
+      ag += h2f(rec.x >> 16);
+      ab += h2f(rec.y);
+    }
+    const float inv_n = 1.0f / static_cast<float>(p.e - p.s);
+    sr = group_sum(ar) * inv_n;
+    sg = group_sum(ag) * inv_n;
+    sb = group_sum(ab) * inv_n;
+    ok = true;
+    const int jbase = p.f - w;
+    for (int step = 0; step < steps && ok; ++step) {
+      float wsum = 0.f;
+      ar = ag = ab = 0.f;
+      for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
+        const uint32_t id = ids[i];
+        const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
+        const int64_t q = static_cast<int64_t>(id & kQMask);
+        if (j < 0 || j >= n_frames || q >= frame_px) {
+          bad_id = 1;
+          continue;
+        }
+        if (mask[static_cast<size_t>(j) * frame_px + q] != 0) continue;
+        const uint2 rec = ld2(crho + i);
+        const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y);
+        const float er = r - sr, eg = g - sg, eb = b - sb;
+        const float wt = __builtin_amdgcn_exp2f(a_c * fmaf(er, er, fmaf(eg, eg, eb * eb)));
+        wsum += wt;
+        ar = fmaf(wt, r, ar);
+        ag = fmaf(wt, g, ag);
+        ab = fmaf(wt, b, ab);
+      }
+      wsum = group_sum(wsum);
+      ar = group_sum(ar);
+      ag = group_sum(ag);
+      ab = group_sum(ab);
+      if (wsum > 0.f) {
+        const float inv = 1.0f / wsum;
+        sr = ar * inv;
+        sg = ag * inv;
+        sb = ab * inv;
+      } else {
+        ok = false;
+      }
+    }
+    bad_id = group_or(bad_id);
+  }
+  if (p.live && lane == 0) {
+    if (p.bad || bad_id) {
+      const float nan = __builtin_nanf("");
+      store_rgb(to_global(out), pix, nan, nan, nan);
+    } else if (ok) {
+      store_rgb(to_global(out), pix, sr, sg, sb);
+    } else {
+      store_rgb(to_global(out), pix, p.cr, p.cg, p.cb);
+    }
+  }
+}
+
+// Workgroups of a 16-lanes-per-pixel launch over n_pix pixels (0 when it would not
+// fit a 32-bit grid).
+int64_t filter_blocks(int64_t n_pix) {
+  const int64_t b = (n_pix * kLanes + kFilterThreads - 1) / kFilterThreads;
+  return b > 0x7FFFFFFF ? 0 : b;
+}
+
+// The checks shared by the two set filters.
+sg_status check_sets_call(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window, const sg_sample_sets* sets,
+                          const void* table, const float* out_rgb) {
+  sg_status s = check_clip(clip, false);
+  if (s != SG_OK) return s;
+  if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
+  if (window < 0) return SG_E_INVALID;
+  if (window > SG_MAX_WINDOW) return SG_E_UNSUPPORTED;
+  if (sets == nullptr || sets->offsets == nullptr || table == nullptr || out_rgb == nullptr) return SG_E_INVALID;
+  if (sets->capacity < 0 || (sets->capacity > 0 && (sets->crho == nullptr || sets->ids == nullptr)))
+    return SG_E_INVALID;
+  if (filter_blocks(static_cast<int64_t>(f1 - f0) * clip->width * clip->height) == 0) return SG_E_UNSUPPORTED;
+  return SG_OK;
+}
+
+}  // namespace
+}  // namespace sg
+
+using sg::check_clip;
+using sg::hip_status;
+
+extern "C" {
+
+sg_status scene_frame_sharpness(const sg_clip* clip, float* out_b, void* stream) {
+  const sg_status s = check_clip(clip, false);
+  if (s != SG_OK) return s;
+  if (out_b == nullptr) return SG_E_INVALID;
+  hipLaunchKernelGGL(sg::k_frame_sharpness, dim3(static_cast<unsigned>(clip->num_frames)), dim3(sg::kSharpThreads),
+                     0, static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->width,
+                     clip->height, out_b);
+  return hip_status(hipGetLastError());
+}
+
+sg_status scene_filter_frames(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                              const sg_sample_sets* sets, const sg_filter_params* params, const float* frame_w,
+                              float* out_rgb, void* stream) {
+  sg_status s = sg::check_sets_call(clip, f0, f1, window, sets, frame_w, out_rgb);
+  if (s != SG_OK) return s;
+  if (params == nullptr) return SG_E_INVALID;
+  sg::FilterJob fj{};
+  if ((s = sg::filter_scales(params, &fj)) != SG_OK) return s;
+  const int64_t n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
+  const dim3 g(static_cast<unsigned>(sg::filter_blocks(n_pix)));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint2* rgbd = reinterpret_cast<const uint2*>(clip->rgbd);
+  const uint2* crho = reinterpret_cast<const uint2*>(sets->crho);
+#define SG_FRAMES(C, T)                                                                                          \
+  hipLaunchKernelGGL((sg::k_filter_frames<C, T>), g, dim3(sg::kFilterThreads), 0, st, rgbd, clip->width,         \
+                     clip->height, clip->num_frames, f0, window, n_pix, sets->offsets, sets->ids, crho,           \
+                     sets->capacity, fj.a_d, fj.a_c, fj.a_t, frame_w, out_rgb)
+  if (fj.use_colour && fj.use_time)
+    SG_FRAMES(true, true);
+  else if (fj.use_colour)
+    SG_FRAMES(true, false);
+  else if (fj.use_time)
+    SG_FRAMES(false, true);
+  else
+    SG_FRAMES(false, false);
+#undef SG_FRAMES
+  return hip_status(hipGetLastError());
+}
+
+sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window, const sg_sample_sets* sets,
+                        const uint8_t* mask, float sigma_rgb, int32_t steps, float* out_rgb, void* stream) {
+  const sg_status s = sg::check_sets_call(clip, f0, f1, window, sets, mask, out_rgb);
+  if (s != SG_OK) return s;
+  if (!(sigma_rgb > 0.0f) || !isfinite(sigma_rgb)) return SG_E_INVALID;
+  if (steps < 1) return SG_E_INVALID;
+  if (steps > SG_MAX_INPAINT_STEPS) return SG_E_UNSUPPORTED;
+  const double log2e = 1.4426950408889634;
+  const float a_c = static_cast<float>(-log2e / (2.0 * sigma_rgb * static_cast<double>(sigma_rgb)));
+  const int64_t n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
+  hipLaunchKernelGGL(sg::k_inpaint, dim3(static_cast<unsigned>(sg::filter_blocks(n_pix))), dim3(sg::kFilterThreads),
+                     0, static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->width,
+                     clip->height, clip->num_frames, f0, window, n_pix, sets->offsets, sets->ids,
+                     reinterpret_cast<const uint2*>(sets->crho), sets->capacity, mask, a_c, steps, out_rgb);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -9,6 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "scene_gather.h")
+HEADERS = [os.path.join(ROOT, "include", n) for n in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if n.endswith(".h")]
 
 
 @pytest.fixture(scope="module")
@@ -20,8 +22,8 @@ def native():
     return _native, _native.load()
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(path):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
     return sorted(set(n for n in names if not n.startswith("SCENE")))
@@ -29,8 +31,10 @@ def _declared_functions():
 
 def test_header_functions_are_exported(native):
     mod, lib = native
-    names = _declared_functions()
-    assert len(names) >= 8
+    assert len(HEADERS) == 2
+    names = [n for h in HEADERS for n in _declared_functions(h)]
+    assert len(names) >= 11
+    assert {"scene_frame_sharpness", "scene_filter_frames", "scene_inpaint"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
         assert n in mod.SIGNATURES, n
@@ -46,6 +50,8 @@ def test_header_constants_match_binding_and_bound_the_gather_reads():
     defs = {k: int(v, 0) for k, v in re.findall(r"^#define (SG_[A-Z_]+) \(?([0-9x]+)", text, flags=re.M)}
     for name in ("SG_APRON", "SG_APRON_RIGHT", "SG_MAX_RADIUS", "SG_MAX_WINDOW", "SG_ID_SHIFT"):
         assert getattr(_native, name) == defs[name], name
+    ftext = open(os.path.join(ROOT, "include", "scene_filters.h")).read()
+    assert _native.SG_MAX_INPAINT_STEPS == int(re.search(r"#define SG_MAX_INPAINT_STEPS (\d+)", ftext).group(1))
     for r in range(defs["SG_MAX_RADIUS"] + 1):
         assert defs["SG_APRON"] >= 2 * r, r
         # rightmost centre x = W - 1 + r; its block rows are read from x - r as whole
@@ -204,6 +210,86 @@ def test_range_beyond_the_int_grid_is_unsupported(native):
     assert lib.scene_gather_workspace_size(ctypes.byref(c), 0, 2048, ctypes.byref(p), ctypes.byref(need)) == 4
     assert lib.scene_gather_filter(ctypes.byref(c), 0, 2048, ctypes.byref(p), ctypes.byref(fp), 0x90000, 0xA0000,
                                    1 << 40, None) == 4
+
+
+def test_frame_sharpness_rejects_bad_arguments(native):
+    mod, lib = native
+    c = _clip(mod)
+    assert lib.scene_frame_sharpness(None, 0x90000, None) == 1
+    assert lib.scene_frame_sharpness(ctypes.byref(c), None, None) == 1
+    c.rgbd = None
+    assert lib.scene_frame_sharpness(ctypes.byref(c), 0x90000, None) == 1
+    c = _clip(mod, w=4097, h=1024)
+    assert lib.scene_frame_sharpness(ctypes.byref(c), 0x90000, None) == 4
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("ok_but_null_table", 1), ("null_sets", 1), ("null_out", 1), ("bad_range", 1), ("neg_window", 1),
+    ("big_window", 4), ("sigma_zero", 1), ("null_params", 1), ("null_ids", 1), ("null_crho", 1),
+    ("neg_capacity", 1),
+])
+def test_filter_frames_rejects_bad_arguments(native, case, expect):
+    mod, lib = native
+    c = _clip(mod)
+    s = _sets(mod, 100)
+    fp = mod.SgFilterParams(0.01, math.inf, math.inf, 0.0)
+    f0, f1, w, table, out = 0, 2, 3, 0xB0000, 0x90000
+    pp = ctypes.byref(fp)
+    if case == "ok_but_null_table":
+        table = None
+    elif case == "null_sets":
+        s = None
+    elif case == "null_out":
+        out = None
+    elif case == "bad_range":
+        f1 = 11
+    elif case == "neg_window":
+        w = -1
+    elif case == "big_window":
+        w = 512
+    elif case == "sigma_zero":
+        fp.sigma_d = 0.0
+    elif case == "null_params":
+        pp = None
+    elif case == "null_ids":
+        s.ids = None
+    elif case == "null_crho":
+        s.crho = None
+    elif case == "neg_capacity":
+        s.capacity = -1
+    sp = ctypes.byref(s) if s is not None else None
+    assert lib.scene_filter_frames(ctypes.byref(c), f0, f1, w, sp, pp, table, out, None) == expect, case
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_mask", 1), ("sigma_zero", 1), ("sigma_nan", 1), ("sigma_inf", 1), ("steps_zero", 1),
+    ("steps_big", 4), ("null_ids", 1), ("bad_range", 1), ("null_out", 1),
+])
+def test_inpaint_rejects_bad_arguments(native, case, expect):
+    mod, lib = native
+    c = _clip(mod)
+    s = _sets(mod, 100)
+    f0, f1, w, mask, sigma, steps, out = 0, 2, 3, 0xB0000, 0.2, 2, 0x90000
+    if case == "null_mask":
+        mask = None
+    elif case == "sigma_zero":
+        sigma = 0.0
+    elif case == "sigma_nan":
+        sigma = math.nan
+    elif case == "sigma_inf":
+        sigma = math.inf
+    elif case == "steps_zero":
+        steps = 0
+    elif case == "steps_big":
+        steps = mod.SG_MAX_INPAINT_STEPS + 1
+    elif case == "null_ids":
+        s.ids = None
+    elif case == "bad_range":
+        f0 = -1
+    elif case == "null_out":
+        out = None
+    assert lib.scene_inpaint(ctypes.byref(c), f0, f1, w, ctypes.byref(s), mask, sigma, steps, out, None) == expect, \
+        case
 
 
 def test_stage_rejects_bad_arguments(native):

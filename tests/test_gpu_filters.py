@@ -1,0 +1,196 @@
+"""GPU parity of the paper's other filters over stored sets (Sec. 6): the frame
+sharpness B(J) and per-frame factors of deblurring (Eq. 5) and computational
+shutters (Eq. 10), and masked mean-shift inpainting (Eq. 8-9), through the C ABI
+against the float64 oracle. All inputs are seeded and synthetic.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import filters as ofilters
+from oracle import gather as ogather
+from oracle import staging as ostaging
+from scenegen import configs, generate
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+F = 11  # output frame of the small workload (24 frames, window +-23)
+
+
+def _sg():
+    import paper_2102_03011_amd as sg
+    return sg
+
+
+def _stage(clip):
+    sg = _sg()
+    return sg.scene_stage(clip.rgb_u8.to("cuda").contiguous(), clip.depth.to("cuda").contiguous(),
+                          clip.cam_to_world.to("cuda").contiguous(), clip.fx, clip.fy, clip.cx, clip.cy)
+
+
+def _moving_box_mask(n, h, w, x0, y0, bw, bh, dx):
+    """M^J: a bw x bh box at (x0 + dx J, y0) in frame J (clipped to the image)."""
+    m = np.zeros((n, h, w), dtype=np.uint8)
+    for j in range(n):
+        xa = max(0, min(w, x0 + dx * j))
+        m[j, y0:y0 + bh, xa:min(w, xa + bw)] = 1
+    return m
+
+
+def _case(wl, clip, f):
+    staged = _stage(clip)
+    col = ostaging.colour_q(clip.rgb_u8.cpu().numpy())
+    dep = ostaging.depth_q(clip.depth.cpu().numpy())
+    sg = _sg()
+    params = sg.GatherParams(window=wl.window, tol=wl.tol, z_near=wl.z_near)
+    sets = sg.scene_gather(staged, f, f + 1, params)
+    torch.cuda.synchronize()
+    sets.check()
+    oprm = ogather.GatherParams(window=wl.window, radius=1, tol=wl.tol, z_near=wl.z_near)
+    orc = ogather.gather_frame(col, dep, clip.cam_to_world.numpy(), clip.fx, clip.fy, clip.cx, clip.cy, f, oprm)
+    band = parity.pixels_with_band_cases(orc)
+    return staged, col, sets, orc, band
+
+
+@pytest.fixture(scope="module")
+def small():
+    wl = configs.small_plain()
+    clip = generate(wl.spec)
+    return (wl, clip) + _case(wl, clip, F)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 100 x 37 (ragged tiles) with invalid depths: NaN, 0, +inf and below z_near
+    wl = configs.tiny(seed=9, width=100, height=37, n_frames=7, window=3, pose_rot_deg=1.0, pose_trans_m=0.03)
+    clip = generate(wl.spec)
+    d = clip.depth.clone()
+    m = torch.rand(d.shape, generator=torch.Generator().manual_seed(5))
+    d[m < 0.03] = float("nan")
+    d[(m >= 0.03) & (m < 0.05)] = 0.0
+    d[(m >= 0.05) & (m < 0.06)] = float("inf")
+    d[(m >= 0.06) & (m < 0.07)] = 0.005
+    clip.depth = d
+    return (wl, clip) + _case(wl, clip, 3)
+
+
+def _err(got, want, band):
+    e = np.abs(got.reshape(-1, 3).astype(np.float64) - want).max(axis=1)
+    return float(e[~band].max())
+
+
+def test_frame_sharpness_matches_oracle_and_repeats_bit_for_bit(small, ragged):
+    sg = _sg()
+    for case in (small, ragged):
+        wl, clip, staged, col = case[:4]
+        b1 = sg.scene_frame_sharpness(staged)
+        b2 = sg.scene_frame_sharpness(staged)
+        torch.cuda.synchronize()
+        assert torch.equal(b1, b2)
+        want = ofilters.frame_sharpness(col)
+        got = b1.cpu().numpy().astype(np.float64)
+        assert np.all(want > 0)
+        np.testing.assert_allclose(got, want, rtol=2e-6)
+
+
+@pytest.mark.parametrize("preset", ["depth", "paper"])
+def test_factor_one_is_the_plain_filter(small, preset):
+    wl, clip, staged, col, sets = small[:5]
+    sg = _sg()
+    fp = (sg.FilterParams(sigma_d=0.01) if preset == "depth"
+          else sg.FilterParams(sigma_d=0.01, sigma_c=40.0 / 255.0, sigma_t=6.0))
+    ones = torch.ones(clip.n_frames, dtype=torch.float32, device="cuda")
+    a = sg.scene_filter_frames(staged, sets, fp, ones)
+    b = sg.scene_filter(staged, sets, fp)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max()) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_deblur_weights_match_oracle(name, request):
+    wl, clip, staged, col, sets, orc, band = request.getfixturevalue(name)
+    sg = _sg()
+    f = orc.frame
+    # Eq. 5 with the paper's deblurring sigmas (colour 200 of 255, frame 20) and the depth term;
+    # each side weights by its own B(J)
+    fp = sg.FilterParams(sigma_d=0.01, sigma_c=200.0 / 255.0, sigma_t=20.0)
+    got = sg.scene_filter_frames(staged, sets, fp, sg.scene_frame_sharpness(staged)).cpu().numpy()
+    want = ofilters.frame_weighted_mean(orc, col[f], wl.window, ofilters.frame_sharpness(col),
+                                        0.01, 200.0 / 255.0, 20.0)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+
+
+def test_shutter_box_and_all_zero_factors(small):
+    wl, clip, staged, col, sets, orc, band = small
+    sg = _sg()
+    fp = sg.FilterParams(sigma_d=math.inf)
+    # a box over frames 5 .. 9 that leaves the output frame itself out: pixels seen
+    # only outside it keep their input colour
+    xi = np.zeros(clip.n_frames, dtype=np.float32)
+    xi[5:10] = 1.0
+    got = sg.scene_filter_frames(staged, sets, fp, torch.from_numpy(xi).cuda()).cpu().numpy()
+    want = ofilters.frame_weighted_mean(orc, col[F], wl.window, xi.astype(np.float64), math.inf)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+    # a decaying tail (trails): xi(J) = 0.7^(F - J) for J <= F
+    tail = np.where(np.arange(clip.n_frames) <= F, 0.7 ** (F - np.arange(clip.n_frames)), 0.0)
+    got = sg.scene_filter_frames(staged, sets, fp, torch.from_numpy(tail.astype(np.float32)).cuda()).cpu().numpy()
+    want = ofilters.frame_weighted_mean(orc, col[F], wl.window, tail.astype(np.float32).astype(np.float64), math.inf)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+    # every factor zero: the input colour, exactly
+    zero = torch.zeros(clip.n_frames, dtype=torch.float32, device="cuda")
+    got = sg.scene_filter_frames(staged, sets, sg.FilterParams(sigma_d=0.01), zero).cpu().numpy()
+    assert np.array_equal(got.reshape(-1, 3).astype(np.float64), col[F].reshape(-1, 3))
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_inpaint_matches_oracle(name, request):
+    wl, clip, staged, col, sets, orc, band = request.getfixturevalue(name)
+    sg = _sg()
+    f = orc.frame
+    n, h, w = clip.n_frames, clip.height, clip.width
+    mask = _moving_box_mask(n, h, w, x0=w // 5, y0=h // 4, bw=w // 3, bh=h // 3, dx=max(1, w // 40))
+    sigma = 55.0 / 255.0
+    got = sg.scene_inpaint(staged, sets, torch.from_numpy(mask).cuda(), sigma, steps=2).cpu().numpy()
+    want = ofilters.inpaint_mean_shift(orc, col[f], wl.window, mask.astype(bool), sigma, steps=2)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+    # unmasked output pixels keep their input colour exactly
+    keep = mask[f].reshape(-1) == 0
+    assert np.array_equal(got.reshape(-1, 3)[keep].astype(np.float64), col[f].reshape(-1, 3)[keep])
+    # and the masked region did change where it had unmasked evidence
+    assert np.abs(got.reshape(-1, 3)[~keep] - col[f].reshape(-1, 3)[~keep]).max() > 0.01
+
+
+def test_sets_past_the_arena_and_foreign_ids_give_nan(small):
+    wl, clip, staged, col, sets = small[:5]
+    sg = _sg()
+    n, h, w = clip.n_frames, clip.height, clip.width
+    params = sg.GatherParams(window=wl.window, tol=wl.tol, z_near=wl.z_near)
+    total = sets.total()
+    cap = total // 2
+    short = sg.scene_gather(staged, F, F + 1, params, capacity=cap)
+    ones = torch.ones(n, dtype=torch.float32, device="cuda")
+    mask = torch.ones((n, h, w), dtype=torch.uint8, device="cuda")
+    a = sg.scene_filter_frames(staged, short, sg.FilterParams(sigma_d=0.01), ones).cpu().numpy().reshape(-1, 3)
+    b = sg.scene_inpaint(staged, short, mask, 0.2).cpu().numpy().reshape(-1, 3)
+    over = short.offsets.cpu().numpy()[1:] > cap
+    assert over.any() and not over.all()
+    for out in (a, b):
+        assert np.isnan(out[over]).all()
+        assert np.isfinite(out[~over]).all()
+    # ids decoded with a smaller window than the gather's: a pixel with a record whose
+    # source frame falls outside the clip is NaN, the rest finite (bounds-checked lookups)
+    w_small = 2
+    alias = sg.SampleSets(F, F + 1, w_small, sets.offsets, sets.ids, sets.crho, sets.status)
+    c = sg.scene_filter_frames(staged, alias, sg.FilterParams(sigma_d=0.01), ones).cpu().numpy().reshape(-1, 3)
+    off = sets.offsets.cpu().numpy()
+    j = F - w_small + (sets.ids.cpu().numpy().view(np.uint32) >> 22).astype(np.int64)
+    outside = (j < 0) | (j >= n)
+    seg = np.repeat(np.arange(off.size - 1), np.diff(off))
+    want_nan = np.zeros(off.size - 1, dtype=bool)
+    want_nan[seg[outside]] = True
+    assert want_nan.any()
+    assert np.array_equal(np.isnan(c).any(axis=1), want_nan)
