@@ -150,15 +150,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_frames(
   const int jbase = p.f - w;  // J = jbase + (id >> SG_ID_SHIFT)
   float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
   int bad_id = 0;
-  for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
-    const uint2 rec = ld2(crho + i);
-    const uint32_t id = ids[i];
-    const int dj = static_cast<int>(id >> SG_ID_SHIFT) - w;
-    const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
-    if (j < 0 || j >= n_frames) {
-      bad_id = 1;
-      continue;
-    }
+  auto accumulate = [&](uint2 rec, uint32_t id, float fw) {
     const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y), rho = h2f(rec.y >> 16);
     float arg = a_d * rho * rho;
     if (kColour) {
@@ -166,14 +158,44 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_frames(
       arg = fmaf(a_c, fmaf(er, er, fmaf(eg, eg, eb * eb)), arg);
     }
     if (kTime) {
-      const float fdj = static_cast<float>(dj);
+      const float fdj = static_cast<float>(static_cast<int>(id >> SG_ID_SHIFT) - w);
       arg = fmaf(a_t, fdj * fdj, arg);
     }
-    const float wt = __builtin_amdgcn_exp2f(arg) * frame_w[j];
+    const float wt = __builtin_amdgcn_exp2f(arg) * fw;
     wsum += wt;
     ar = fmaf(wt, r, ar);
     ag = fmaf(wt, g, ag);
     ab = fmaf(wt, b, ab);
+  };
+  // factor of a record's frame, 0 (and bad_id set) when the id's frame is outside the clip
+  auto factor = [&](uint32_t id) {
+    const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
+    if (j < 0 || j >= n_frames) {
+      bad_id = 1;
+      return 0.0f;
+    }
+    return frame_w[j];
+  };
+  // four records per lane in flight (records, then their frames' factors); each
+  // lane still adds its records in order
+  int64_t i = p.s + lane;
+  for (; i + 3 * kLanes < p.e; i += 4 * kLanes) {
+    uint2 rec[4];
+    uint32_t id[4];
+    float fw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rec[k] = ld2(crho + i + k * kLanes);
+      id[k] = ids[i + k * kLanes];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fw[k] = factor(id[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) accumulate(rec[k], id[k], fw[k]);
+  }
+  for (; i < p.e; i += kLanes) {
+    const uint32_t id = ids[i];
+    accumulate(ld2(crho + i), id, factor(id));
   }
   wsum = group_sum(wsum);
   ar = group_sum(ar);
@@ -216,7 +238,19 @@ __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
   int bad_id = 0;
   if (run) {
     float ar = 0.f, ag = 0.f, ab = 0.f;
-    for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
+    int64_t i = p.s + lane;
+    for (; i + 3 * kLanes < p.e; i += 4 * kLanes) {
+      uint2 rec[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rec[k] = ld2(crho + i + k * kLanes);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ar += h2f(rec[k].x);
+        ag += h2f(rec[k].x >> 16);
+        ab += h2f(rec[k].y);
+      }
+    }
+    for (; i < p.e; i += kLanes) {
       const uint2 rec = ld2(crho + i);
       ar += h2f(rec.x);
       ag += h2f(rec.x >> 16);
@@ -228,19 +262,22 @@ __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
     sb = group_sum(ab) * inv_n;
     ok = true;
     const int jbase = p.f - w;
+    // 1 when the record's source pixel may contribute (unmasked); 0 when masked, or
+    // when the id lies outside the clip (bad_id set, the table not read)
+    auto usable = [&](uint32_t id) {
+      const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
+      const int64_t q = static_cast<int64_t>(id & kQMask);
+      if (j < 0 || j >= n_frames || q >= frame_px) {
+        bad_id = 1;
+        return false;
+      }
+      return mask[static_cast<size_t>(j) * frame_px + q] == 0;
+    };
     for (int step = 0; step < steps && ok; ++step) {
       float wsum = 0.f;
       ar = ag = ab = 0.f;
-      for (int64_t i = p.s + lane; i < p.e; i += kLanes) {
-        const uint32_t id = ids[i];
-        const int j = jbase + static_cast<int>(id >> SG_ID_SHIFT);
-        const int64_t q = static_cast<int64_t>(id & kQMask);
-        if (j < 0 || j >= n_frames || q >= frame_px) {
-          bad_id = 1;
-          continue;
-        }
-        if (mask[static_cast<size_t>(j) * frame_px + q] != 0) continue;
-        const uint2 rec = ld2(crho + i);
+      auto accumulate = [&](uint2 rec, bool use) {
+        if (!use) return;
         const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y);
         const float er = r - sr, eg = g - sg, eb = b - sb;
         const float wt = __builtin_amdgcn_exp2f(a_c * fmaf(er, er, fmaf(eg, eg, eb * eb)));
@@ -248,6 +285,26 @@ __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
         ar = fmaf(wt, r, ar);
         ag = fmaf(wt, g, ag);
         ab = fmaf(wt, b, ab);
+      };
+      // four records per lane in flight: records and ids, then the source mask bytes
+      int64_t i = p.s + lane;
+      for (; i + 3 * kLanes < p.e; i += 4 * kLanes) {
+        uint2 rec[4];
+        uint32_t id[4];
+        bool use[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          rec[k] = ld2(crho + i + k * kLanes);
+          id[k] = ids[i + k * kLanes];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) use[k] = usable(id[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) accumulate(rec[k], use[k]);
+      }
+      for (; i < p.e; i += kLanes) {
+        const uint2 rec = ld2(crho + i);
+        accumulate(rec, usable(ids[i]));
       }
       wsum = group_sum(wsum);
       ar = group_sum(ar);
