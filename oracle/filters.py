@@ -143,3 +143,38 @@ def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask
         if ok:
             out[i] = s_ref
     return out
+
+
+def scene_points(depth: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float,
+                 cy: float) -> np.ndarray:
+    """World position of every pixel q = (x, y) of every frame J (Sec. 3: a pixel
+    with its depth and camera matrix is a scene point): X_cam = d ((x - cx) / fx,
+    (y - cy) / fy, 1), X = R^J X_cam + t^J with C^J = [R^J | t^J], each sum taken
+    left to right. depth [N, H, W] -> [N, H, W, 3] float64."""
+    n, h, w = depth.shape
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    out = np.empty((n, h, w, 3))
+    for j in range(n):
+        d = np.asarray(depth[j], dtype=np.float64)
+        xc, yc, zc = d * ((xx - cx) / fx), d * ((yy - cy) / fy), d
+        c = np.asarray(cam_to_world[j], dtype=np.float64)
+        for k in range(3):
+            out[j, :, :, k] = ((c[k, 0] * xc + c[k, 1] * yc) + c[k, 2] * zc) + c[k, 3]
+    return out
+
+
+def scene_box_mask(depth: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
+                   lo, hi) -> np.ndarray:
+    """Inpainting masks from a scene-space region (Sec. 6, inpainting: the samples
+    inside the region, projected back into the images, form M). Reading: the region
+    is an axis-aligned box [lo, hi] in world coordinates, bounds included; a pixel
+    without a valid depth (not finite, or <= 0) is not a scene point and stays
+    unmasked. Returns [N, H, W] bool."""
+    d = np.asarray(depth, dtype=np.float64)
+    with np.errstate(invalid="ignore"):   # inf depths give NaN positions; they are masked out below
+        pts = scene_points(d, cam_to_world, fx, fy, cx, cy)
+        ok = np.isfinite(d) & (d > 0.0)
+        inside = np.ones(d.shape, dtype=bool)
+        for k in range(3):
+            inside &= (pts[..., k] >= lo[k]) & (pts[..., k] <= hi[k])
+    return ok & inside

@@ -184,3 +184,56 @@ def test_inpaint_leaves_unmasked_all_masked_and_empty_pixels():
     mask = _mask(on=[(1, 1), (1, 2), (0, 5)])
     got = of.inpaint_mean_shift(sets, cf, win, mask, 0.2)
     np.testing.assert_array_equal(got, cf.reshape(-1, 3)[:3])
+
+
+# ---------------------------------------------------------------------------
+# masks from a scene-space box
+
+def _cams(*mats):
+    return np.stack([np.asarray(m, dtype=np.float64) for m in mats])
+
+
+def test_box_mask_of_a_fronto_parallel_plane_is_a_rectangle():
+    # identity camera, depth 2, f = 100, c = (10, 8): X = 2 (x - 10) / 100, Y = 2 (y - 8) / 100.
+    # |X| <= 0.1 <=> 5 <= x <= 15; -0.04 <= Y <= 0.06 <=> 6 <= y <= 11
+    h, w = 20, 24
+    d = np.full((1, h, w), 2.0)
+    m = of.scene_box_mask(d, _cams(np.eye(4)), 100.0, 100.0, 10.0, 8.0, (-0.1, -0.04, 1.0), (0.1, 0.06, 3.0))
+    want = np.zeros((h, w), dtype=bool)
+    want[6:12, 5:16] = True
+    assert np.array_equal(m[0], want)
+
+
+def test_box_mask_follows_the_camera_pose():
+    # camera 1 translated by +0.2 along world X, camera 2 rotated 90 degrees about Z
+    # (camera x -> world y): the same world box selects shifted / transposed pixels
+    h, w = 20, 24
+    d = np.full((3, h, w), 2.0)
+    t = np.eye(4)
+    t[0, 3] = 0.2
+    rz = np.array([[0.0, -1.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+    lo, hi = (-0.1, -0.04, 1.0), (0.1, 0.06, 3.0)
+    m = of.scene_box_mask(d, _cams(np.eye(4), t, rz), 100.0, 100.0, 10.0, 8.0, lo, hi)
+    # frame 1: X = 2 (x - 10) / 100 + 0.2 in [-0.1, 0.1] <=> -5 <= x <= 5
+    want1 = np.zeros((h, w), dtype=bool)
+    want1[6:12, 0:6] = True
+    assert np.array_equal(m[1], want1)
+    # frame 2: world X = -Yc = -2 (y - 8) / 100 in [-0.1, 0.1] <=> 3 <= y <= 13;
+    # world Y = Xc = 2 (x - 10) / 100 in [-0.04, 0.06] <=> 8 <= x <= 13
+    want2 = np.zeros((h, w), dtype=bool)
+    want2[3:14, 8:14] = True
+    assert np.array_equal(m[2], want2)
+
+
+def test_box_mask_depth_range_and_invalid_depths():
+    h, w = 6, 6
+    d = np.full((1, h, w), 2.0)
+    d[0, 0, 0] = np.nan
+    d[0, 0, 1] = np.inf
+    d[0, 0, 2] = 0.0
+    d[0, 1, :] = 5.0                       # behind the box's far face
+    m = of.scene_box_mask(d, _cams(np.eye(4)), 1e6, 1e6, 2.5, 2.5, (-1.0, -1.0, 1.5), (1.0, 1.0, 2.0))
+    want = np.ones((h, w), dtype=bool)
+    want[0, :3] = False
+    want[1, :] = False
+    assert np.array_equal(m[0], want)      # z = 2.0 on the far face is inside (bounds included)
