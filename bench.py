@@ -157,7 +157,8 @@ def fused_leg(sg, clip, staged, wl, params, fparams, timed, totals, stored_out, 
 
 def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
     """The paper's other filters on the stored sets of output frame f (the last
-    timed frame): the frame sharpness B(J) over the whole clip once, then `reps`
+    timed frame): the frame sharpness B(J) and a scene-space box mask over the
+    whole clip, then `reps`
     calls each of the plain filter, the deblurring filter (Eq. 5: B(J) times the
     Eq. 4 weight with the paper's colour and frame sigmas) and inpainting (Eq. 8-9,
     two steps, sigma 55/255) under a moving box mask over ~10 % of each frame.
@@ -190,18 +191,21 @@ def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
 
     bj = torch.empty((n,), dtype=torch.float32, device=dev)
     ms_sharp = timed(lambda: sg.scene_frame_sharpness(staged, out=bj), 3)
+    box_mask = torch.empty_like(mask)
+    ms_box = timed(lambda: sg.scene_box_mask(staged, (-1.0, -1.0, 0.5), (1.0, 1.0, 4.0), out=box_mask), 3)
     ms_plain = timed(lambda: sg.scene_filter(staged, sets, fparams, out=out), reps)
     ms_deblur = timed(lambda: sg.scene_filter_frames(staged, sets, deblur, bj, out=out), reps)
     ms_inpaint = timed(lambda: sg.scene_inpaint(staged, sets, mask, 55.0 / 255.0, 2, out=out), reps)
     alg = 12 * n_rec + 28 * h * w
     res = {"output_frame": f, "records": n_rec, "frames": n,
-           "frame_sharpness_ms_per_clip": ms_sharp,
+           "frame_sharpness_ms_per_clip": ms_sharp, "box_mask_ms_per_clip": ms_box,
            "plain_filter_ms": ms_plain, "deblur_filter_ms": ms_deblur,
            "deblur_roofline": {"bound": "hbm", "achieved": alg / (ms_deblur / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": alg / (ms_deblur / 1e3) / 1e9 / HBM_PEAK_GBS,
                                "alg_bytes_per_launch": alg},
            "inpaint_ms": ms_inpaint, "inpaint_masked_fraction": float(mask[f].float().mean().item())}
-    log(f"filters: B(J) {ms_sharp:.3f} ms/clip, plain {ms_plain:.3f}, deblur {ms_deblur:.3f}, "
+    log(f"filters: B(J) {ms_sharp:.3f} ms/clip, box mask {ms_box:.3f} ms/clip, plain {ms_plain:.3f}, "
+        f"deblur {ms_deblur:.3f}, "
         f"inpaint {ms_inpaint:.3f} ms/frame")
     return res
 

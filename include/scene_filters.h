@@ -63,6 +63,18 @@ sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t win
                         const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, int32_t steps,
                         float* out_rgb, void* stream);
 
+/* Inpainting masks from a scene-space region (Sec. 6, inpainting: the samples that
+ * fall into the region, projected back into the images, form M). M^J(q) = 1 when
+ * the scene point of pixel q = (x, y) of frame J lies in the world-space box
+ * [lo, hi] (bounds included), 0 otherwise and for pixels without a valid stored
+ * depth d (not finite, or <= 0). Float64, each sum left to right:
+ * X_cam = d ((x - cx) / fx, (y - cy) / fy, 1), X = R^J X_cam + t^J with
+ * C^J = cam_to_world[J] = [R^J | t^J].
+ * box: HOST [6] float64 = (x_lo, y_lo, z_lo, x_hi, y_hi, z_hi), each finite
+ * (lo > hi gives an empty mask), read before the call returns.
+ * mask: device [num_frames][H][W] uint8, every entry written (0 or 1). */
+sg_status scene_box_mask(const sg_clip* clip, const double* box, uint8_t* mask, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

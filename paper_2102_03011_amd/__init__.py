@@ -354,6 +354,21 @@ def scene_inpaint(clip: StagedClip, sets: SampleSets, mask: torch.Tensor, sigma_
     return out
 
 
+def scene_box_mask(clip: StagedClip, lo, hi, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Inpainting masks from a world-space box [lo, hi] (3 floats each): 1 where a
+    pixel's scene point lies inside -> [N, H, W] uint8."""
+    shape = (clip.num_frames, clip.height, clip.width)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.uint8, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.uint8)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    box = (ctypes.c_double * 6)(*[float(v) for v in lo], *[float(v) for v in hi])
+    cc = clip.c_struct()
+    _check(_lib.scene_box_mask(ctypes.byref(cc), box, out.data_ptr(), _stream_handle()), "scene_box_mask")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # learned per-sample weights
 

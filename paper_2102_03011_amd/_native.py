@@ -97,6 +97,7 @@ SIGNATURES = {
     "scene_inpaint": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_float, ctypes.c_int32,
                                       c_void_p, c_void_p]),
+    "scene_box_mask": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.POINTER(ctypes.c_double), c_void_p, c_void_p]),
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),

@@ -1,7 +1,7 @@
 // The paper's other filters over stored sample sets (Sec. 6): the per-frame
 // factor of deblurring (Eq. 5) and computational shutters (Eq. 10), the frame
-// sharpness B(J) that deblurring weights by, and inpainting by masked mean-shift
-// (Eq. 8-9). Same record layout and lane organisation as the denoising filter:
+// sharpness B(J) that deblurring weights by, inpainting by masked mean-shift
+// (Eq. 8-9) and its masks from a scene-space box. Same record layout and lane organisation as the denoising filter:
 // 16 lanes per output pixel stride through its CSR segment, each in a fixed
 // order, then a fixed butterfly combines them.
 //
@@ -333,6 +333,42 @@ __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Masks from a scene-space box: one thread per pixel of the clip, float64.
+
+struct WorldBox {
+  double lo[3], hi[3];
+};
+
+__global__ __launch_bounds__(256) void k_box_mask(const uint16_t* __restrict__ depth_, const double* __restrict__ c2w_,
+                                                  int width, int height, int64_t total, double fx, double fy,
+                                                  double cx, double cy, WorldBox box, uint8_t* __restrict__ mask) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t frame_px = static_cast<int64_t>(width) * height;
+  const int j = static_cast<int>(i / frame_px);
+  const int64_t self = i - static_cast<int64_t>(j) * frame_px;
+  const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const double d = static_cast<double>(h2f(to_global(depth_)[static_cast<size_t>(j) * pplane + padded_index(x, y, pw)]));
+  uint8_t m = 0;
+  if (d > 0.0 && d < INFINITY) {  // NaN fails both
+    const double xc = d * ((static_cast<double>(x) - cx) / fx);
+    const double yc = d * ((static_cast<double>(y) - cy) / fy);
+    const double zc = d;
+    gp<const double> c = to_global(c2w_) + static_cast<size_t>(j) * 16;
+    bool in = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double v = ((c[4 * k] * xc + c[4 * k + 1] * yc) + c[4 * k + 2] * zc) + c[4 * k + 3];
+      in = in && v >= box.lo[k] && v <= box.hi[k];
+    }
+    m = in ? 1 : 0;
+  }
+  to_global(mask)[i] = m;
+}
+
 // Workgroups of a 16-lanes-per-pixel launch over n_pix pixels (0 when it would not
 // fit a 32-bit grid).
 int64_t filter_blocks(int64_t n_pix) {
@@ -416,6 +452,23 @@ sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t win
                      0, static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->width,
                      clip->height, clip->num_frames, f0, window, n_pix, sets->offsets, sets->ids,
                      reinterpret_cast<const uint2*>(sets->crho), sets->capacity, mask, a_c, steps, out_rgb);
+  return hip_status(hipGetLastError());
+}
+
+sg_status scene_box_mask(const sg_clip* clip, const double* box, uint8_t* mask, void* stream) {
+  const sg_status s = check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if (box == nullptr || mask == nullptr) return SG_E_INVALID;
+  sg::WorldBox b{};
+  for (int k = 0; k < 3; ++k) {
+    if (!isfinite(box[k]) || !isfinite(box[k + 3])) return SG_E_INVALID;
+    b.lo[k] = box[k];
+    b.hi[k] = box[k + 3];
+  }
+  const int64_t total = static_cast<int64_t>(clip->num_frames) * clip->width * clip->height;
+  hipLaunchKernelGGL(sg::k_box_mask, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), clip->depth, clip->cam_to_world, clip->width, clip->height,
+                     total, clip->fx, clip->fy, clip->cx, clip->cy, b, mask);
   return hip_status(hipGetLastError());
 }
 

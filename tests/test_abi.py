@@ -34,7 +34,7 @@ def test_header_functions_are_exported(native):
     assert len(HEADERS) == 2
     names = [n for h in HEADERS for n in _declared_functions(h)]
     assert len(names) >= 11
-    assert {"scene_frame_sharpness", "scene_filter_frames", "scene_inpaint"} <= set(names)
+    assert {"scene_frame_sharpness", "scene_filter_frames", "scene_inpaint", "scene_box_mask"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
         assert n in mod.SIGNATURES, n
@@ -290,6 +290,21 @@ def test_inpaint_rejects_bad_arguments(native, case, expect):
         out = None
     assert lib.scene_inpaint(ctypes.byref(c), f0, f1, w, ctypes.byref(s), mask, sigma, steps, out, None) == expect, \
         case
+
+
+def test_box_mask_rejects_bad_arguments(native):
+    mod, lib = native
+    box = (ctypes.c_double * 6)(-1.0, -1.0, 0.5, 1.0, 1.0, 3.0)
+    c = _clip(mod)
+    assert lib.scene_box_mask(None, box, 0x90000, None) == 1
+    assert lib.scene_box_mask(ctypes.byref(c), None, 0x90000, None) == 1
+    assert lib.scene_box_mask(ctypes.byref(c), box, None, None) == 1
+    for k in range(6):
+        bad = (ctypes.c_double * 6)(*box)
+        bad[k] = math.nan if k % 2 else math.inf
+        assert lib.scene_box_mask(ctypes.byref(c), bad, 0x90000, None) == 1, k
+    c.depth = None
+    assert lib.scene_box_mask(ctypes.byref(c), box, 0x90000, None) == 1
 
 
 def test_stage_rejects_bad_arguments(native):

@@ -1,6 +1,7 @@
 """GPU parity of the paper's other filters over stored sets (Sec. 6): the frame
 sharpness B(J) and per-frame factors of deblurring (Eq. 5) and computational
-shutters (Eq. 10), and masked mean-shift inpainting (Eq. 8-9), through the C ABI
+shutters (Eq. 10), and masked mean-shift inpainting (Eq. 8-9) with its masks from
+a scene-space box, through the C ABI
 against the float64 oracle. All inputs are seeded and synthetic.
 """
 import math
@@ -194,3 +195,38 @@ def test_sets_past_the_arena_and_foreign_ids_give_nan(small):
     want_nan[seg[outside]] = True
     assert want_nan.any()
     assert np.array_equal(np.isnan(c).any(axis=1), want_nan)
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_box_mask_matches_oracle_and_feeds_inpainting(name, request):
+    wl, clip, staged, col, sets, orc, band = request.getfixturevalue(name)
+    sg = _sg()
+    f = orc.frame
+    dep = ostaging.depth_q(clip.depth.cpu().numpy())
+    cams = clip.cam_to_world.numpy()
+    pts = ofilters.scene_points(np.where(np.isfinite(dep) & (dep > 0), dep, 1.0), cams, clip.fx, clip.fy, clip.cx,
+                                clip.cy)
+    valid = np.isfinite(dep) & (dep > 0)
+    # a box around the middle of the scene points of the output frame
+    p = pts[f][valid[f]]
+    lo = [float(np.quantile(p[:, k], 0.3)) for k in range(3)]
+    hi = [float(np.quantile(p[:, k], 0.7)) for k in range(3)]
+    lo[2] = float(p[:, 2].min()) - 1.0
+    got = sg.scene_box_mask(staged, lo, hi).cpu().numpy()
+    want = ofilters.scene_box_mask(dep, cams, clip.fx, clip.fy, clip.cx, clip.cy, lo, hi)
+    # same float64 arithmetic in the same order: equal bits, except where a coordinate
+    # lies within 1e-12 of a face (none is expected)
+    near = np.zeros(dep.shape, dtype=bool)
+    for k in range(3):
+        for b in (lo[k], hi[k]):
+            near |= valid & (np.abs(pts[..., k] - b) <= 1e-12 * max(1.0, abs(b)))
+    assert set(np.unique(got)) <= {0, 1}
+    assert np.array_equal(got.astype(bool)[~near], want[~near])
+    assert 0 < want[f].mean() < 1
+    assert not got[~valid].any()
+    # inpainting under the box's masks, each side with its own
+    sigma = 55.0 / 255.0
+    out = sg.scene_inpaint(staged, sets, torch.from_numpy(got).cuda(), sigma).cpu().numpy()
+    ref = ofilters.inpaint_mean_shift(orc, col[f], wl.window, want, sigma)
+    if not near.any():
+        assert _err(out, ref, band) <= parity.COLOUR_TOL
