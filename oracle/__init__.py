@@ -19,6 +19,8 @@ Video Processing):
                 Gaussian denoising weight around the reference sample (Sec. 5.1 Eq. 4);
                 the per-frame factors of deblurring (Sec. 6 Eq. 5) and computational
                 shutters (Eq. 10); inpainting by masked mean-shift (Eq. 8-9)
+  frustum    -- the paper's depth-agnostic frustum gather (Sec. 4, Eq. 1-2) by its
+                definition, and the hull-rasterisation algorithm that pins it
   bruteforce -- all-pairs twin of `gather` for tiny inputs (pure Python loops)
   metrics    -- PSNR (Sec. 5.1, denoising PSNR figure)
 
