@@ -210,6 +210,32 @@ def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
     return res
 
 
+def frustum_leg(sg, clip, staged, f, window: int, reps: int) -> dict:
+    """The depth-agnostic frustum gather (l = 3, depth range 0.01 .. 1000) of output
+    frame f with a +-window window: count (carry, bucket, count, scan) and scatter,
+    event-timed; records per pixel and gathered records per second."""
+    import torch
+    prm = sg.FrustumParams(window=window)
+    ws = torch.empty(sg.scene_frustum_workspace_size(staged, f, prm), dtype=torch.uint8, device=staged.rgbd.device)
+    sets = sg.scene_gather_frustum(staged, f, prm, ws=ws)
+    torch.cuda.synchronize()
+    sets.check()
+    total = sets.total()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        sg.scene_gather_frustum(staged, f, prm, capacity=total, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    n_pix = clip.height * clip.width
+    res = {"window": window, "output_frame": f, "ms_per_frame": ms, "records": total,
+           "records_per_pixel": total / n_pix, "records_per_s": total / (ms / 1e3),
+           "workspace_gb": ws.numel() / 1e9}
+    log(f"frustum gather +-{window}: {ms:.2f} ms/frame, {total / n_pix:.0f} records per pixel")
+    return res
+
+
 def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int, with_curve: bool = True) -> dict:
     """The learned-weight filter on the same gathers (window +-w), timed like the plain
     step; PSNR of plain and learned on a few spread frames; and the learned path at
@@ -473,6 +499,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-fused", action="store_true", help="skip the fused gather + filter leg")
+    ap.add_argument("--frustum-window", type=int, default=0,
+                    help="also time the depth-agnostic frustum gather with this window (0: skip)")
     ap.add_argument("--no-filters", action="store_true",
                     help="skip the deblurring / inpainting filters leg")
     ap.add_argument("--no-curve", action="store_true",
@@ -609,6 +637,8 @@ def main() -> int:
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if args.frustum_window > 0:
+        res["frustum"] = frustum_leg(sg, clip, staged, timed[-1], args.frustum_window, max(2, args.steps // 2))
     if not args.no_filters:
         res["filters"] = filters_leg(sg, clip, staged, wl, arena, timed[-1], fparams, max(3, args.steps))
     if not args.no_fused:

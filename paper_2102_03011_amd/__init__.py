@@ -253,6 +253,51 @@ def scene_gather(clip: StagedClip, f0: int, f1: int, params: GatherParams, capac
 
 
 @dataclass
+class FrustumParams:
+    """Depth-agnostic frustum gather (include/scene_frustum.h): window +-w, frustum
+    side l pixels (the paper's 3), depth range [near, far] (0.01, 1000)."""
+    window: int
+    l: float = 3.0
+    near: float = 0.01
+    far: float = 1000.0
+
+    def c_struct(self) -> _native.SgFrustumParams:
+        return _native.SgFrustumParams(int(self.window), float(self.l), float(self.near), float(self.far))
+
+
+def scene_frustum_workspace_size(clip: StagedClip, f: int, params: FrustumParams) -> int:
+    out = ctypes.c_size_t(0)
+    cc, pp = clip.c_struct(), params.c_struct()
+    _check(_lib.scene_frustum_workspace_size(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(out)),
+           "scene_frustum_workspace_size")
+    return int(out.value)
+
+
+def scene_gather_frustum(clip: StagedClip, f: int, params: FrustumParams, capacity: int | None = None,
+                         ws: torch.Tensor | None = None) -> SampleSets:
+    """Sample sets of output frame f by the depth-agnostic frustum test (every
+    observation along each pixel's ray). capacity None: count, synchronise, size
+    the arena exactly, scatter; otherwise the arena holds `capacity` records (check
+    `sets.check()` afterwards)."""
+    if ws is None:
+        ws = torch.empty(scene_frustum_workspace_size(clip, f, params), dtype=torch.uint8, device=clip.rgbd.device)
+    _need_gpu(ws, "workspace", torch.uint8)
+    cc, pp = clip.c_struct(), params.c_struct()
+    tmp = alloc_sets(clip, f, f + 1, params.window, 0)
+    ts = tmp.c_struct()
+    _check(_lib.scene_frustum_count(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ts), ws.data_ptr(),
+                                    ws.numel(), _stream_handle()), "scene_frustum_count")
+    if capacity is None:
+        capacity = tmp.total()
+    sets = alloc_sets(clip, f, f + 1, params.window, capacity)
+    sets.offsets.copy_(tmp.offsets)
+    ss = sets.c_struct()
+    _check(_lib.scene_frustum_scatter(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ss), ws.data_ptr(),
+                                      ws.numel(), _stream_handle()), "scene_frustum_scatter")
+    return sets
+
+
+@dataclass
 class FilterParams:
     sigma_d: float = 0.01
     sigma_c: float = math.inf

@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/scene_gather.h and include/scene_filters.h.
+"""ctypes declarations of the C ABI in include/scene_gather.h, include/scene_filters.h
+and include/scene_frustum.h.
 
 Loads the in-tree libscenegather.so. There is no fallback: if the library is
 missing or fails to load, import of the binding raises.
@@ -18,6 +19,7 @@ SG_MAX_RADIUS = 3
 SG_APRON = 6
 SG_APRON_RIGHT = 7
 SG_MAX_INPAINT_STEPS = 16
+SG_MAX_FRUSTUM_L = 7.0
 
 c_void_p = ctypes.c_void_p
 
@@ -39,6 +41,11 @@ class SgGatherParams(ctypes.Structure):
 class SgSampleSets(ctypes.Structure):
     _fields_ = [("offsets", c_void_p), ("ids", c_void_p), ("crho", c_void_p),
                 ("capacity", ctypes.c_int64), ("status", c_void_p)]
+
+
+class SgFrustumParams(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("l", ctypes.c_float), ("near_z", ctypes.c_float),
+                ("far_z", ctypes.c_float)]
 
 
 class SgFilterParams(ctypes.Structure):
@@ -98,6 +105,12 @@ SIGNATURES = {
                                       ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_float, ctypes.c_int32,
                                       c_void_p, c_void_p]),
     "scene_box_mask": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.POINTER(ctypes.c_double), c_void_p, c_void_p]),
+    "scene_frustum_workspace_size": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32,
+                                                     ctypes.POINTER(SgFrustumParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "scene_frustum_count": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.POINTER(SgFrustumParams),
+                                            ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_frustum_scatter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.POINTER(SgFrustumParams),
+                                              ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_size_t, c_void_p]),
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),

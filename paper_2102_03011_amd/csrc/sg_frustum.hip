@@ -1,0 +1,374 @@
+// Depth-agnostic frustum gather (Sec. 4, Eq. 1-2).
+//
+// The paper rasterises, per output pixel p and window frame J, the convex hull of
+// p's frustum projected into J, an epipolar band that can cross the whole image,
+// and tests every pixel in it. Its dual is what the GPU runs here: a source pixel
+// q of J reaches only the output pixels within L1 distance l/2 of its point p'(q)
+// carried into the output view. Per window frame:
+//   carry   -- every q: p'(q), z'(q) in float32; q is kept when its depth is valid
+//              and near <= z' <= far, and filed under its nearest output pixel
+//              b(q) = round(p'(q)) on a grid extended by the bucket radius rb
+//              (a member has |p - b(q)|_1 < l/2 + 1, so rb = ceil(l/2 + 1) - 1);
+//   bucket  -- counting sort of the kept q by b(q) (count, scan, atomic fill: the
+//              order inside a bucket is arbitrary);
+//   count / scatter -- each output pixel reads the buckets within L1 distance rb,
+//              applies Eq. 2, and (scatter) emits its members of J in ascending q
+//              by repeated minimum, so the records come out in canonical order
+//              whatever order the buckets hold.
+// The member counts are scanned into the caller's CSR offsets between the passes.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <climits>
+
+#include "scene_frustum.h"
+#include "sg_device.h"
+#include "sg_internal.h"
+#include "sg_validate.h"
+
+namespace sg {
+namespace {
+
+constexpr int kMapFloats = 16;  // per window frame: M (3x3, row-major), k (3), padding
+constexpr int kThreads = 256;
+
+// a source pixel carried into the output view: p' = (x, y), z', bucket (-1: not kept)
+struct __attribute__((aligned(16))) Carried {
+  float x, y, z;
+  int32_t b;
+};
+
+int bucket_radius(float l) { return static_cast<int>(ceilf(0.5f * l + 1.0f)) - 1; }
+
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+struct FrustumLayout {
+  int jlo, n_j, rb;
+  int64_t n_pix, n_buckets;  // per window frame
+  size_t maps, carry, boff, bfill, items, partial, total;
+};
+
+FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_params* p) {
+  FrustumLayout l{};
+  l.jlo = f - p->window > 0 ? f - p->window : 0;
+  const int jhi = f + p->window < c->num_frames - 1 ? f + p->window : c->num_frames - 1;
+  l.n_j = jhi - l.jlo + 1;
+  l.rb = bucket_radius(p->l);
+  l.n_pix = static_cast<int64_t>(c->width) * c->height;
+  l.n_buckets = static_cast<int64_t>(c->width + 2 * l.rb) * (c->height + 2 * l.rb);
+  const int64_t scan_a = (l.n_j * l.n_buckets + kScanTile - 1) / kScanTile;
+  const int64_t scan_b = (l.n_pix + kScanTile - 1) / kScanTile;
+  size_t at = 0;
+  l.maps = at;
+  at += align_up(static_cast<size_t>(l.n_j) * kMapFloats * sizeof(float));
+  l.carry = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Carried));
+  l.boff = at;
+  at += align_up((static_cast<size_t>(l.n_j) * l.n_buckets + 1) * sizeof(int64_t));
+  l.bfill = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_buckets * sizeof(int32_t));
+  l.items = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(int32_t));
+  l.partial = at;
+  at += align_up(static_cast<size_t>((scan_a > scan_b ? scan_a : scan_b) + 1) * sizeof(int64_t));
+  l.total = at;
+  return l;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero(T* __restrict__ p, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    p[i] = T(0);
+}
+
+// (C^f)^-1 C^J in float64 (rigid: the inverse rotation is the transpose), folded
+// with K: a pixel (x, y) of J with depth d goes to Y = d M (x, y, 1) + k, z' = Y_3,
+// p' = (Y_1, Y_2) / Y_3. J = f gives exactly M = I, k = 0.
+__global__ __launch_bounds__(64) void k_frustum_pose(const double* __restrict__ c2w, int f, int jlo, int n_j,
+                                                     double fx, double fy, double cx, double cy,
+                                                     float* __restrict__ maps) {
+  for (int jn = threadIdx.x; jn < n_j; jn += 64) {
+    const int j = jlo + jn;
+    float* m = maps + jn * kMapFloats;
+    for (int i = 0; i < kMapFloats; ++i) m[i] = 0.0f;
+    if (j == f) {
+      m[0] = m[4] = m[8] = 1.0f;
+      continue;
+    }
+    const double* a = c2w + static_cast<size_t>(f) * 16;
+    const double* b = c2w + static_cast<size_t>(j) * 16;
+    double r[3][3], t[3], am[3][3];
+    for (int i = 0; i < 3; ++i) {
+      for (int k = 0; k < 3; ++k) r[i][k] = a[i] * b[k] + a[4 + i] * b[4 + k] + a[8 + i] * b[8 + k];
+      t[i] = a[i] * (b[3] - a[3]) + a[4 + i] * (b[7] - a[7]) + a[8 + i] * (b[11] - a[11]);
+    }
+    for (int i = 0; i < 3; ++i) {  // R K^-1
+      am[i][0] = r[i][0] / fx;
+      am[i][1] = r[i][1] / fy;
+      am[i][2] = r[i][2] - r[i][0] * cx / fx - r[i][1] * cy / fy;
+    }
+    for (int k = 0; k < 3; ++k) {  // K R K^-1
+      m[k] = static_cast<float>(fx * am[0][k] + cx * am[2][k]);
+      m[3 + k] = static_cast<float>(fy * am[1][k] + cy * am[2][k]);
+      m[6 + k] = static_cast<float>(am[2][k]);
+    }
+    m[9] = static_cast<float>(fx * t[0] + cx * t[2]);
+    m[10] = static_cast<float>(fy * t[1] + cy * t[2]);
+    m[11] = static_cast<float>(t[2]);
+  }
+}
+
+// grid (pixels / 256, window frames)
+__global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __restrict__ depth_,
+                                                            const float* __restrict__ maps, int width, int height,
+                                                            int jlo, int rb, float near_z, float far_z, int64_t n_pix,
+                                                            int64_t n_buckets, Carried* __restrict__ carry,
+                                                            unsigned long long* __restrict__ bcount) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (q >= n_pix) return;
+  const int jn = blockIdx.y;
+  const int y = static_cast<int>(q / width), x = static_cast<int>(q - static_cast<int64_t>(y) * width);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const float d = h2f(to_global(depth_)[static_cast<size_t>(jlo + jn) * pplane + padded_index(x, y, pw)]);
+  const float* m = maps + jn * kMapFloats;
+  int b = -1;
+  float px = 0.0f, py = 0.0f, z = 0.0f;
+  if (d > 0.0f && d < INFINITY) {
+    const float fx = static_cast<float>(x), fy = static_cast<float>(y);
+    const float y0 = fmaf(d, fmaf(m[0], fx, fmaf(m[1], fy, m[2])), m[9]);
+    const float y1 = fmaf(d, fmaf(m[3], fx, fmaf(m[4], fy, m[5])), m[10]);
+    z = fmaf(d, fmaf(m[6], fx, fmaf(m[7], fy, m[8])), m[11]);
+    if (z >= near_z && z <= far_z) {
+      px = y0 / z;
+      py = y1 / z;
+      const float ex = px + 0.5f, ey = py + 0.5f;
+      // NaN fails every comparison; the bounds keep b inside the extended grid
+      if (ex >= static_cast<float>(-rb) && ex < static_cast<float>(width + rb) && ey >= static_cast<float>(-rb) &&
+          ey < static_cast<float>(height + rb)) {
+        const int bx = static_cast<int>(floorf(ex)), by = static_cast<int>(floorf(ey));
+        b = (by + rb) * (width + 2 * rb) + (bx + rb);
+        atomicAdd(bcount + 1 + static_cast<int64_t>(jn) * n_buckets + b, 1ull);
+      }
+    }
+  }
+  carry[static_cast<int64_t>(jn) * n_pix + q] = Carried{px, py, z, b};
+}
+
+// grid (pixels / 256, window frames): file every kept q in its bucket
+__global__ __launch_bounds__(kThreads) void k_frustum_bucket(const Carried* __restrict__ carry,
+                                                             const int64_t* __restrict__ boff,
+                                                             int32_t* __restrict__ bfill, int64_t n_pix,
+                                                             int64_t n_buckets, int32_t* __restrict__ items) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (q >= n_pix) return;
+  const int jn = blockIdx.y;
+  const Carried c = carry[static_cast<int64_t>(jn) * n_pix + q];
+  const int b = c.b;
+  if (b < 0) return;
+  const int64_t e = static_cast<int64_t>(jn) * n_buckets + b;
+  const int slot = atomicAdd(bfill + e, 1);
+  to_global(items)[to_global(boff)[e] + slot] = static_cast<int32_t>(q);
+}
+
+// Calls fn(q, carried) for every q filed within L1 distance rb of output pixel
+// (x, y) in window frame jn and passing Eq. 2.
+template <typename Fn>
+__device__ __forceinline__ void for_members(const Carried* __restrict__ carry, const int32_t* __restrict__ items,
+                                            const int64_t* __restrict__ boff, int width, int rb, float half,
+                                            int64_t n_pix, int64_t n_buckets, int jn, int x, int y, Fn&& fn) {
+  const Carried* cj = carry + static_cast<int64_t>(jn) * n_pix;  // (struct copies take generic pointers)
+  gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
+  gp<const int32_t> it = to_global(items);
+  const int ew = width + 2 * rb;
+  const float fx = static_cast<float>(x), fy = static_cast<float>(y);
+  for (int dy = -rb; dy <= rb; ++dy) {
+    const int span = rb - (dy < 0 ? -dy : dy);
+    for (int dx = -span; dx <= span; ++dx) {
+      const int64_t b = static_cast<int64_t>(y + dy + rb) * ew + (x + dx + rb);
+      const int64_t e = bj[b + 1];
+      for (int64_t k = bj[b]; k < e; ++k) {
+        const int32_t q = it[k];
+        const Carried c = cj[q];
+        if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(q, c);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __restrict__ carry,
+                                                            const int32_t* __restrict__ items,
+                                                            const int64_t* __restrict__ boff, int width, int n_j,
+                                                            int rb, float half, int64_t n_pix, int64_t n_buckets,
+                                                            int64_t* __restrict__ counts) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (p >= n_pix) return;
+  const int y = static_cast<int>(p / width), x = static_cast<int>(p - static_cast<int64_t>(y) * width);
+  int64_t n = 0;
+  for (int jn = 0; jn < n_j; ++jn)
+    for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
+  to_global(counts)[p] = n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_frustum_scatter(
+    const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_, const Carried* __restrict__ carry,
+    const int32_t* __restrict__ items, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
+    int n_j, int rb, float half, int64_t n_pix, int64_t n_buckets, const int64_t* __restrict__ offsets_,
+    uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity, uint32_t* __restrict__ status_) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (p >= n_pix) return;
+  gp<uint32_t> status = to_global(status_);
+  const int64_t start = to_global(offsets_)[p], end = to_global(offsets_)[p + 1];
+  if (start < 0 || end < start) {
+    flag_or(status, SG_FLAG_INCONSISTENT);
+    return;
+  }
+  if (end > capacity) {
+    if (end > start) flag_or(status, SG_FLAG_CAPACITY);
+    return;
+  }
+  const int y = static_cast<int>(p / width), x = static_cast<int>(p - static_cast<int64_t>(y) * width);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const float dp = h2f(to_global(depth_)[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+  const bool has_ref = dp > 0.0f && dp < INFINITY;
+  gp<const uint2> rgbd = to_global(rgbd_);
+  gp<uint32_t> ids = to_global(ids_);
+  gp<uint2> crho = to_global(crho_);
+  int64_t cur = start;
+  for (int jn = 0; jn < n_j; ++jn) {
+    const int j = jlo + jn;
+    const uint32_t id_j = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
+    int32_t last = -1;
+    for (;;) {  // members of J in ascending q: the smallest one above the last emitted
+      int32_t best = INT_MAX;
+      float best_z = 0.0f;
+      for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+        if (q > last && q < best) {
+          best = q;
+          best_z = c.z;
+        }
+      });
+      if (best == INT_MAX) break;
+      if (cur < end) {  // a count that changed since pass 1 never writes past the segment
+        const int qy = best / width, qx = best - qy * width;
+        const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
+        const float rho = has_ref ? (best_z - dp) / dp : __builtin_nanf("");
+        st2(crho + cur, make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16)));
+        ids[cur] = id_j | static_cast<uint32_t>(best);
+      }
+      ++cur;
+      last = best;
+    }
+  }
+  if (cur != end) flag_or(status, SG_FLAG_INCONSISTENT);
+}
+
+sg_status check_frustum(const sg_clip* clip, int32_t f, const sg_frustum_params* p) {
+  sg_status s = check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if (p == nullptr) return SG_E_INVALID;
+  if (f < 0 || f >= clip->num_frames) return SG_E_INVALID;
+  if (p->window < 0) return SG_E_INVALID;
+  if (p->window > SG_MAX_WINDOW) return SG_E_UNSUPPORTED;
+  if (!(p->l > 0.0f) || !isfinite(p->l)) return SG_E_INVALID;
+  if (p->l > SG_MAX_FRUSTUM_L) return SG_E_UNSUPPORTED;
+  if (!(p->near_z > 0.0f) || !isfinite(p->far_z) || !(p->far_z > p->near_z)) return SG_E_INVALID;
+  return SG_OK;
+}
+
+struct FrustumCall {
+  FrustumLayout l;
+  float* maps;
+  Carried* carry;
+  int64_t* boff;
+  int32_t* bfill;
+  int32_t* items;
+  int64_t* partial;
+};
+
+sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_params* p, const sg_sample_sets* sets,
+                          void* ws, size_t ws_bytes, bool need_arena, FrustumCall* c) {
+  sg_status s = check_frustum(clip, f, p);
+  if (s != SG_OK) return s;
+  if (sets == nullptr || sets->offsets == nullptr || sets->status == nullptr || ws == nullptr) return SG_E_INVALID;
+  if (need_arena && (sets->capacity < 0 || (sets->capacity > 0 && (sets->ids == nullptr || sets->crho == nullptr))))
+    return SG_E_INVALID;
+  c->l = frustum_layout(clip, f, p);
+  if (ws_bytes < c->l.total) return SG_E_INVALID;
+  char* base = static_cast<char*>(ws);
+  c->maps = reinterpret_cast<float*>(base + c->l.maps);
+  c->carry = reinterpret_cast<Carried*>(base + c->l.carry);
+  c->boff = reinterpret_cast<int64_t*>(base + c->l.boff);
+  c->bfill = reinterpret_cast<int32_t*>(base + c->l.bfill);
+  c->items = reinterpret_cast<int32_t*>(base + c->l.items);
+  c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
+  return SG_OK;
+}
+
+unsigned zero_blocks(int64_t n) {
+  const int64_t b = (n + kThreads - 1) / kThreads;
+  return static_cast<unsigned>(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+}  // namespace
+}  // namespace sg
+
+using sg::hip_status;
+
+extern "C" {
+
+sg_status scene_frustum_workspace_size(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
+                                       size_t* bytes) {
+  const sg_status s = sg::check_frustum(clip, f, params);
+  if (s != SG_OK) return s;
+  if (bytes == nullptr) return SG_E_INVALID;
+  *bytes = sg::frustum_layout(clip, f, params).total;
+  return SG_OK;
+}
+
+sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
+                              sg_sample_sets* sets, void* workspace, size_t workspace_bytes, void* stream) {
+  sg::FrustumCall c{};
+  sg_status s = sg::frustum_prepare(clip, f, params, sets, workspace, workspace_bytes, false, &c);
+  if (s != SG_OK) return s;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const sg::FrustumLayout& l = c.l;
+  const int64_t n_bk = static_cast<int64_t>(l.n_j) * l.n_buckets;
+  const dim3 per_pixel(static_cast<unsigned>((l.n_pix + sg::kThreads - 1) / sg::kThreads));
+  const dim3 per_pixel_frame(per_pixel.x, static_cast<unsigned>(l.n_j));
+  const float half = 0.5f * params->l;
+  hipLaunchKernelGGL(sg::k_zero<int64_t>, dim3(sg::zero_blocks(n_bk + 1)), dim3(sg::kThreads), 0, st, c.boff,
+                     n_bk + 1);
+  hipLaunchKernelGGL(sg::k_zero<int32_t>, dim3(sg::zero_blocks(n_bk)), dim3(sg::kThreads), 0, st, c.bfill, n_bk);
+  hipLaunchKernelGGL(sg::k_frustum_pose, dim3(1), dim3(64), 0, st, clip->cam_to_world, f, l.jlo, l.n_j, clip->fx,
+                     clip->fy, clip->cx, clip->cy, c.maps);
+  hipLaunchKernelGGL(sg::k_frustum_carry, per_pixel_frame, dim3(sg::kThreads), 0, st, clip->depth, c.maps,
+                     clip->width, clip->height, l.jlo, l.rb, params->near_z, params->far_z, l.n_pix, l.n_buckets,
+                     c.carry, reinterpret_cast<unsigned long long*>(c.boff));
+  if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
+  hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st, c.carry, c.boff, c.bfill,
+                     l.n_pix, l.n_buckets, c.items);
+  hipLaunchKernelGGL(sg::k_frustum_count, per_pixel, dim3(sg::kThreads), 0, st, c.carry, c.items, c.boff,
+                     clip->width, l.n_j, l.rb, half, l.n_pix, l.n_buckets, sets->offsets + 1);
+  return hip_status(sg::launch_scan(sets->offsets, l.n_pix, c.partial, st));
+}
+
+sg_status scene_frustum_scatter(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
+                                sg_sample_sets* sets, void* workspace, size_t workspace_bytes, void* stream) {
+  sg::FrustumCall c{};
+  const sg_status s = sg::frustum_prepare(clip, f, params, sets, workspace, workspace_bytes, true, &c);
+  if (s != SG_OK) return s;
+  const sg::FrustumLayout& l = c.l;
+  hipLaunchKernelGGL(sg::k_frustum_scatter, dim3(static_cast<unsigned>((l.n_pix + sg::kThreads - 1) / sg::kThreads)),
+                     dim3(sg::kThreads), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.carry, c.items, c.boff, clip->width,
+                     clip->height, f, params->window, l.jlo, l.n_j, l.rb, 0.5f * params->l, l.n_pix, l.n_buckets,
+                     sets->offsets, sets->ids, reinterpret_cast<uint2*>(sets->crho), sets->capacity, sets->status);
+  return hip_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -31,9 +31,10 @@ def _declared_functions(path):
 
 def test_header_functions_are_exported(native):
     mod, lib = native
-    assert len(HEADERS) == 2
+    assert len(HEADERS) == 3
     names = [n for h in HEADERS for n in _declared_functions(h)]
-    assert len(names) >= 11
+    assert len(names) >= 14
+    assert {"scene_frustum_workspace_size", "scene_frustum_count", "scene_frustum_scatter"} <= set(names)
     assert {"scene_frame_sharpness", "scene_filter_frames", "scene_inpaint", "scene_box_mask"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
@@ -305,6 +306,60 @@ def test_box_mask_rejects_bad_arguments(native):
         assert lib.scene_box_mask(ctypes.byref(c), bad, 0x90000, None) == 1, k
     c.depth = None
     assert lib.scene_box_mask(ctypes.byref(c), box, 0x90000, None) == 1
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_clip", 1), ("f_neg", 1), ("f_past_end", 1), ("neg_window", 1), ("big_window", 4), ("l_zero", 1),
+    ("l_nan", 1), ("l_big", 4), ("near_zero", 1), ("far_below_near", 1), ("far_inf", 1), ("null_params", 1),
+    ("null_depth", 1), ("null_sets", 1), ("null_status", 1), ("null_ws", 1), ("small_ws", 1),
+])
+def test_frustum_rejects_bad_arguments(native, case, expect):
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgFrustumParams(2, 3.0, 0.01, 1000.0)
+    need = ctypes.c_size_t(0)
+    assert lib.scene_frustum_workspace_size(ctypes.byref(c), 4, ctypes.byref(p), ctypes.byref(need)) == 0
+    assert need.value > 5 * 64 * 32 * 20
+    s = _sets(mod, 100)
+    f, ws, wsb = 4, 0x80000, need.value
+    cp, pp = ctypes.byref(c), ctypes.byref(p)
+    if case == "null_clip":
+        cp = None
+    elif case == "f_neg":
+        f = -1
+    elif case == "f_past_end":
+        f = 10
+    elif case == "neg_window":
+        p.window = -1
+    elif case == "big_window":
+        p.window = 512
+    elif case == "l_zero":
+        p.l = 0.0
+    elif case == "l_nan":
+        p.l = math.nan
+    elif case == "l_big":
+        p.l = 7.5
+    elif case == "near_zero":
+        p.near_z = 0.0
+    elif case == "far_below_near":
+        p.far_z = 0.005
+    elif case == "far_inf":
+        p.far_z = math.inf
+    elif case == "null_params":
+        pp = None
+    elif case == "null_depth":
+        c.depth = None
+    elif case == "null_sets":
+        s = None
+    elif case == "null_status":
+        s.status = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb -= 1
+    sp = ctypes.byref(s) if s is not None else None
+    for fn in (lib.scene_frustum_count, lib.scene_frustum_scatter):
+        assert fn(cp, f, pp, sp, ws, wsb, None) == expect, (case, fn)
 
 
 def test_stage_rejects_bad_arguments(native):

@@ -1,0 +1,141 @@
+"""GPU parity of the depth-agnostic frustum gather (Sec. 4, Eq. 1-2) through the C
+ABI against the float64 oracle's definition; all inputs seeded and synthetic."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import filters as ofilters
+from oracle import frustum as ofr
+from oracle import staging as ostaging
+from scenegen import configs, generate
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _sg():
+    import paper_2102_03011_amd as sg
+    return sg
+
+
+def _stage(clip):
+    sg = _sg()
+    return sg.scene_stage(clip.rgb_u8.to("cuda").contiguous(), clip.depth.to("cuda").contiguous(),
+                          clip.cam_to_world.to("cuda").contiguous(), clip.fx, clip.fy, clip.cx, clip.cy)
+
+
+def _ragged_invalid(clip):
+    d = clip.depth.clone()
+    m = torch.rand(d.shape, generator=torch.Generator().manual_seed(5))
+    d[m < 0.03] = float("nan")
+    d[(m >= 0.03) & (m < 0.05)] = 0.0
+    d[(m >= 0.05) & (m < 0.06)] = float("inf")
+    d[(m >= 0.06) & (m < 0.07)] = 0.005
+    clip.depth = d
+    return clip
+
+
+def _case(name):
+    if name == "small":
+        wl = configs.tiny(seed=4, width=64, height=48, n_frames=5, window=2)
+        clip, f = generate(wl.spec), 2
+    else:
+        wl = configs.tiny(seed=9, width=100, height=37, n_frames=7, window=3, pose_rot_deg=1.0, pose_trans_m=0.03)
+        clip, f = _ragged_invalid(generate(wl.spec)), 3
+    staged = _stage(clip)
+    col = ostaging.colour_q(clip.rgb_u8.cpu().numpy())
+    dep = ostaging.depth_q(clip.depth.cpu().numpy())
+    orc = ofr.gather_frustum(col, dep, clip.cam_to_world.numpy(), clip.fx, clip.fy, clip.cx, clip.cy, f,
+                             ofr.FrustumParams(window=wl.window))
+    return wl, clip, staged, col, dep, f, orc
+
+
+@pytest.fixture(scope="module", params=["small", "ragged"])
+def case(request):
+    return _case(request.param)
+
+
+def _unsure(orc):
+    seg = np.repeat(np.arange(orc.offsets.size - 1), np.diff(orc.offsets))
+    u = orc.near_miss.copy()
+    u[seg[orc.marginal]] = True
+    return u
+
+
+def test_frustum_sets_match_oracle(case):
+    wl, clip, staged, col, dep, f, orc = case
+    sg = _sg()
+    h, w = clip.height, clip.width
+    sets = sg.scene_gather_frustum(staged, f, sg.FrustumParams(window=wl.window))
+    torch.cuda.synchronize()
+    sets.check()
+    g_off, g_ids, g_crho = parity.gpu_sets_to_host(sets, 0, h * w)
+    unsure = _unsure(orc)
+    assert unsure.mean() < 0.2
+    assert orc.offsets[-1] > 5 * h * w          # depth-agnostic sets: several samples per pixel
+    dp = dep[f].reshape(-1)
+    for i in np.flatnonzero(~unsure):
+        a, b = g_off[i], g_off[i + 1]
+        c, d = orc.offsets[i], orc.offsets[i + 1]
+        assert np.array_equal(g_ids[a:b], orc.ids[c:d]), i
+        got_col = parity.f16_to_f64(g_crho[a:b, :3].copy())
+        assert np.array_equal(got_col, orc.colour[c:d]), i
+        got_rho = parity.f16_to_f64(g_crho[a:b, 3].copy())
+        want = orc.rho[c:d]
+        if not (np.isfinite(dp[i]) and dp[i] > 0):
+            assert np.isnan(got_rho).all() and np.isnan(want).all(), i
+        else:
+            # binary16 rounding of a float32 value: half an ulp (2^-11 relative) + float32 error
+            assert np.all(np.abs(got_rho - want) <= 2.0 ** -11 * np.abs(want) + 1e-5), i
+
+
+def test_frustum_sets_filter_like_the_oracle(case):
+    wl, clip, staged, col, dep, f, orc = case
+    sg = _sg()
+    h, w = clip.height, clip.width
+    sets = sg.scene_gather_frustum(staged, f, sg.FrustumParams(window=wl.window))
+    out = sg.scene_filter(staged, sets, sg.FilterParams(sigma_d=0.01)).cpu().numpy().reshape(-1, 3)
+    c_ref = col[f].reshape(-1, 3)[orc.pixels]
+    dj = (orc.ids.astype(np.int64) >> 22) - wl.window
+    want = ofilters.weighted_mean(orc.offsets, orc.colour, orc.rho, dj, c_ref, 0.01)
+    # pixels with a member near their own depth (|rho| < 0.1): their weights cannot
+    # all vanish on either side. (A pixel below the near plane, depth 0.005 in the
+    # ragged clip, has lost its own sample; every member's depth Gaussian underflows,
+    # to 0 / 0 on both sides.)
+    seg = np.repeat(np.arange(orc.offsets.size - 1), np.diff(orc.offsets))
+    close = np.zeros(orc.offsets.size - 1, dtype=bool)
+    close[seg[np.abs(orc.rho) < 0.1]] = True
+    keep = ~_unsure(orc) & close
+    assert keep.mean() > 0.7
+    got = out[keep].astype(np.float64)
+    assert np.isfinite(got).all()
+    err = np.abs(got - want[keep]).max()
+    assert err <= parity.COLOUR_TOL, err
+
+
+def test_frustum_capacity_overflow_flag_and_no_overrun():
+    wl, clip, staged, col, dep, f, orc = _case("small")
+    sg = _sg()
+    prm = sg.FrustumParams(window=wl.window)
+    exact = sg.scene_gather_frustum(staged, f, prm)
+    total = exact.total()
+    cap = total // 2
+    big = sg.alloc_sets(staged, f, f + 1, wl.window, total)
+    big.ids.fill_(-7)
+    ws = torch.empty(sg.scene_frustum_workspace_size(staged, f, prm), dtype=torch.uint8, device="cuda")
+    short = sg.SampleSets(f, f + 1, wl.window, big.offsets, big.ids[:cap], big.crho[:cap], big.status)
+    import ctypes
+    cc, pp = staged.c_struct(), prm.c_struct()
+    lib = sg._lib
+    ss = short.c_struct()
+    assert lib.scene_frustum_count(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ss), ws.data_ptr(),
+                                   ws.numel(), None) == 0
+    assert lib.scene_frustum_scatter(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ss), ws.data_ptr(),
+                                     ws.numel(), None) == 0
+    torch.cuda.synchronize()
+    assert short.flags() & sg.SG_FLAG_CAPACITY
+    assert bool((big.ids[cap:] == -7).all())
+    off = big.offsets.cpu().numpy()
+    last = int(off[1:][off[1:] <= cap].max())
+    assert torch.equal(big.ids[:last], exact.ids[:last])
