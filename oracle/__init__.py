@@ -21,6 +21,8 @@ Video Processing):
                 shutters (Eq. 10); inpainting by masked mean-shift (Eq. 8-9)
   frustum    -- the paper's depth-agnostic frustum gather (Sec. 4, Eq. 1-2) by its
                 definition, and the hull-rasterisation algorithm that pins it
+  depth      -- data-term-only multi-view depth over a temporal window (Sec. 3,
+                preprocessing: 3x3 RGB SSD along the epipolar lines, lowest mean cost)
   bruteforce -- all-pairs twin of `gather` for tiny inputs (pure Python loops)
   metrics    -- PSNR (Sec. 5.1, denoising PSNR figure)
 

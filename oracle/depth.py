@@ -1,0 +1,63 @@
+"""Data-term-only multi-view depth (Sec. 3, preprocessing) -- test infrastructure only.
+
+For each pixel p of frame f the paper searches along the epipolar lines of the
+frames in a temporal window and keeps the depth with the lowest average cost, the
+cost being the sum of squared RGB differences over 3x3 patches; there is no
+smoothness term. Readings (the paper names only the data term and the patch):
+  - the search runs over a given list of depth hypotheses d_k (each one a point on
+    every epipolar line at once);
+  - for hypothesis d, p's scene point X = C^f [d K^-1 (p_x, p_y, 1), 1] is projected
+    into frame J and rounded to the nearest pixel q_J; the patch cost is
+    sum over the 3x3 offsets o of |I^f(p + o) - I^J(q_J + o)|^2 (RGB);
+  - a frame J counts for d when X lies in front of it (depth > 0) and both patches
+    lie inside their images; cost(d) is the mean over the counted frames, and a
+    hypothesis no frame counts for is not a candidate;
+  - D(p) = the hypothesis of least cost, the lowest index on ties; NaN when p has no
+    candidate (its own patch leaves the image, or no frame sees it).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import poses as _poses
+
+
+def patch_ssd(a: np.ndarray, ay: int, ax: int, b: np.ndarray, by: int, bx: int) -> float:
+    """Sum of squared RGB differences of the 3x3 patches centred at (ax, ay) in a and (bx, by) in b."""
+    pa = a[ay - 1:ay + 2, ax - 1:ax + 2, :]
+    pb = b[by - 1:by + 2, bx - 1:bx + 2, :]
+    return float(np.sum((pa - pb) ** 2))
+
+
+def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
+                   f: int, window: int, hypotheses: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """D^f and the least average cost per pixel, [H, W] each (float64).
+    colour [N, H, W, 3]; the frames J != f in [f - window, f + window] are searched."""
+    n, h, w = colour.shape[:3]
+    k = _poses.intrinsics(fx, fy, cx, cy)
+    kinv = np.linalg.inv(k)
+    others = [j for j in range(max(0, f - window), min(n - 1, f + window) + 1) if j != f]
+    to_j = {j: np.linalg.inv(cam_to_world[j]) @ cam_to_world[f] for j in others}
+    depth = np.full((h, w), np.nan)
+    best = np.full((h, w), np.inf)
+    for y in range(1, h - 1):
+        for x in range(1, w - 1):
+            ray = kinv @ np.array([x, y, 1.0])
+            for d in hypotheses:
+                xf = np.append(d * ray, 1.0)
+                costs = []
+                for j in others:
+                    yj = to_j[j] @ xf
+                    if yj[2] <= 0:
+                        continue
+                    u = k[0, 0] * yj[0] / yj[2] + k[0, 2]
+                    v = k[1, 1] * yj[1] / yj[2] + k[1, 2]
+                    qx, qy = int(np.floor(u + 0.5)), int(np.floor(v + 0.5))
+                    if 1 <= qx < w - 1 and 1 <= qy < h - 1:
+                        costs.append(patch_ssd(colour[f], y, x, colour[j], qy, qx))
+                if costs:
+                    c = float(np.mean(costs))
+                    if c < best[y, x]:
+                        best[y, x] = c
+                        depth[y, x] = d
+    return depth, best
