@@ -13,13 +13,22 @@ smoothness term. Readings (the paper names only the data term and the patch):
     lie inside their images; cost(d) is the mean over the counted frames, and a
     hypothesis no frame counts for is not a candidate;
   - D(p) = the hypothesis of least cost, the lowest index on ties; NaN when p has no
-    candidate (its own patch leaves the image, or no frame sees it).
+    candidate (its own patch leaves the image, or no frame sees it); a hypothesis
+    that is not finite and positive is not a candidate.
+For comparisons with a float32 evaluation, `estimate_depth` also flags pixels
+whose decision float32 may take differently: a projection within `rnd_band`
+pixels of a rounding boundary (a half-integer; the default suits 1080p
+coordinates), or a best cost within COST_BAND (relative) of a different cost of
+another candidate (equal costs come from equal patches and tie alike in float32).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import poses as _poses
+
+RND_BAND = 1e-3
+COST_BAND = 1e-4
 
 
 def patch_ssd(a: np.ndarray, ay: int, ax: int, b: np.ndarray, by: int, bx: int) -> float:
@@ -30,9 +39,11 @@ def patch_ssd(a: np.ndarray, ay: int, ax: int, b: np.ndarray, by: int, bx: int) 
 
 
 def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
-                   f: int, window: int, hypotheses: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """D^f and the least average cost per pixel, [H, W] each (float64).
-    colour [N, H, W, 3]; the frames J != f in [f - window, f + window] are searched."""
+                   f: int, window: int, hypotheses: np.ndarray, with_bands: bool = False,
+                   rnd_band: float = RND_BAND):
+    """D^f and the least average cost per pixel, [H, W] each (float64), and with
+    with_bands the band flags [H, W] bool. colour [N, H, W, 3]; the frames J != f in
+    [f - window, f + window] are searched."""
     n, h, w = colour.shape[:3]
     k = _poses.intrinsics(fx, fy, cx, cy)
     kinv = np.linalg.inv(k)
@@ -40,10 +51,14 @@ def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: 
     to_j = {j: np.linalg.inv(cam_to_world[j]) @ cam_to_world[f] for j in others}
     depth = np.full((h, w), np.nan)
     best = np.full((h, w), np.inf)
+    band = np.zeros((h, w), dtype=bool)
     for y in range(1, h - 1):
         for x in range(1, w - 1):
             ray = kinv @ np.array([x, y, 1.0])
+            all_costs = []
             for d in hypotheses:
+                if not (np.isfinite(d) and d > 0):
+                    continue
                 xf = np.append(d * ray, 1.0)
                 costs = []
                 for j in others:
@@ -52,12 +67,23 @@ def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: 
                         continue
                     u = k[0, 0] * yj[0] / yj[2] + k[0, 2]
                     v = k[1, 1] * yj[1] / yj[2] + k[1, 2]
+                    for c_ in (u, v):
+                        if abs(c_ + 0.5 - np.floor(c_ + 0.5)) <= rnd_band or abs(c_ + 0.5 - np.ceil(c_ + 0.5)) <= rnd_band:
+                            band[y, x] = True
                     qx, qy = int(np.floor(u + 0.5)), int(np.floor(v + 0.5))
                     if 1 <= qx < w - 1 and 1 <= qy < h - 1:
                         costs.append(patch_ssd(colour[f], y, x, colour[j], qy, qx))
                 if costs:
                     c = float(np.mean(costs))
+                    all_costs.append(c)
                     if c < best[y, x]:
                         best[y, x] = c
                         depth[y, x] = d
+            if len(all_costs) > 1:
+                lo = min(all_costs)
+                gaps = [c - lo for c in all_costs if c > lo]
+                if gaps and min(gaps) <= COST_BAND * max(lo, 1e-30):
+                    band[y, x] = True
+    if with_bands:
+        return depth, best, band
     return depth, best

@@ -297,6 +297,25 @@ def scene_gather_frustum(clip: StagedClip, f: int, params: FrustumParams, capaci
     return sets
 
 
+def scene_estimate_depth(clip: StagedClip, f: int, window: int, hypotheses: torch.Tensor,
+                         with_cost: bool = True) -> tuple[torch.Tensor, torch.Tensor | None]:
+    """Data-term-only depth of frame f over the hypotheses [K] float32 (GPU):
+    -> (depth [H, W], least mean patch cost [H, W] or None), float32."""
+    _need_gpu(hypotheses, "hypotheses", torch.float32)
+    dev = clip.rgbd.device
+    nbytes = ctypes.c_size_t(0)
+    cc = clip.c_struct()
+    _check(_lib.scene_depth_workspace_size(ctypes.byref(cc), f, window, ctypes.byref(nbytes)),
+           "scene_depth_workspace_size")
+    ws = torch.empty(max(1, int(nbytes.value)), dtype=torch.uint8, device=dev)
+    depth = torch.empty((clip.height, clip.width), dtype=torch.float32, device=dev)
+    cost = torch.empty_like(depth) if with_cost else None
+    _check(_lib.scene_estimate_depth(ctypes.byref(cc), f, window, hypotheses.data_ptr(), int(hypotheses.numel()),
+                                     depth.data_ptr(), cost.data_ptr() if cost is not None else None,
+                                     ws.data_ptr(), ws.numel(), _stream_handle()), "scene_estimate_depth")
+    return depth, cost
+
+
 @dataclass
 class FilterParams:
     sigma_d: float = 0.01

@@ -1,5 +1,5 @@
-"""ctypes declarations of the C ABI in include/scene_gather.h, include/scene_filters.h
-and include/scene_frustum.h.
+"""ctypes declarations of the C ABI in include/scene_gather.h, include/scene_filters.h,
+include/scene_frustum.h and include/scene_depth.h.
 
 Loads the in-tree libscenegather.so. There is no fallback: if the library is
 missing or fails to load, import of the binding raises.
@@ -20,6 +20,7 @@ SG_APRON = 6
 SG_APRON_RIGHT = 7
 SG_MAX_INPAINT_STEPS = 16
 SG_MAX_FRUSTUM_L = 7.0
+SG_MAX_DEPTH_HYPOTHESES = 4096
 
 c_void_p = ctypes.c_void_p
 
@@ -111,6 +112,11 @@ SIGNATURES = {
                                             ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_size_t, c_void_p]),
     "scene_frustum_scatter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.POINTER(SgFrustumParams),
                                               ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_depth_workspace_size": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "scene_estimate_depth": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, c_void_p,
+                                             ctypes.c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_size_t,
+                                             c_void_p]),
     "scene_filter_learned": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                              ctypes.POINTER(SgMlp), c_void_p, ctypes.c_size_t, c_void_p, c_void_p]),

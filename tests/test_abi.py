@@ -31,9 +31,10 @@ def _declared_functions(path):
 
 def test_header_functions_are_exported(native):
     mod, lib = native
-    assert len(HEADERS) == 3
+    assert len(HEADERS) == 4
     names = [n for h in HEADERS for n in _declared_functions(h)]
-    assert len(names) >= 14
+    assert len(names) >= 16
+    assert {"scene_depth_workspace_size", "scene_estimate_depth"} <= set(names)
     assert {"scene_frustum_workspace_size", "scene_frustum_count", "scene_frustum_scatter"} <= set(names)
     assert {"scene_frame_sharpness", "scene_filter_frames", "scene_inpaint", "scene_box_mask"} <= set(names)
     for n in names:
@@ -360,6 +361,45 @@ def test_frustum_rejects_bad_arguments(native, case, expect):
     sp = ctypes.byref(s) if s is not None else None
     for fn in (lib.scene_frustum_count, lib.scene_frustum_scatter):
         assert fn(cp, f, pp, sp, ws, wsb, None) == expect, (case, fn)
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_clip", 1), ("f_neg", 1), ("f_past_end", 1), ("neg_window", 1), ("big_window", 4), ("null_hyp", 1),
+    ("zero_hyp", 1), ("many_hyp", 4), ("null_out", 1), ("null_ws", 1), ("small_ws", 1), ("null_rgbd", 1),
+])
+def test_depth_rejects_bad_arguments(native, case, expect):
+    mod, lib = native
+    c = _clip(mod)
+    need = ctypes.c_size_t(0)
+    assert lib.scene_depth_workspace_size(ctypes.byref(c), 4, 2, ctypes.byref(need)) == 0
+    assert need.value == 5 * 16 * 4
+    f, w, hyp, n_hyp, out, ws, wsb = 4, 2, 0xB0000, 8, 0x90000, 0xA0000, need.value
+    cp = ctypes.byref(c)
+    if case == "null_clip":
+        cp = None
+    elif case == "f_neg":
+        f = -1
+    elif case == "f_past_end":
+        f = 10
+    elif case == "neg_window":
+        w = -1
+    elif case == "big_window":
+        w = 512
+    elif case == "null_hyp":
+        hyp = None
+    elif case == "zero_hyp":
+        n_hyp = 0
+    elif case == "many_hyp":
+        n_hyp = mod.SG_MAX_DEPTH_HYPOTHESES + 1
+    elif case == "null_out":
+        out = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb -= 1
+    elif case == "null_rgbd":
+        c.rgbd = None
+    assert lib.scene_estimate_depth(cp, f, w, hyp, n_hyp, out, None, ws, wsb, None) == expect, case
 
 
 def test_stage_rejects_bad_arguments(native):
