@@ -236,6 +236,27 @@ def frustum_leg(sg, clip, staged, f, window: int, reps: int) -> dict:
     return res
 
 
+def depth_leg(sg, clip, staged, f, n_hyp: int, reps: int) -> dict:
+    """Data-term depth of frame f over +-2 frames and n_hyp hypotheses spaced
+    uniformly in inverse depth over [1, 30] m, event-timed."""
+    import torch
+    hyp = (1.0 / torch.linspace(1.0, 1.0 / 30.0, n_hyp, dtype=torch.float64)).to(torch.float32).cuda()
+    sg.scene_estimate_depth(staged, f, 2, hyp)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        sg.scene_estimate_depth(staged, f, 2, hyp)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    n_pix = clip.height * clip.width
+    res = {"window": 2, "hypotheses": n_hyp, "ms_per_frame": ms,
+           "patch_costs_per_s": n_pix * n_hyp * 4 / (ms / 1e3)}
+    log(f"depth estimate: {ms:.2f} ms/frame ({n_hyp} hypotheses, 4 frames)")
+    return res
+
+
 def learned_leg(sg, clip, staged, wl, params, fparams, timed, plain_ms, steps: int, with_curve: bool = True) -> dict:
     """The learned-weight filter on the same gathers (window +-w), timed like the plain
     step; PSNR of plain and learned on a few spread frames; and the learned path at
@@ -499,6 +520,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-fused", action="store_true", help="skip the fused gather + filter leg")
+    ap.add_argument("--depth-hypotheses", type=int, default=0,
+                    help="also time the data-term depth estimate with this many hypotheses (0: skip)")
     ap.add_argument("--frustum-window", type=int, default=0,
                     help="also time the depth-agnostic frustum gather with this window (0: skip)")
     ap.add_argument("--no-filters", action="store_true",
@@ -637,6 +660,8 @@ def main() -> int:
         "psnr_db": {"noisy_input": 10 * math.log10(1 / mse_n), "plain_filter": 10 * math.log10(1 / mse_f)},
         "gpu": torch.cuda.get_device_name(0),
     }
+    if args.depth_hypotheses > 0:
+        res["depth"] = depth_leg(sg, clip, staged, timed[-1], args.depth_hypotheses, max(2, args.steps // 2))
     if args.frustum_window > 0:
         res["frustum"] = frustum_leg(sg, clip, staged, timed[-1], args.frustum_window, max(2, args.steps // 2))
     if not args.no_filters:
