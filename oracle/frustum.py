@@ -92,9 +92,9 @@ def gather_frustum(colour: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarr
     pixels = np.asarray(pixels, dtype=np.int64)
     slot = -np.ones(h * w, dtype=np.int64)
     slot[pixels] = np.arange(pixels.size)
-    members = [[] for _ in range(pixels.size)]     # (id, rho, colour, marginal)
-    near_miss = np.zeros(pixels.size, dtype=bool)
     dp = depth[f].reshape(-1)
+    parts = []     # (slot, id, rho, colour, marginal) per window frame and offset
+    near_miss = np.zeros(pixels.size, dtype=bool)
     j_lo, j_hi = max(0, f - prm.window), min(n_frames - 1, f + prm.window)
     for j in range(j_lo, j_hi + 1):
         px, py, z = carried_into_output(depth[j], cam_to_world[j], cam_to_world[f], k)
@@ -102,39 +102,48 @@ def gather_frustum(colour: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarr
             ok = np.isfinite(depth[j]) & (depth[j] > 0) & np.isfinite(px) & np.isfinite(py)
             in_z = (z >= prm.near) & (z <= prm.far)
             z_marg = (np.abs(z - prm.near) <= Z_BAND * prm.near) | (np.abs(z - prm.far) <= Z_BAND * prm.far)
-        for qy, qx in zip(*np.nonzero(ok & (in_z | z_marg))):
-            q = int(qy) * w + int(qx)
-            ax, ay = px[qy, qx], py[qy, qx]
-            bx, by = int(np.floor(ax)), int(np.floor(ay))
-            for oy in range(by - reach, by + reach + 1):
-                for ox in range(bx - reach, bx + reach + 1):
-                    if not (0 <= ox < w and 0 <= oy < h):
-                        continue
-                    i = slot[oy * w + ox]
-                    if i < 0:
-                        continue
-                    dist = abs(ox - ax) + abs(oy - ay)
-                    marg = bool(z_marg[qy, qx]) or abs(dist - half) <= L1_BAND
-                    if dist < half and in_z[qy, qx]:
-                        d_ref = dp[oy * w + ox]
-                        rho = (z[qy, qx] - d_ref) / d_ref if (np.isfinite(d_ref) and d_ref > 0) else np.nan
-                        ident = ((j - f + prm.window) << ID_SHIFT) | q
-                        members[i].append((ident, rho, colour[j, qy, qx], marg))
-                    elif marg:
-                        near_miss[i] = True
+        cand = np.flatnonzero((ok & (in_z | z_marg)).ravel())     # source pixels q worth testing
+        ax, ay = px.ravel()[cand], py.ravel()[cand]
+        zq, inzq, zmq = z.ravel()[cand], in_z.ravel()[cand], z_marg.ravel()[cand]
+        bx, by = np.floor(ax).astype(np.int64), np.floor(ay).astype(np.int64)
+        # every output pixel within `reach` of the carried point, one offset at a time
+        for oy_off in range(-reach, reach + 1):
+            for ox_off in range(-reach, reach + 1):
+                ox, oy = bx + ox_off, by + oy_off
+                inside = (ox >= 0) & (ox < w) & (oy >= 0) & (oy < h)
+                at = np.where(inside, oy * w + ox, 0)
+                sl = np.where(inside, slot[at], -1)
+                use = sl >= 0
+                if not use.any():
+                    continue
+                dist = np.abs(ox - ax) + np.abs(oy - ay)
+                marg = zmq | (np.abs(dist - half) <= L1_BAND)
+                member = use & (dist < half) & inzq
+                near_miss[sl[use & ~member & marg]] = True
+                if not member.any():
+                    continue
+                q = cand[member]
+                d_ref = dp[at[member]]
+                with np.errstate(invalid="ignore", divide="ignore"):
+                    rho = np.where(np.isfinite(d_ref) & (d_ref > 0), (zq[member] - d_ref) / d_ref, np.nan)
+                ident = ((j - f + prm.window) << ID_SHIFT) | q
+                parts.append((sl[member], ident, rho, colour[j].reshape(-1, 3)[q], marg[member]))
+    if parts:
+        slots = np.concatenate([p_[0] for p_ in parts])
+        idents = np.concatenate([p_[1] for p_ in parts]).astype(np.int64)
+        rhos = np.concatenate([p_[2] for p_ in parts])
+        cols = np.concatenate([p_[3] for p_ in parts])
+        margs = np.concatenate([p_[4] for p_ in parts])
+    else:
+        slots = idents = np.zeros(0, dtype=np.int64)
+        rhos, cols, margs = np.zeros(0), np.zeros((0, 3)), np.zeros(0, dtype=bool)
+    order = np.lexsort((idents, slots))      # by output pixel, then ascending id
+    counts = np.bincount(slots, minlength=pixels.size)
     offsets = np.zeros(pixels.size + 1, dtype=np.int64)
-    ids, rhos, cols, margs = [], [], [], []
-    for i, mem in enumerate(members):
-        mem.sort(key=lambda t: t[0])
-        offsets[i + 1] = offsets[i] + len(mem)
-        for (ident, rho, c, marg) in mem:
-            ids.append(ident)
-            rhos.append(rho)
-            cols.append(c)
-            margs.append(marg)
-    return FrustumSets(frame=f, pixels=pixels, offsets=offsets, ids=np.array(ids, dtype=np.uint32),
-                       rho=np.array(rhos, dtype=np.float64), colour=np.array(cols, dtype=np.float64).reshape(-1, 3),
-                       marginal=np.array(margs, dtype=bool), near_miss=near_miss)
+    offsets[1:] = np.cumsum(counts)
+    return FrustumSets(frame=f, pixels=pixels, offsets=offsets, ids=idents[order].astype(np.uint32),
+                       rho=rhos[order], colour=cols[order].reshape(-1, 3), marginal=margs[order],
+                       near_miss=near_miss)
 
 
 def _convex_hull(pts: np.ndarray) -> np.ndarray:
