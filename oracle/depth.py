@@ -40,10 +40,11 @@ def patch_ssd(a: np.ndarray, ay: int, ax: int, b: np.ndarray, by: int, bx: int) 
 
 def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
                    f: int, window: int, hypotheses: np.ndarray, with_bands: bool = False,
-                   rnd_band: float = RND_BAND):
+                   rnd_band: float = RND_BAND, pixels: np.ndarray | None = None):
     """D^f and the least average cost per pixel, [H, W] each (float64), and with
     with_bands the band flags [H, W] bool. colour [N, H, W, 3]; the frames J != f in
-    [f - window, f + window] are searched."""
+    [f - window, f + window] are searched. With `pixels` (flat indices y W + x) only
+    those pixels are estimated; the others stay NaN / inf / unflagged."""
     n, h, w = colour.shape[:3]
     k = _poses.intrinsics(fx, fy, cx, cy)
     kinv = np.linalg.inv(k)
@@ -52,8 +53,10 @@ def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: 
     depth = np.full((h, w), np.nan)
     best = np.full((h, w), np.inf)
     band = np.zeros((h, w), dtype=bool)
-    for y in range(1, h - 1):
-        for x in range(1, w - 1):
+    todo = np.arange(h * w) if pixels is None else np.asarray(pixels, dtype=np.int64)
+    for y, x in zip(todo // w, todo % w):
+        y, x = int(y), int(x)
+        if 1 <= x < w - 1 and 1 <= y < h - 1:
             ray = kinv @ np.array([x, y, 1.0])
             all_costs = []
             for d in hypotheses:

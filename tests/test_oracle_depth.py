@@ -57,3 +57,18 @@ def test_patch_cost_is_the_sum_of_squared_rgb_differences():
     d, cost = odepth.estimate_depth(frames, cams, FX, FX, 2.0, 2.0, 0, 1, np.array([1.5]))
     assert cost[2, 2] == pytest.approx(0.27, rel=1e-12)
     assert d[2, 2] == 1.5
+
+
+def test_a_pixel_list_gives_the_same_estimates():
+    rng = np.random.default_rng(5)
+    h, w = 8, 11
+    frames = rng.random((3, h, w, 3))
+    cams = np.stack([np.eye(4), _translated(0.03), _translated(-0.02)])
+    hyp = np.array([1.0, 1.5, 2.5, 4.0])
+    full = odepth.estimate_depth(frames, cams, FX, FX, 5.0, 3.5, 0, 2, hyp, with_bands=True)
+    pix = np.array([0, 13, 27, 40, 52, 87])
+    part = odepth.estimate_depth(frames, cams, FX, FX, 5.0, 3.5, 0, 2, hyp, with_bands=True, pixels=pix)
+    for a, b in zip(full, part):
+        np.testing.assert_array_equal(a.reshape(-1)[pix], b.reshape(-1)[pix])
+    others = np.setdiff1d(np.arange(h * w), pix)
+    assert np.isnan(part[0].reshape(-1)[others]).all()
