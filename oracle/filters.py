@@ -54,13 +54,6 @@ def filter_sets(sets: OracleSets, colour_f: np.ndarray, window: int, sigma_d: fl
     return weighted_mean(sets.offsets, sets.colour, sets.rho, dj, c_ref, sigma_d, sigma_c, sigma_t)
 
 
-def sample_weight_sum(sets: OracleSets, sigma_d: float) -> np.ndarray:
-    """W(p) of Eq. 3 for the depth term alone (used for the W/|S| statistic of Sec. 5)."""
-    n = sets.offsets.size - 1
-    seg = np.repeat(np.arange(n), np.diff(sets.offsets))
-    return np.bincount(seg, weights=_factor(sets.rho ** 2, sigma_d), minlength=n)
-
-
 # ---------------------------------------------------------------------------
 # The paper's other filters over the same sets (Sec. 6).
 

@@ -117,6 +117,64 @@ def test_first_adam_step_closed_form():
     assert abs(mlp.b3 - (before.b3 - 0.01 * 0.25 / (0.25 + 1e-8))) < 1e-15
 
 
+def test_adam_three_steps_hand_computed():
+    """Three steps on one scalar with gradients 1, -1, 2 (lr 0.1, beta1 0.9, beta2 0.999):
+    worked by hand, m = 0.1, -0.01, 0.191 and v = 0.001, 0.001999, 0.005997001;
+    bias-corrected m = 1, -0.01 / 0.19, 0.191 / 0.271 and v = 1, 1, 0.005997001 /
+    0.002997001, so the parameter moves by -0.1, +0.05263157894736842 x 0.1 and
+    -0.1 x 0.7047970479704797 / sqrt(2.001000667000111). From the second step on
+    every moment decay and both bias corrections change the result."""
+    mlp = learned.init_mlp(3)
+    mlp.b3 = 0.0
+    opt = learned.Adam(lr=0.1)
+    want_theta = [-0.1, -0.1 + 0.005263157894736842, -0.1 + 0.005263157894736842 - 0.04982421404270304]
+    want_m = [0.1, -0.01, 0.191]
+    want_v = [0.001, 0.001999, 0.005997001]
+    for t, g in enumerate([1.0, -1.0, 2.0]):
+        opt.step(mlp, {"b3": g})
+        assert abs(opt.m["b3"] - want_m[t]) < 1e-15
+        assert abs(opt.v["b3"] - want_v[t]) < 1e-15
+        # eps = 1e-8 moves each step by at most lr * 1e-8
+        assert abs(mlp.b3 - want_theta[t]) < 1e-8 * (t + 1), (t, mlp.b3)
+
+
+def test_adam_constant_gradient_moves_lr_every_step():
+    """With a constant gradient c the bias-corrected moments are exactly c and c^2 at
+    every step t, so each step moves the parameter by lr c / (|c| + eps); a bias
+    correction that used the wrong power of beta would change the step from t = 2 on."""
+    mlp = learned.init_mlp(4)
+    before = mlp.w3.copy()
+    c = np.linspace(-2.0, 2.0, 64)
+    c[c == 0] = 0.5
+    opt = learned.Adam(lr=0.01)
+    for t in range(1, 21):
+        opt.step(mlp, {"w3": c})
+        assert np.allclose(mlp.w3, before - t * 0.01 * c / (np.abs(c) + 1e-8), atol=1e-12), t
+
+
+def test_colour_median_feature_on_hand_built_sets():
+    """Feature x2 = |c_s - lower median of the set|_2 on three hand-built sets of a
+    single frame (ids with J = f): n = 4 (lower median = 2nd smallest per channel,
+    (0.2, 0.5, 0.4)), n = 3 (the median, (0.5, 0.5, 0.9)) and n = 1 (0). Distances
+    worked by hand: sqrt(0.26), sqrt(0.1), sqrt(0.18), sqrt(0.14); sqrt(0.32),
+    sqrt(0.26), sqrt(0.74); 0."""
+    w_img, h_img = 8, 4
+    colour = np.array([[0.1, 0.5, 0.9], [0.3, 0.2, 0.4], [0.2, 0.8, 0.1], [0.4, 0.6, 0.7],
+                       [0.9, 0.9, 0.9], [0.0, 0.5, 1.0], [0.5, 0.0, 0.2],
+                       [0.7, 0.1, 0.3]])
+    offsets = np.array([0, 4, 7, 8])
+    pixels = np.array([9, 10, 20])
+    pix_of = np.repeat(np.arange(3), np.diff(offsets))
+    # every record is the output pixel itself, source frame f, window 1
+    ids = ((1 << 22) | pixels[pix_of]).astype(np.uint32)
+    depth = np.full((3, h_img, w_img), 5.0)
+    cams = np.stack([np.eye(4)] * 3)
+    feat = learned.features(pix_of, ids, np.zeros(8), colour, offsets, pixels, 1, depth, cams,
+                            10.0, 10.0, 3.5, 1.5, window=1, radius=1)
+    want = np.sqrt([0.26, 0.1, 0.18, 0.14, 0.32, 0.26, 0.74, 0.0])
+    assert np.allclose(feat[:, 1], want, rtol=0, atol=1e-15)
+
+
 def test_lower_median_brute_force():
     rng = np.random.default_rng(7)
     for n in range(1, 12):
