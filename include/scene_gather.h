@@ -178,6 +178,21 @@ sg_status scene_gather(const sg_clip* clip, int32_t f0, int32_t f1,
                        const sg_gather_params* params, sg_sample_sets* sets,
                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* scene_gather without a caller workspace and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc). The workspace is a library-owned static device
+ * array of SG_NOALLOC_SCRATCH_BYTES bytes; each GPU the library runs on holds its
+ * own copy until the process ends (its address is looked up on the first call on
+ * that GPU: the GPU of `stream`). Results are identical to scene_gather's with the
+ * same arguments. Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (different streams, or different host threads) race and give wrong
+ * sets; serialise them. Nothing in the array needs clearing between calls.
+ * SG_E_UNSUPPORTED when the call's workspace (scene_gather_workspace_size) exceeds
+ * SG_NOALLOC_SCRATCH_BYTES (split [f0, f1) into calls); other errors as scene_gather. */
+#define SG_NOALLOC_SCRATCH_BYTES (4u << 20)
+sg_status scene_gather_noalloc(const sg_clip* clip, int32_t f0, int32_t f1,
+                               const sg_gather_params* params, sg_sample_sets* sets, void* stream);
+
 /* Filter (Sec. 5 Eq. 3 with the weight above): out_rgb device [P][3] float32 with
  * O(p) = sum w(s) c_s / sum w(s) over the set of p, or I^f(p) (the stored colour of
  * the output pixel) when the set is empty. `window` must be the w used to gather

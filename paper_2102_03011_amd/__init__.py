@@ -252,6 +252,16 @@ def scene_gather(clip: StagedClip, f0: int, f1: int, params: GatherParams, capac
     return sets
 
 
+def scene_gather_noalloc(clip: StagedClip, f0: int, f1: int, params: GatherParams, sets: SampleSets) -> SampleSets:
+    """scene_gather into caller-provided sets with the library's static device
+    scratch as workspace (no allocation by the library; the caller's `sets` hold
+    the arena). Never synchronises; check `sets.check()` afterwards."""
+    cc, pp, ss = clip.c_struct(), params.c_struct(), sets.c_struct()
+    _check(_lib.scene_gather_noalloc(ctypes.byref(cc), f0, f1, ctypes.byref(pp), ctypes.byref(ss),
+                                     _stream_handle()), "scene_gather_noalloc")
+    return sets
+
+
 @dataclass
 class FrustumParams:
     """Depth-agnostic frustum gather (include/scene_frustum.h): window +-w, frustum

@@ -21,6 +21,7 @@ SG_APRON_RIGHT = 7
 SG_MAX_INPAINT_STEPS = 16
 SG_MAX_FRUSTUM_L = 7.0
 SG_MAX_DEPTH_HYPOTHESES = 4096
+SG_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 c_void_p = ctypes.c_void_p
 
@@ -92,6 +93,9 @@ SIGNATURES = {
     "scene_gather": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                      c_void_p, ctypes.c_size_t, c_void_p]),
+    "scene_gather_noalloc": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                             c_void_p]),
     "scene_filter": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(SgSampleSets), ctypes.POINTER(SgFilterParams),
                                      c_void_p, c_void_p]),

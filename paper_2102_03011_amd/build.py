@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libscenegather.so")
 
-SOURCES = ["sg_kernels.hip", "sg_learned.hip", "sg_filters.hip", "sg_frustum.hip", "sg_depth.hip", "sg_api.cpp", "sg_batch.cpp"]
+SOURCES = ["sg_kernels.hip", "sg_learned.hip", "sg_filters.hip", "sg_frustum.hip", "sg_depth.hip", "sg_noalloc.hip",
+           "sg_api.cpp", "sg_batch.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -37,9 +37,8 @@ Layout layout(const sg_clip* c, int32_t f0, int32_t f1, const sg_gather_params* 
   return l;
 }
 
-sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
-                  sg_sample_sets* sets, void* ws, size_t ws_bytes, bool need_arena,
-                  sg::GatherJob* jb) {
+sg_status validate(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                   const sg_sample_sets* sets, bool need_arena) {
   sg_status s = check_clip(clip, true);
   if (s != SG_OK) return s;
   if ((s = check_range(clip, f0, f1)) != SG_OK) return s;
@@ -47,6 +46,14 @@ sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_p
   if (sets == nullptr || sets->offsets == nullptr || sets->status == nullptr) return SG_E_INVALID;
   if (need_arena && (sets->capacity < 0 || (sets->capacity > 0 && (sets->ids == nullptr || sets->crho == nullptr))))
     return SG_E_INVALID;
+  return SG_OK;
+}
+
+sg_status prepare(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                  sg_sample_sets* sets, void* ws, size_t ws_bytes, bool need_arena,
+                  sg::GatherJob* jb) {
+  sg_status s = validate(clip, f0, f1, params, sets, need_arena);
+  if (s != SG_OK) return s;
   if (ws == nullptr) return SG_E_INVALID;
   const Layout l = layout(clip, f0, f1, params);
   if (ws_bytes < l.total) return SG_E_INVALID;
@@ -86,6 +93,18 @@ sg_status run_count(const sg::GatherJob& jb, hipStream_t st) {
 }
 
 }  // namespace
+
+namespace sg {
+
+sg_status gather_host_checks(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                             const sg_sample_sets* sets, size_t* ws_bytes) {
+  const sg_status s = validate(clip, f0, f1, params, sets, true);
+  if (s != SG_OK) return s;
+  *ws_bytes = layout(clip, f0, f1, params).total;
+  return SG_OK;
+}
+
+}  // namespace sg
 
 extern "C" {
 

@@ -142,6 +142,10 @@ hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_
 hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,
                                   hipStream_t st);
 
+// Every host-side check of scene_gather (no HIP call) and its workspace bytes.
+sg_status gather_host_checks(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* params,
+                             const sg_sample_sets* sets, size_t* ws_bytes);
+
 hipError_t launch_stage(const uint8_t* rgb, const float* depth, int n_frames, int width, int height,
                         uint16_t* rgbd, uint16_t* depth16, hipStream_t st);
 hipError_t launch_pose_prep(const GatherJob& jb, hipStream_t st);

@@ -514,3 +514,44 @@ def test_batch_entry_points_reject_bad_arguments(native):
     assert lib.sg_batch_get_config(None, n_out) == 1
     assert lib.sg_batch_pixel_base(None, 0) == -1
     lib.sg_batch_destroy(None)
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_clip", 1), ("f_past_end", 1), ("big_window", 4), ("null_sets", 1), ("null_arena", 1),
+    ("null_rgbd", 1), ("scratch_too_small", 4),
+])
+def test_noalloc_gather_rejects_on_the_host(native, case, expect):
+    """scene_gather_noalloc makes every host check of scene_gather before any HIP
+    call, and refuses a call whose workspace exceeds its static scratch."""
+    mod, lib = native
+    c = _clip(mod)
+    p = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    s = _sets(mod, 100)
+    f0, f1 = 2, 4
+    cp, sp = ctypes.byref(c), ctypes.byref(s)
+    if case == "null_clip":
+        cp = None
+    elif case == "f_past_end":
+        f1 = 11
+    elif case == "big_window":
+        p.window = 512
+    elif case == "null_sets":
+        sp = None
+    elif case == "null_arena":
+        s.ids = None
+    elif case == "null_rgbd":
+        c.rgbd = None
+    elif case == "scratch_too_small":
+        # 1000 output frames x 1023 window slots x 64 B of relative maps > 4 MiB
+        c.num_frames, f0, f1, p.window = 1000, 0, 1000, 511
+        need = ctypes.c_size_t(0)
+        assert lib.scene_gather_workspace_size(cp, f0, f1, ctypes.byref(p), ctypes.byref(need)) == 0
+        assert need.value > mod.SG_NOALLOC_SCRATCH_BYTES
+    assert lib.scene_gather_noalloc(cp, f0, f1, ctypes.byref(p), sp, None) == expect, case
+
+
+def test_noalloc_scratch_size_matches_header():
+    from paper_2102_03011_amd import _native
+    text = open(HEADER).read()
+    m = re.search(r"#define SG_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and _native.SG_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
