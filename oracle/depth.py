@@ -27,7 +27,10 @@ import numpy as np
 
 from . import poses as _poses
 
-RND_BAND = 1e-3
+# float32 projections of the hypotheses are off by up to 4.9e-4 px at 1920x1080
+# (full-scale workload's poses, +-2 frames, 1-30 m; tests/test_float32_bands.py):
+# the rounding band is six times that
+RND_BAND = 3e-3
 COST_BAND = 1e-4
 
 

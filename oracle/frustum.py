@@ -35,9 +35,11 @@ from . import poses as _poses
 from .gather import ID_SHIFT
 
 # Band flags for comparisons with a float32 evaluation of the same test: p' carried
-# in float32 through float32-rounded pose maps is off by up to ~1e-4 px at 1080p,
-# z' by a few float32 ulps.
-L1_BAND = 2e-3      # |L1 - l/2| below this (pixels): membership may differ in float32
+# in float32 through float32-rounded pose maps is off by up to 7.0e-4 px (L1) at
+# 1920x1080 with the full-scale workload's poses over a +-10 window, z' by up to
+# 2.2e-7 relative (measured in tests/test_float32_bands.py); each band is at least
+# five times that.
+L1_BAND = 4e-3      # |L1 - l/2| below this (pixels): membership may differ in float32
 Z_BAND = 1e-5       # relative distance of z' to near / far below this: likewise
 
 

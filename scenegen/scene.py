@@ -231,14 +231,27 @@ def _raycast(o, rot, dirs_cam, box_lo, box_hi):
     return t_best, obj, face
 
 
-def generate(spec: SceneSpec, device="cpu", chunk_rays: int = 1 << 18) -> Clip:
-    """Render a clip: clean radiance, z-depth, face ids; then add the noise models."""
-    device = torch.device(device)
-    gen = torch.Generator().manual_seed(int(spec.seed) * 7919 + 17)
-    W, H, N = spec.width, spec.height, spec.n_frames
-    fx = fy = spec.focal
-    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+@dataclass
+class SceneSetup:
+    """Everything a clip's seed fixes before rendering: camera path (true and
+    observed poses), boxes, texture tables and the seed of the observation noise."""
+    poses: torch.Tensor       # [N][4][4] true camera-to-world
+    noisy: torch.Tensor       # [N][4][4] observed (perturbed) camera-to-world
+    box_lo: torch.Tensor
+    box_hi: torch.Tensor
+    box_vel: torch.Tensor
+    perm: torch.Tensor
+    base: torch.Tensor
+    shift: torch.Tensor
+    face_col: torch.Tensor
+    moving: torch.Tensor
+    noise_seed: int
 
+
+def scene_setup(spec: SceneSpec, device="cpu") -> SceneSetup:
+    """The seeded draws of `generate` up to rendering, in the same order (cheap: no rays)."""
+    gen = torch.Generator().manual_seed(int(spec.seed) * 7919 + 17)
+    N = spec.n_frames
     poses = _camera_path(spec, gen)
     path_xz = poses[:, [0, 2], 3]
     box_lo, box_hi, box_vel = _place_boxes(spec, path_xz, gen)
@@ -260,6 +273,34 @@ def generate(spec: SceneSpec, device="cpu", chunk_rays: int = 1 << 18) -> Clip:
         dT[:3, 3] = t
         noisy[i] = poses[i] @ dT
     noise_seed = int(torch.randint(0, 2**62, (1,), generator=gen))
+    return SceneSetup(poses, noisy, box_lo, box_hi, box_vel, perm, base, shift, face_col, moving, noise_seed)
+
+
+def true_depth(spec: SceneSpec, setup: SceneSetup, frame: int, pixels: torch.Tensor) -> torch.Tensor:
+    """Noise-free z-depth of the given flat pixel indices (y W + x) of one frame (float64, CPU)."""
+    W = spec.width
+    fx = fy = spec.focal
+    cx, cy = (W - 1) / 2.0, (spec.height - 1) / 2.0
+    xs = (pixels % W).to(torch.float64)
+    ys = (pixels // W).to(torch.float64)
+    dirs = torch.stack([(xs - cx) / fx, (ys - cy) / fy, torch.ones_like(xs)], dim=-1)
+    off = setup.box_vel * frame
+    t, _, _ = _raycast(setup.poses[frame, :3, 3], setup.poses[frame, :3, :3], dirs, setup.box_lo + off,
+                       setup.box_hi + off)
+    return t
+
+
+def generate(spec: SceneSpec, device="cpu", chunk_rays: int = 1 << 18) -> Clip:
+    """Render a clip: clean radiance, z-depth, face ids; then add the noise models."""
+    device = torch.device(device)
+    W, H, N = spec.width, spec.height, spec.n_frames
+    fx = fy = spec.focal
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+
+    su = scene_setup(spec, device)
+    poses, noisy, box_lo, box_hi, box_vel = su.poses, su.noisy, su.box_lo, su.box_hi, su.box_vel
+    perm, base, shift, face_col, moving = su.perm, su.base, su.shift, su.face_col, su.moving
+    noise_seed = su.noise_seed
 
     ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64), torch.arange(W, dtype=torch.float64), indexing="ij")
     dirs = torch.stack([(xs - cx) / fx, (ys - cy) / fy, torch.ones_like(xs)], dim=-1).reshape(-1, 3).to(device)
