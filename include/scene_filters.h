@@ -1,6 +1,6 @@
 /* scene_filters.h -- the paper's other filters over stored sample sets (HIP, gfx950).
  *
- * Klose et al., Sampling Based Scene-Space Video Processing, Sec. 6: deblurring
+ * Klose et al., Sampling Based Scene-Space Video Processing, Sec. 5: deblurring
  * (Eq. 5), computational scene-space shutters (Eq. 10) and inpainting (Eq. 8-9)
  * reduce the same sample sets S(p) as the denoising filter of scene_gather.h with
  * other weights. The sets, clip and status conventions are those of
@@ -63,7 +63,7 @@ sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t win
                         const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, int32_t steps,
                         float* out_rgb, void* stream);
 
-/* Inpainting masks from a scene-space region (Sec. 6, inpainting: the samples that
+/* Inpainting masks from a scene-space region (Sec. 5, inpainting: the samples that
  * fall into the region, projected back into the images, form M). M^J(q) = 1 when
  * the scene point of pixel q = (x, y) of frame J lies in the world-space box
  * [lo, hi] (bounds included), 0 otherwise and for pixels without a valid stored

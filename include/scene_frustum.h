@@ -48,7 +48,8 @@ sg_status scene_frustum_workspace_size(const sg_clip* clip, int32_t f, const sg_
 
 /* Pass 1: carry every pixel of every window frame into the output view, bucket
  * them by nearest output pixel, count each output pixel's members and scan the
- * counts into sets->offsets (total at offsets[P]). Needs clip->depth. */
+ * counts into sets->offsets (total at offsets[P]). Clears *sets->status (as
+ * scene_gather_count does). Needs clip->depth. */
 sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
                               sg_sample_sets* sets, void* workspace, size_t workspace_bytes, void* stream);
 

@@ -17,10 +17,15 @@
  *   - colour is on the 0-1 scale (the paper's 0-255 divided by 255);
  *   - binary16 values are passed as their 16-bit patterns (uint16_t).
  *
- * Memory ownership: every device buffer is allocated by the caller and only
- * borrowed for the duration of the work enqueued on `stream`. The library
- * allocates no device memory. `stream` is a hipStream_t (NULL = the default
- * stream); all GPU work is enqueued asynchronously on it.
+ * Memory ownership: every data buffer (planes, poses, sample sets, outputs,
+ * workspaces) is allocated by the caller and only borrowed for the duration of the
+ * work enqueued on `stream`. The single-clip entry points allocate no device
+ * memory. Two exceptions own device memory of their own: a batch
+ * (sg_batch_create allocates its plan, relative maps, scan partials, queue
+ * counters and a pinned host copy of the step's frames; sg_batch_destroy frees
+ * them), and scene_gather_noalloc's static scratch array (SG_NOALLOC_SCRATCH_BYTES
+ * per GPU, held until the process ends). `stream` is a hipStream_t (NULL = the
+ * default stream); all GPU work is enqueued asynchronously on it.
  *
  * Errors: argument checks run on the host before any GPU work and return
  * synchronously (SG_E_INVALID, SG_E_UNSUPPORTED). A failing HIP call returns
@@ -120,7 +125,7 @@ typedef struct sg_sample_sets {
   uint32_t* status;
 } sg_sample_sets;
 
-/* Filter weights (Sec. 5.1 Eq. 4, diagonal Gaussian around the reference sample):
+/* Filter weights (Sec. 5 Eq. 4, diagonal Gaussian around the reference sample):
  * w(s) = exp(-rho^2 / 2 sigma_d^2) * exp(-|c_s - c_ref|^2 / 2 sigma_c^2) * exp(-(J - f)^2 / 2 sigma_t^2),
  * c_ref = I^f(p). A sigma of +INFINITY disables its term. */
 typedef struct sg_filter_params {
@@ -214,7 +219,7 @@ sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1,
                               float* out_rgb, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Learned per-sample weights (replacing the hand-set weight of Sec. 5.1 Eq. 4 in
+ * Learned per-sample weights (replacing the hand-set weight of Sec. 5 Eq. 4 in
  * the weighted mean of Sec. 5 Eq. 3): O(p) = sum_s softmax(m)_s c_s over the set of
  * p, m_s = MLP(standardised features of s), MLP 8 -> 64 -> 64 -> 1 with GELU.
  * Features of a sample (source frame J, source pixel q) of output pixel p, frame f:
@@ -223,9 +228,11 @@ sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1,
  *   angle at the scene point between the rays from the camera centres of f and J;
  *   6 |grad D^J|(q) / D^J(q) (central differences, one-sided where a neighbour has
  *   no valid depth); 7 log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)); 8 (J - f) / w.
- * GELU uses the tanh form 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3)))
- * (Hendrycks and Gimpel); activations are stored as bfloat16, products accumulate
- * in float32 on the matrix cores.
+ * GELU is the exact form GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2 (Phi the
+ * standard normal CDF; not the tanh approximation); the kernels evaluate erf with
+ * Abramowitz-Stegun 7.1.28 (|error| <= 3e-7). Matrix operands (standardised
+ * features, hidden activations) are bfloat16 hi/lo pairs, products accumulate in
+ * float32 on the matrix cores.
  *
  * Parameter layout (device):
  *   w : bfloat16 [SG_MLP_NW] = W1 [8][64] (feature, hidden), W2 [64][64] (in, out), W3 [64]

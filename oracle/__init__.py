@@ -16,15 +16,15 @@ Video Processing):
   poses      -- camera matrices C^f, their inverses and relative products (Sec. 3, Sec. 4 Eq. 1-2)
   gather     -- sample sets S^f(p) with the depth-guided frustum test (Sec. 4)
   filters    -- weighted mean O(p) = sum w(s) s_rgb / W (Sec. 5 Eq. 3) with the
-                Gaussian denoising weight around the reference sample (Sec. 5.1 Eq. 4);
-                the per-frame factors of deblurring (Sec. 6 Eq. 5) and computational
+                Gaussian denoising weight around the reference sample (Sec. 5 Eq. 4);
+                the per-frame factors of deblurring (Sec. 5 Eq. 5) and computational
                 shutters (Eq. 10); inpainting by masked mean-shift (Eq. 8-9)
   frustum    -- the paper's depth-agnostic frustum gather (Sec. 4, Eq. 1-2) by its
                 definition, and the hull-rasterisation algorithm that pins it
   depth      -- data-term-only multi-view depth over a temporal window (Sec. 3,
                 preprocessing: 3x3 RGB SSD along the epipolar lines, lowest mean cost)
   bruteforce -- all-pairs twin of `gather` for tiny inputs (pure Python loops)
-  metrics    -- PSNR (Sec. 5.1, denoising PSNR figure)
+  metrics    -- PSNR (Sec. 5, the denoising PSNR figure)
 
 Parity unpinned: nothing in this package is unpinned; see the test suite for
 the pin of each function.

@@ -1,14 +1,14 @@
 """Sample-set filtering (test infrastructure only).
 
 Sec. 5 Eq. 3: O(p) = (1 / W) sum_{s in S(p)} w(s) s_rgb with W = sum w(s).
-Sec. 5.1 Eq. 4: the denoising weight is a Gaussian around the reference
+Sec. 5 Eq. 4: the denoising weight is a Gaussian around the reference
 sample s_ref (the sample that the output pixel itself contributes: frame f,
 pixel p) with a diagonal covariance. Here the terms are
   w(s) = exp(-rho_s^2 / (2 sd^2)) * exp(-|c_s - c_ref|^2 / (2 sc^2)) * exp(-(J_s - f)^2 / (2 st^2))
 where rho_s is the sample's relative depth residual (the depth-guided gather's
 stand-in for the scene-space distance to s_ref), c_ref = I^f(p), and a sigma
 of +inf disables its term (weight factor 1). sd alone is the depth-Gaussian
-weighted mean; sd = sc = st = inf is the plain mean of Sec. 5.1 (w = 1).
+weighted mean; sd = sc = st = inf is the plain mean of Sec. 5 (w = 1).
 An empty set returns the input colour I^f(p) (reading: the paper is silent).
 """
 from __future__ import annotations
@@ -55,14 +55,14 @@ def filter_sets(sets: OracleSets, colour_f: np.ndarray, window: int, sigma_d: fl
 
 
 # ---------------------------------------------------------------------------
-# The paper's other filters over the same sets (Sec. 6).
+# The paper's other filters over the same sets (Sec. 5).
 
 def frame_weighted_mean(sets: OracleSets, colour_f: np.ndarray, window: int, frame_w: np.ndarray,
                         sigma_d: float, sigma_c: float = math.inf, sigma_t: float = math.inf) -> np.ndarray:
     """Eq. 3 with the weight of Eq. 4 multiplied by a per-source-frame factor
     frame_w[J] (J = the frame the sample came from, absolute index):
-      deblurring (Sec. 6, Eq. 5): frame_w[J] = B(J), the frame's summed gradient magnitude;
-      computational shutter (Sec. 6, Eq. 10): frame_w[J] = xi(J) with every sigma +inf.
+      deblurring (Sec. 5, Eq. 5): frame_w[J] = B(J), the frame's summed gradient magnitude;
+      computational shutter (Sec. 5, Eq. 10): frame_w[J] = xi(J) with every sigma +inf.
     Reading: a set whose weights sum to zero (empty, or every sample on a frame of
     factor 0) returns the input colour I^f(p). Returns [n, 3] float64."""
     n = sets.offsets.size - 1
@@ -100,7 +100,7 @@ def frame_sharpness(colour: np.ndarray) -> np.ndarray:
 
 def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask: np.ndarray,
                        sigma_rgb: float, steps: int = 2) -> np.ndarray:
-    """Inpainting (Sec. 6, Eq. 8-9) for the output pixels of frame sets.frame.
+    """Inpainting (Sec. 5, Eq. 8-9) for the output pixels of frame sets.frame.
 
     mask [N, H, W] bool: M^J(q), True = the pixel shows content to remove.
     For an output pixel with M^f(p) = 1: s_ref starts as the mean colour of all
@@ -158,7 +158,7 @@ def scene_points(depth: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: flo
 
 def scene_box_mask(depth: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
                    lo, hi) -> np.ndarray:
-    """Inpainting masks from a scene-space region (Sec. 6, inpainting: the samples
+    """Inpainting masks from a scene-space region (Sec. 5, inpainting: the samples
     inside the region, projected back into the images, form M). Reading: the region
     is an axis-aligned box [lo, hi] in world coordinates, bounds included; a pixel
     without a valid depth (not finite, or <= 0) is not a scene point and stays

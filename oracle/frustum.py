@@ -22,7 +22,7 @@ point behind the output camera or past `far` is not in V), bounds included.
 
 Each sample also carries rho = (z' - d_p) / d_p, its relative depth offset along
 p's ray from p's own scene point (reading: the scene-space distance to the
-reference sample that Sec. 5.1 weights by, measured the way the depth-guided
+reference sample that Sec. 5 weights by, measured the way the depth-guided
 path measures it); rho is NaN when p has no valid depth.
 """
 from __future__ import annotations

@@ -1,7 +1,7 @@
 """Learned per-sample weights for the sample-set filter (test infrastructure only).
 
 The paper's filter is a weighted mean of a sample set (Sec. 5, Eq. 3) with a
-hand-set weight (Sec. 5.1, Eq. 4). Here the weight comes from a small MLP on
+hand-set weight (Sec. 5, Eq. 4). Here the weight comes from a small MLP on
 eight per-sample features, normalised over the set with a softmax:
 
   O(p) = sum_s a_s c_s,  a = softmax_s(m_s),  m_s = MLP(standardise(x_s)),

@@ -1,6 +1,6 @@
 """Image quality metric (test infrastructure only).
 
-PSNR as plotted for denoising in Sec. 5.1 (denoising PSNR figure): on the
+PSNR as plotted for denoising in Sec. 5 (the denoising PSNR figure): on the
 0-1 scale, PSNR = 10 log10(1 / MSE) over all pixels and channels, which equals
 20 log10(255 / sigma) for zero-mean error of standard deviation sigma on the
 0-255 scale.

@@ -1,4 +1,4 @@
-// The paper's other filters over stored sample sets (Sec. 6): the per-frame
+// The paper's other filters over stored sample sets (Sec. 5): the per-frame
 // factor of deblurring (Eq. 5) and computational shutters (Eq. 10), the frame
 // sharpness B(J) that deblurring weights by, inpainting by masked mean-shift
 // (Eq. 8-9) and its masks from a scene-space box. Same record layout and lane organisation as the denoising filter:

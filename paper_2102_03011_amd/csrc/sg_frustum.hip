@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kThreads) void k_zero(T* __restrict__ p, int64_t n)
 // p' = (Y_1, Y_2) / Y_3. J = f gives exactly M = I, k = 0.
 __global__ __launch_bounds__(64) void k_frustum_pose(const double* __restrict__ c2w, int f, int jlo, int n_j,
                                                      double fx, double fy, double cx, double cy,
-                                                     float* __restrict__ maps) {
+                                                     float* __restrict__ maps, uint32_t* __restrict__ status) {
+  if (threadIdx.x == 0) *status = 0u;  // the count pass starts a new set of flags
   for (int jn = threadIdx.x; jn < n_j; jn += 64) {
     const int j = jlo + jn;
     float* m = maps + jn * kMapFloats;
@@ -345,7 +346,7 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
                      n_bk + 1);
   hipLaunchKernelGGL(sg::k_zero<int32_t>, dim3(sg::zero_blocks(n_bk)), dim3(sg::kThreads), 0, st, c.bfill, n_bk);
   hipLaunchKernelGGL(sg::k_frustum_pose, dim3(1), dim3(64), 0, st, clip->cam_to_world, f, l.jlo, l.n_j, clip->fx,
-                     clip->fy, clip->cx, clip->cy, c.maps);
+                     clip->fy, clip->cx, clip->cy, c.maps, sets->status);
   hipLaunchKernelGGL(sg::k_frustum_carry, per_pixel_frame, dim3(sg::kThreads), 0, st, clip->depth, c.maps,
                      clip->width, clip->height, l.jlo, l.rb, params->near_z, params->far_z, l.n_pix, l.n_buckets,
                      c.carry, reinterpret_cast<unsigned long long*>(c.boff));

@@ -2,7 +2,7 @@
 //
 // The weighted mean of Sec. 5 Eq. 3 takes its weights from a small MLP on eight
 // per-sample features, normalised over each set with a softmax (the learned
-// replacement of the hand-set Gaussian of Sec. 5.1 Eq. 4):
+// replacement of the hand-set Gaussian of Sec. 5 Eq. 4):
 //   O(p) = sum_s softmax(m)_s c_s,  m_s = MLP(standardised features of s).
 //
 // Inference (k_filter_learned): a wave owns 16 consecutive output pixels and

@@ -555,3 +555,13 @@ def test_noalloc_scratch_size_matches_header():
     text = open(HEADER).read()
     m = re.search(r"#define SG_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
     assert m and _native.SG_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+
+
+def test_header_states_the_erf_gelu_the_oracle_and_kernels_use():
+    """The MLP contract in the header is the exact erf form GELU(z) = z Phi(z), the
+    function the oracle evaluates (GELU(1) = Phi(1) = 0.8413447460685429...)."""
+    from oracle import learned
+    text = open(HEADER).read()
+    assert "GELU(z) = z Phi(z)" in text and "0.044715" not in text
+    assert abs(float(learned.gelu(1.0)) - 0.8413447460685429) < 1e-15
+    assert abs(float(learned.gelu(-1.0)) + (1.0 - 0.8413447460685429)) < 1e-15

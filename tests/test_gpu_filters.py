@@ -1,4 +1,4 @@
-"""GPU parity of the paper's other filters over stored sets (Sec. 6): the frame
+"""GPU parity of the paper's other filters over stored sets (Sec. 5): the frame
 sharpness B(J) and per-frame factors of deblurring (Eq. 5) and computational
 shutters (Eq. 10), and masked mean-shift inpainting (Eq. 8-9) with its masks from
 a scene-space box, through the C ABI

@@ -139,3 +139,13 @@ def test_frustum_capacity_overflow_flag_and_no_overrun():
     off = big.offsets.cpu().numpy()
     last = int(off[1:][off[1:] <= cap].max())
     assert torch.equal(big.ids[:last], exact.ids[:last])
+    # the flagged sets object again, now with the whole arena: the count pass
+    # clears the status word, so no stale flag of the earlier call survives
+    full = big.c_struct()
+    assert lib.scene_frustum_count(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(full), ws.data_ptr(),
+                                   ws.numel(), None) == 0
+    assert lib.scene_frustum_scatter(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(full), ws.data_ptr(),
+                                     ws.numel(), None) == 0
+    torch.cuda.synchronize()
+    assert big.flags() == 0
+    assert torch.equal(big.ids[:total], exact.ids[:total])

@@ -12,7 +12,9 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import depth as odepth
 from oracle import filters as ofilters
+from oracle import frustum as ofrustum
 from oracle import gather as ogather
 from oracle import staging as ostaging
 from scenegen import configs, generate
@@ -127,3 +129,74 @@ def test_hd_720p_w30_sampled_frames(report, hd_clip, f):
     rows = np.arange(f % 8, clip.height, 8)
     pixels = (rows[:, None] * clip.width + np.arange(clip.width)[None, :]).ravel()
     _check(wl, clip, staged, f, pixels, report)
+
+
+def test_full_scale_frustum_w10_sampled(full_clip):
+    """Depth-agnostic frustum gather (Sec. 4, Eq. 1-2) at 1920x1080 with a +-10
+    window, output frame 72 (the benchmark's frustum leg): 2000 seeded pixels
+    against the oracle's definition, computed for those pixels only. Outside the
+    oracle's bands: member ids and colours exact, rho within binary16 rounding."""
+    import paper_2102_03011_amd as sg
+    wl, clip, staged = full_clip
+    f, win = 72, 10
+    h, w = clip.height, clip.width
+    sets = sg.scene_gather_frustum(staged, f, sg.FrustumParams(window=win))
+    torch.cuda.synchronize()
+    sets.check()
+    g_off, g_ids, g_crho = parity.gpu_sets_to_host(sets, 0, h * w)
+    pixels = np.sort(np.random.default_rng(72).choice(h * w, 2000, replace=False))
+    lo, col, dep = _window_planes(clip, f, win)
+    cams = clip.cam_to_world[lo:lo + col.shape[0]].numpy()
+    orc = ofrustum.gather_frustum(col, dep, cams, clip.fx, clip.fy, clip.cx, clip.cy, f - lo,
+                                  ofrustum.FrustumParams(window=win), pixels=pixels)
+    seg = np.repeat(np.arange(pixels.size), np.diff(orc.offsets))
+    unsure = orc.near_miss.copy()
+    unsure[seg[orc.marginal]] = True
+    assert unsure.mean() < 0.2
+    assert orc.offsets[-1] > 20 * pixels.size
+    dp = dep[f - lo].reshape(-1)
+    checked = 0
+    for k in np.flatnonzero(~unsure):
+        i = pixels[k]
+        a, b = g_off[i], g_off[i + 1]
+        c, d = orc.offsets[k], orc.offsets[k + 1]
+        assert np.array_equal(g_ids[a:b], orc.ids[c:d]), i
+        assert np.array_equal(parity.f16_to_f64(g_crho[a:b, :3].copy()), orc.colour[c:d]), i
+        got_rho = parity.f16_to_f64(g_crho[a:b, 3].copy())
+        if np.isfinite(dp[i]) and dp[i] > 0:
+            assert np.all(np.abs(got_rho - orc.rho[c:d]) <= 2.0 ** -11 * np.abs(orc.rho[c:d]) + 1e-5), i
+        else:
+            assert np.isnan(got_rho).all(), i
+        checked += 1
+    print({"frustum_1080p_w10_pixels": int(pixels.size), "checked": checked, "unsure": int(unsure.sum()),
+           "records_checked": int(sum(orc.offsets[k + 1] - orc.offsets[k] for k in np.flatnonzero(~unsure)))})
+
+
+def test_full_scale_depth_estimate_sampled(full_clip):
+    """Data-term depth (Sec. 3) of 1080p frame 72 over +-2 frames and 32 hypotheses
+    uniform in inverse depth over 1-30 m (the benchmark's depth leg): 2000 seeded
+    pixels against the oracle; outside its bands the depths are equal and the
+    least costs within 1e-4 relative."""
+    import paper_2102_03011_amd as sg
+    wl, clip, staged = full_clip
+    f = 72
+    hyp = (1.0 / np.linspace(1.0, 1.0 / 30.0, 32)).astype(np.float32)
+    d, cost = sg.scene_estimate_depth(staged, f, 2, torch.from_numpy(hyp).cuda())
+    d = d.cpu().numpy().astype(np.float64).reshape(-1)
+    cost = cost.cpu().numpy().astype(np.float64).reshape(-1)
+    h, w = clip.height, clip.width
+    pixels = np.sort(np.random.default_rng(7).choice(h * w, 2000, replace=False))
+    lo, col, _ = _window_planes(clip, f, 2)
+    cams = clip.cam_to_world[lo:lo + col.shape[0]].numpy()
+    want, want_cost, band = odepth.estimate_depth(col, cams, clip.fx, clip.fy, clip.cx, clip.cy, f - lo, 2,
+                                                  hyp.astype(np.float64), with_bands=True, pixels=pixels)
+    want, want_cost, band = want.reshape(-1)[pixels], want_cost.reshape(-1)[pixels], band.reshape(-1)[pixels]
+    got, got_cost = d[pixels], cost[pixels]
+    ok = ~band
+    assert ok.mean() > 0.7
+    both_nan = np.isnan(got) & np.isnan(want)
+    assert np.all((got[ok] == want[ok]) | both_nan[ok])
+    fin = ok & np.isfinite(want_cost)
+    assert fin.sum() > 0.5 * pixels.size
+    np.testing.assert_allclose(got_cost[fin], want_cost[fin], rtol=1e-4, atol=1e-7)
+    print({"depth_1080p_pixels": int(pixels.size), "band": int(band.sum()), "finite": int(fin.sum())})

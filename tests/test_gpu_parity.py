@@ -108,8 +108,9 @@ def test_stage_bit_exact(small):
     assert np.array_equal(got[..., 3], want_d)
 
 
-@pytest.mark.parametrize("f", [0, 11, 23])
+@pytest.mark.parametrize("f", list(range(24)))
 def test_small_workload_frames(small, f):
+    """Every output frame of the 320x180, 24-frame workload (window = all frames)."""
     wl, clip, staged, col, dep, rgbd = small
     sg = _sg()
     params = sg.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)

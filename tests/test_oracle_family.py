@@ -1,4 +1,4 @@
-"""Pins of the oracle's deblurring, shutter and inpainting filters (Sec. 6,
+"""Pins of the oracle's deblurring, shutter and inpainting filters (Sec. 5,
 Eq. 5, Eq. 8-10) against closed forms and values worked out by hand."""
 import math
 
