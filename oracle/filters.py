@@ -85,6 +85,62 @@ def frame_weighted_mean(sets: OracleSets, colour_f: np.ndarray, window: int, fra
     return out
 
 
+def scene_space_weighted_mean(sets: OracleSets, colour_f: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarray,
+                              fx: float, fy: float, cx: float, cy: float, window: int, sigma_d: float,
+                              sigma_c: float, sigma_xyz: float, sigma_t: float,
+                              frame_w: np.ndarray | None = None) -> np.ndarray:
+    """Eq. 3 with the full weight of Eq. 4 (Sec. 5, denoising): a Gaussian around the
+    reference sample over colour, scene-space position and frame time,
+      w(s) = exp(-|c_s - c_ref|^2 / 2 sc^2) exp(-|X_s - X_ref|^2 / 2 sxyz^2) exp(-(J_s - f)^2 / 2 st^2)
+    times the depth-residual term exp(-rho_s^2 / 2 sd^2) of the depth-guided gather
+    and, when given, a per-source-frame factor frame_w[J] (deblurring, Eq. 5, reuses
+    this weight times B(J)). X_s is the sample's scene point, X = C^J [D^J(q) K^-1
+    (q_x, q_y, 1), 1] from its source pixel's stored depth, and X_ref that of the
+    output pixel p itself (the reference sample s_ref of frame f). A sigma of +inf
+    disables its term. sxyz is in world units (the paper states it in units of a
+    scene scaled so that 90 % of its points lie in a 10^3 cube; the caller converts).
+    Readings: an output pixel without a valid depth has no reference point, so with
+    a finite sxyz it returns I^f(p), as does a set whose weights sum to zero.
+    depth [N, H, W] float64 (the stored depths), cam_to_world [N, 4, 4]. Returns [n, 3]."""
+    n_frames, h, w_img = depth.shape
+    n = sets.offsets.size - 1
+    counts = np.diff(sets.offsets)
+    seg = np.repeat(np.arange(n), counts)
+    c_ref = colour_f.reshape(-1, 3)[sets.pixels]
+    dj = (sets.ids.astype(np.int64) >> ID_SHIFT) - window
+    src = sets.frame + dj
+    q = sets.ids.astype(np.int64) & ((1 << ID_SHIFT) - 1)
+    dc2 = np.sum((sets.colour - c_ref[seg]) ** 2, axis=1)
+    w = _factor(sets.rho * sets.rho, sigma_d) * _factor(dc2, sigma_c) * _factor(dj.astype(np.float64) ** 2, sigma_t)
+    if frame_w is not None:
+        w = w * np.asarray(frame_w, dtype=np.float64)[src]
+    no_ref = np.zeros(n, dtype=bool)
+    if not math.isinf(sigma_xyz):
+        def world(frames, pix):
+            x = (pix % w_img).astype(np.float64)
+            y = (pix // w_img).astype(np.float64)
+            d = depth[frames, pix // w_img, pix % w_img].astype(np.float64)
+            xc = np.stack([d * (x - cx) / fx, d * (y - cy) / fy, d])
+            rot = cam_to_world[frames, :3, :3]
+            return np.einsum("nij,jn->ni", rot, xc) + cam_to_world[frames, :3, 3], d
+        x_ref, d_ref = world(np.full(n, sets.frame), sets.pixels.astype(np.int64))
+        no_ref = ~(np.isfinite(d_ref) & (d_ref > 0.0))
+        x_s, _ = world(src, q)
+        dxyz2 = np.sum((x_s - x_ref[seg]) ** 2, axis=1)
+        with np.errstate(invalid="ignore"):
+            w = w * _factor(dxyz2, sigma_xyz)
+        w[no_ref[seg]] = 0.0
+    wsum = np.bincount(seg, weights=w, minlength=n)
+    out = np.empty((n, 3))
+    for ch in range(3):
+        out[:, ch] = np.bincount(seg, weights=w * sets.colour[:, ch], minlength=n)
+    none = (wsum == 0.0) | no_ref
+    with np.errstate(invalid="ignore", divide="ignore"):
+        out = out / wsum[:, None]
+    out[none] = c_ref[none]
+    return out
+
+
 def frame_sharpness(colour: np.ndarray) -> np.ndarray:
     """B(J) of Eq. 5: the sum over the pixels q of frame J of |grad I^J(q)|.
     Reading (the paper names the gradient operator only): forward differences
@@ -99,7 +155,7 @@ def frame_sharpness(colour: np.ndarray) -> np.ndarray:
 
 
 def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask: np.ndarray,
-                       sigma_rgb: float, steps: int = 2) -> np.ndarray:
+                       sigma_rgb: float, steps: int = 2, sigma_ref: float = math.inf) -> np.ndarray:
     """Inpainting (Sec. 5, Eq. 8-9) for the output pixels of frame sets.frame.
 
     mask [N, H, W] bool: M^J(q), True = the pixel shows content to remove.
@@ -110,7 +166,13 @@ def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask
     after `steps` steps (the paper uses two). Readings: only the colour dimensions
     are used (the paper gives sigma_rgb alone); the initial mean takes every sample,
     masked ones included, as Eq. 8 is written; an unmasked output pixel, an empty
-    set, or a step whose weights sum to zero returns I^f(p). Returns [n, 3] float64."""
+    set, or a step whose weights sum to zero returns I^f(p). Returns [n, 3] float64.
+
+    Semi-transparency (same paragraph): with a finite sigma_ref every weight is also
+    multiplied by exp(-|c_s - I^f(p)|^2 / (2 sigma_ref^2)), the standard weighting
+    around the input pixel, which favours samples coloured like the object being
+    made transparent (the paper uses sigma_rgb = 80 for it). Reading: the factor
+    multiplies the inpainting weight of every step; the initial mean is unchanged."""
     h, w_img = colour_f.shape[:2]
     c_ref = colour_f.reshape(-1, 3)[sets.pixels]
     dj = (sets.ids.astype(np.int64) >> ID_SHIFT) - window
@@ -125,9 +187,11 @@ def inpaint_mean_shift(sets: OracleSets, colour_f: np.ndarray, window: int, mask
         cs = sets.colour[a:b]
         keep = ~src_masked[a:b]
         s_ref = cs.mean(axis=0)
+        to_input = _factor(np.sum((cs - c_ref[i]) ** 2, axis=1), sigma_ref)
         ok = True
         for _ in range(steps):
             wgt = np.where(keep, np.exp(-np.sum((cs - s_ref) ** 2, axis=1) / (2.0 * sigma_rgb * sigma_rgb)), 0.0)
+            wgt = wgt * to_input
             tot = wgt.sum()
             if tot == 0.0:
                 ok = False

@@ -237,3 +237,111 @@ def test_box_mask_depth_range_and_invalid_depths():
     want[0, :3] = False
     want[1, :] = False
     assert np.array_equal(m[0], want)      # z = 2.0 on the far face is inside (bounds included)
+
+
+# ---------------------------------------------------------------------------
+# Eq. 4 with the scene-space term, and semi-transparency
+
+def _two_cameras():
+    """Frame 0 at the origin, frame 1 translated by (0.5, 0, 0), no rotation;
+    fx = fy = 100, cx = cy = 0; 4 x 4 images (only the listed pixels matter)."""
+    cams = np.stack([np.eye(4), np.eye(4)])
+    cams[1, 0, 3] = 0.5
+    return cams
+
+
+def test_scene_space_distances_worked_by_hand():
+    """Frame 0 at the origin, frame 1 translated by (0.5, 0, 0); fx = fy = 100,
+    (cx, cy) = (40, 1); images 64 x 4. Output pixel p = (40, 1) of frame 0 with depth
+    2: X_ref = (0, 0, 2). Samples: p itself (distance 0); frame 1 pixel (15, 1) at
+    depth 2: X = (2 (-25) / 100 + 0.5, 0, 2) = X_ref (distance 0); frame 1 pixel
+    (20, 1) at depth 2: X = (0.1, 0, 2) (distance^2 0.01); frame 1 pixel (15, 2) at
+    depth 2.2: X = (-0.55 + 0.5, 0.022, 2.2) (distance^2 0.0025 + 0.022^2 + 0.04).
+    With sigma_xyz = 0.1 the weights are 1, 1, e^-0.5 and e^-(0.042984 / 0.02)."""
+    w_img, h_img, cx, cy = 64, 4, 40.0, 1.0
+    cams = _two_cameras()
+    depth = np.full((2, h_img, w_img), 5.0)
+    depth[0, 1, 40] = 2.0
+    depth[1, 1, 15] = 2.0
+    depth[1, 1, 20] = 2.0
+    depth[1, 2, 15] = 2.2
+    cols = [(0.1, 0.2, 0.3), (0.4, 0.5, 0.6), (0.9, 0.1, 0.5), (0.2, 0.8, 0.7)]
+    p = w_img + 40
+    sets = _sets(0, 1, [[(0, p, cols[0], 0.0), (1, w_img + 15, cols[1], 0.0), (1, w_img + 20, cols[2], 0.0),
+                         (1, 2 * w_img + 15, cols[3], 0.0)]], h=h_img, w=w_img)
+    sets.pixels = np.array([p], dtype=np.int64)
+    colour_f = np.zeros((h_img, w_img, 3))
+    colour_f[1, 40] = cols[0]
+    got = of.scene_space_weighted_mean(sets, colour_f, depth, cams, 100.0, 100.0, cx, cy, 1,
+                                       math.inf, math.inf, 0.1, math.inf)
+    wts = np.array([1.0, 1.0, math.exp(-0.5), math.exp(-0.042984 / 0.02)])
+    want = (wts[:, None] * np.array(cols)).sum(0) / wts.sum()
+    assert np.allclose(got[0], want, rtol=0, atol=1e-14)
+    # sigma_xyz infinite: the plain mean; the frame factor multiplies each weight
+    got = of.scene_space_weighted_mean(sets, colour_f, depth, cams, 100.0, 100.0, cx, cy, 1,
+                                       math.inf, math.inf, math.inf, math.inf)
+    assert np.allclose(got[0], np.mean(cols, axis=0), atol=1e-15)
+    got = of.scene_space_weighted_mean(sets, colour_f, depth, cams, 100.0, 100.0, cx, cy, 1,
+                                       math.inf, math.inf, 0.1, math.inf, frame_w=np.array([3.0, 0.0]))
+    assert np.allclose(got[0], cols[0], atol=1e-15)
+    # an output pixel without a valid depth has no reference point: I^f(p)
+    depth[0, 1, 40] = np.nan
+    got = of.scene_space_weighted_mean(sets, colour_f, depth, cams, 100.0, 100.0, cx, cy, 1,
+                                       math.inf, math.inf, 0.1, math.inf)
+    assert np.array_equal(got[0], np.array(cols[0]))
+
+
+def test_scene_space_term_is_invariant_to_a_rigid_motion_of_the_world():
+    """Moving every camera by the same rigid transform moves every scene point with
+    it, so no distance (and no output) changes."""
+    rng = np.random.default_rng(3)
+    w_img, h_img = 12, 9
+    depth = 2.0 + 3.0 * rng.random((3, h_img, w_img))
+    cams = np.stack([np.eye(4)] * 3)
+    for j in range(3):
+        a = rng.normal(size=3) * 0.05
+        cams[j, :3, :3] = _rot(a)
+        cams[j, :3, 3] = rng.normal(size=3) * 0.2
+    g = np.eye(4)
+    g[:3, :3] = _rot(np.array([0.3, -0.7, 1.1]))
+    g[:3, 3] = [4.0, -2.0, 9.0]
+    members = []
+    for i in range(6):
+        members.append([(j, int(rng.integers(0, w_img * h_img)), tuple(rng.random(3)), 0.0)
+                        for j in (0, 1, 2) for _ in range(3)])
+    sets = _sets(1, 1, members, h=h_img, w=w_img)
+    sets.pixels = rng.choice(w_img * h_img, 6, replace=False).astype(np.int64)
+    colour_f = rng.random((h_img, w_img, 3))
+    args = (30.0, 30.0, 5.5, 4.0, 1, math.inf, 0.2, 0.3, 1.5)
+    a = of.scene_space_weighted_mean(sets, colour_f, depth, cams, *args)
+    b = of.scene_space_weighted_mean(sets, colour_f, depth, g @ cams, *args)
+    assert np.allclose(a, b, rtol=0, atol=1e-12)
+    assert not np.allclose(a, of.scene_space_weighted_mean(sets, colour_f, depth, cams, 30.0, 30.0, 5.5, 4.0, 1,
+                                                           math.inf, 0.2, math.inf, 1.5), atol=1e-6)
+
+
+def _rot(v):
+    th = float(np.linalg.norm(v))
+    k = v / th
+    kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(th) * kx + (1 - math.cos(th)) * (kx @ kx)
+
+
+def test_semi_transparency_two_sample_closed_form():
+    """Masked output pixel with input colour I = c1 and two unmasked samples c1, c2:
+    the first step starts from the mean (c1 + c2) / 2, equidistant from both, so the
+    inpainting factors are equal and only the factor around the input remains:
+    s_1 = (c1 + e^-b c2) / (1 + e^-b), b = |c2 - c1|^2 / (2 sigma_ref^2). With
+    sigma_ref infinite it is plain inpainting, (c1 + c2) / 2 after one step."""
+    c1, c2 = np.array([0.2, 0.3, 0.4]), np.array([0.6, 0.3, 0.1])
+    sets = _sets(0, 0, [[(0, 5, tuple(c1), 0.0), (0, 6, tuple(c2), 0.0)]])
+    colour_f = np.zeros((4, 4, 3))
+    colour_f[0, 0] = c1
+    mask = np.zeros((1, 4, 4), bool)
+    mask[0, 0, 0] = True
+    sr = 0.3
+    b = float(np.sum((c2 - c1) ** 2)) / (2 * sr * sr)
+    got = of.inpaint_mean_shift(sets, colour_f, 0, mask, 0.2, steps=1, sigma_ref=sr)
+    assert np.allclose(got[0], (c1 + math.exp(-b) * c2) / (1 + math.exp(-b)), atol=1e-15)
+    got = of.inpaint_mean_shift(sets, colour_f, 0, mask, 0.2, steps=1)
+    assert np.allclose(got[0], (c1 + c2) / 2, atol=1e-15)
