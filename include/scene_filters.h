@@ -3,7 +3,8 @@
  * Klose et al., Sampling Based Scene-Space Video Processing, Sec. 5: deblurring
  * (Eq. 5), computational scene-space shutters (Eq. 10) and inpainting (Eq. 8-9)
  * reduce the same sample sets S(p) as the denoising filter of scene_gather.h with
- * other weights. The sets, clip and status conventions are those of
+ * other weights; scene_filter_xyz adds Eq. 4's scene-space term, and
+ * scene_semi_transparent the semi-transparency of the inpainting paragraph. The sets, clip and status conventions are those of
  * scene_gather.h: every pointer named "device" is device memory owned by the
  * caller and borrowed for the call on `stream` (a hipStream_t, NULL = the null
  * stream); arguments are checked on the host before any GPU work, and a failed
@@ -48,6 +49,29 @@ sg_status scene_filter_frames(const sg_clip* clip, int32_t f0, int32_t f1, int32
                               const sg_sample_sets* sets, const sg_filter_params* params,
                               const float* frame_w, float* out_rgb, void* stream);
 
+/* The full weight of Eq. 4 (Sec. 5, denoising): Eq. 3 with
+ *   w(s) = exp(-rho^2 / 2 sigma_d^2) exp(-|c_s - c_ref|^2 / 2 sigma_c^2)
+ *          exp(-|X_s - X_ref|^2 / 2 sigma_xyz^2) exp(-(J - f)^2 / 2 sigma_t^2) * frame_w[J]
+ * (params->sigma_d, sigma_c, sigma_t as for scene_filter; +INFINITY disables a term).
+ * X_s is the sample's scene point (its source pixel q with its stored depth D^J(q) and
+ * camera C^J) and X_ref the scene point of the output pixel p (stored depth d_p,
+ * camera C^f): the distance is measured in the camera frame of J through the gather's
+ * folded relative map, in float32. sigma_xyz > 0 in world units (the paper states
+ * its sigma_xyz for a scene scaled so that 90 % of its points lie in a 10^3 cube:
+ * the caller converts), +INFINITY disables the term. frame_w: device [num_frames]
+ * float32 factors (deblurring, Eq. 5: B(J) from scene_frame_sharpness) or NULL for
+ * none. gparams: the gather parameters the sets were gathered with (window decodes
+ * J; the relative maps of every (f, J) pair are written into `workspace`, of at
+ * least scene_gather_workspace_size(clip, f0, f1, gparams) bytes). Needs clip->depth
+ * and the poses. An output pixel without a valid stored depth (not finite, or <= 0)
+ * has no reference point: with a finite sigma_xyz it gets I^f(p), as does a set
+ * whose weights sum to zero; a set that did not fit the arena, or an id outside the
+ * clip, gives NaN. sets->ids must be non-NULL when capacity > 0. */
+sg_status scene_filter_xyz(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* gparams,
+                           const sg_sample_sets* sets, const sg_filter_params* params, float sigma_xyz,
+                           const float* frame_w, void* workspace, size_t workspace_bytes, float* out_rgb,
+                           void* stream);
+
 /* Inpainting, Eq. 8-9. mask: device [num_frames][H][W] uint8, nonzero where the
  * pixel shows content to remove (M = 1). For an output pixel with M^f(p) = 1:
  * s_ref starts as the mean colour of all samples of its set (Eq. 8), and each of
@@ -62,6 +86,17 @@ sg_status scene_filter_frames(const sg_clip* clip, int32_t f0, int32_t f1, int32
 sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
                         const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, int32_t steps,
                         float* out_rgb, void* stream);
+
+/* Semi-transparency (Sec. 5, inpainting paragraph: the standard multivariate
+ * weighting around the input pixel added to the inpainting weight, sigma_rgb = 80
+ * of 255 there): scene_inpaint with every weight of Eq. 9 also multiplied by
+ * exp(-|c_s - I^f(p)|^2 / (2 sigma_ref^2)), which favours samples coloured like the
+ * object being made transparent. sigma_ref > 0 on the stored colours' scale
+ * (+INFINITY gives scene_inpaint exactly); other arguments and results as for
+ * scene_inpaint. */
+sg_status scene_semi_transparent(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                                 const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, float sigma_ref,
+                                 int32_t steps, float* out_rgb, void* stream);
 
 /* Inpainting masks from a scene-space region (Sec. 5, inpainting: the samples that
  * fall into the region, projected back into the images, form M). M^J(q) = 1 when

@@ -299,6 +299,15 @@ sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
                                 const int32_t* pixel_idx, int32_t n_pix, double* moments,
                                 void* workspace, size_t workspace_bytes, void* stream);
 
+/* The MLP's input standardisation from moments accumulated by
+ * scene_feature_moments (device float64 [17]: count, sums, sums of squares): in
+ * float64 on the device, mean_k = sum_k / n and std_k = sqrt(max(sumsq_k / n -
+ * mean_k^2, 0)) (n = max(count, 1)); a feature with std_k <= 1e-12 max(|mean_k|, 1)
+ * (no spread) gets std_k = 1. Writes float32 mean_k and 1 / std_k into the feature
+ * mean and 1/std entries of mlp_b (device float32 [SG_MLP_NB]); the other entries
+ * are left as they are. SG_E_INVALID on a null pointer. */
+sg_status scene_mlp_standardise(const double* moments, float* mlp_b, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched gather + filter (the per-clip computation of Sec. 4 and Sec. 5 Eq. 3,
  * run for many clips of different size, length and window in one step).

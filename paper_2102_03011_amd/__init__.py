@@ -428,6 +428,53 @@ def scene_inpaint(clip: StagedClip, sets: SampleSets, mask: torch.Tensor, sigma_
     return out
 
 
+def scene_semi_transparent(clip: StagedClip, sets: SampleSets, mask: torch.Tensor, sigma_rgb: float,
+                           sigma_ref: float, steps: int = 2, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Semi-transparency: inpainting whose weights also favour samples coloured like
+    the input pixel (Gaussian of sigma_ref around I^f(p)) -> [f1 - f0, H, W, 3] float32."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    _need_gpu(out, "out", torch.float32)
+    _need_gpu(mask, "mask", torch.uint8)
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    if tuple(mask.shape) != (clip.num_frames, clip.height, clip.width):
+        raise SceneGatherError(f"mask must have shape ({clip.num_frames}, {clip.height}, {clip.width})")
+    cc, ss = clip.c_struct(), sets.c_struct()
+    _check(_lib.scene_semi_transparent(ctypes.byref(cc), sets.f0, sets.f1, sets.window, ctypes.byref(ss),
+                                       mask.data_ptr(), float(sigma_rgb), float(sigma_ref), int(steps),
+                                       out.data_ptr(), _stream_handle()), "scene_semi_transparent")
+    return out
+
+
+def scene_filter_xyz(clip: StagedClip, sets: SampleSets, gparams: GatherParams, params: FilterParams,
+                     sigma_xyz: float, frame_w: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """Weighted mean with the full Eq. 4 weight (colour, scene-space position in world
+    units, frame time, depth residual) and an optional per-frame factor [N] float32
+    (deblurring: scene_frame_sharpness) -> [f1 - f0, H, W, 3] float32."""
+    shape = (sets.f1 - sets.f0, clip.height, clip.width, 3)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=clip.rgbd.device)
+    if ws is None:
+        ws = alloc_workspace(clip, sets.f0, sets.f1, gparams)
+    _need_gpu(out, "out", torch.float32)
+    _need_gpu(ws, "workspace", torch.uint8)
+    if frame_w is not None:
+        _need_gpu(frame_w, "frame_w", torch.float32)
+        if tuple(frame_w.shape) != (clip.num_frames,):
+            raise SceneGatherError(f"frame_w must have shape ({clip.num_frames},)")
+    if tuple(out.shape) != shape:
+        raise SceneGatherError(f"out must have shape {shape}")
+    cc, ss, pp, gg = clip.c_struct(), sets.c_struct(), params.c_struct(), gparams.c_struct()
+    _check(_lib.scene_filter_xyz(ctypes.byref(cc), sets.f0, sets.f1, ctypes.byref(gg), ctypes.byref(ss),
+                                 ctypes.byref(pp), float(sigma_xyz),
+                                 frame_w.data_ptr() if frame_w is not None else None, ws.data_ptr(), ws.numel(),
+                                 out.data_ptr(), _stream_handle()), "scene_filter_xyz")
+    return out
+
+
 def scene_box_mask(clip: StagedClip, lo, hi, out: torch.Tensor | None = None) -> torch.Tensor:
     """Inpainting masks from a world-space box [lo, hi] (3 floats each): 1 where a
     pixel's scene point lies inside -> [N, H, W] uint8."""
@@ -461,11 +508,13 @@ class MLPParams:
     b: torch.Tensor
 
     @staticmethod
-    def from_arrays(w1, b1, w2, b2, w3, b3, mean, std, device="cuda") -> "MLPParams":
+    def from_arrays(w1, b1, w2, b2, w3, b3, mean, inv_std, device="cuda") -> "MLPParams":
+        """Pack the layers (weights rounded to bfloat16) and the standardisation
+        (feature mean and 1/std, as the caller gives them) into the device layout."""
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).reshape(-1)
         w = torch.cat([t(w1), t(w2), t(w3)])
         b = torch.cat([t(b1), t(b2), torch.tensor([float(b3), 0.0, 0.0, 0.0], dtype=torch.float64), t(mean),
-                       1.0 / t(std)])
+                       t(inv_std)])
         return MLPParams(_bf16_bits(w).to(device).contiguous(), b.to(torch.float32).to(device).contiguous())
 
     def c_struct(self) -> _native.SgMlp:
@@ -568,16 +617,15 @@ def scene_feature_moments(clip: StagedClip, sets: SampleSets, params: GatherPara
     return moments
 
 
-def standardisation_from_moments(moments: torch.Tensor):
-    """(mean, std) float64 numpy arrays [8] from accumulated moments; a feature
-    with no spread gets std 1."""
-    m = moments.detach().cpu().double().numpy()
-    n = max(m[0], 1.0)
-    mean = m[1:1 + N_FEATURES] / n
-    var = np.maximum(m[1 + N_FEATURES:] / n - mean * mean, 0.0)
-    std = np.sqrt(var)
-    std[~(std > 1e-12 * np.maximum(np.abs(mean), 1.0))] = 1.0
-    return mean, std
+def scene_mlp_standardise(moments: torch.Tensor, mlp: MLPParams) -> None:
+    """Set mlp's feature mean and 1/std from moments accumulated by
+    scene_feature_moments (computed on the device)."""
+    _need_gpu(moments, "moments", torch.float64)
+    _need_gpu(mlp.b, "mlp.b", torch.float32)
+    if moments.numel() != 1 + 2 * N_FEATURES or mlp.b.numel() != SG_MLP_NB:
+        raise SceneGatherError("scene_mlp_standardise: moments must have 17 entries, mlp.b SG_MLP_NB")
+    _check(_lib.scene_mlp_standardise(moments.data_ptr(), mlp.b.data_ptr(), _stream_handle()),
+           "scene_mlp_standardise")
 
 
 # ---------------------------------------------------------------------------

@@ -109,6 +109,13 @@ SIGNATURES = {
     "scene_inpaint": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_float, ctypes.c_int32,
                                       c_void_p, c_void_p]),
+    "scene_filter_xyz": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
+                                         ctypes.POINTER(SgFilterParams), ctypes.c_float, c_void_p, c_void_p,
+                                         ctypes.c_size_t, c_void_p, c_void_p]),
+    "scene_semi_transparent": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(SgSampleSets), c_void_p, ctypes.c_float, ctypes.c_float,
+                                               ctypes.c_int32, c_void_p, c_void_p]),
     "scene_box_mask": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.POINTER(ctypes.c_double), c_void_p, c_void_p]),
     "scene_frustum_workspace_size": (ctypes.c_int, [ctypes.POINTER(SgClip), ctypes.c_int32,
                                                      ctypes.POINTER(SgFrustumParams), ctypes.POINTER(ctypes.c_size_t)]),
@@ -128,6 +135,7 @@ SIGNATURES = {
                                               ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgSampleSets),
                                               c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_size_t,
                                               c_void_p]),
+    "scene_mlp_standardise": (ctypes.c_int, [c_void_p, c_void_p, c_void_p]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.POINTER(SgClip), ctypes.c_int32,
                                         ctypes.POINTER(SgGatherParams), ctypes.POINTER(SgFilterParams),
                                         ctypes.POINTER(ctypes.c_int32)]),

@@ -350,4 +350,9 @@ sg_status scene_feature_moments(const sg_clip* clip, int32_t f0, int32_t f1,
   return hip_status(sg::launch_feature_moments(lj, pixel_idx, n_pix, moments, st));
 }
 
+sg_status scene_mlp_standardise(const double* moments, float* mlp_b, void* stream) {
+  if (moments == nullptr || mlp_b == nullptr) return SG_E_INVALID;
+  return hip_status(sg::launch_standardise(moments, mlp_b, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

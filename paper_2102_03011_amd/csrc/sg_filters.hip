@@ -16,6 +16,7 @@
 
 #include "scene_filters.h"
 #include "sg_device.h"
+#include "sg_internal.h"
 #include "sg_validate.h"
 
 namespace sg {
@@ -216,13 +217,138 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_frames(
 }
 
 // ---------------------------------------------------------------------------
+// Eq. 3 with the full Eq. 4 weight: colour, scene-space position and frame time
+// around the reference sample, the depth-residual term, and an optional per-frame
+// factor (Eq. 5). The scene-space distance between a sample (J, q, stored depth
+// D) and the reference point X of output pixel p is measured in the camera frame
+// of J (rigid maps keep distances): with the folded map of (f, J), Y = d_p M (x, y, 1)
+// + k = K (camera-J coordinates of X), and K (camera-J coordinates of the sample)
+// = D (q_x, q_y, 1), so their difference e = D (q_x, q_y, 1) - Y gives the distance
+// vector K^-1 e = ((e_x - cx e_z) / fx, (e_y - cy e_z) / fy, e_z).
+
+struct XyzArgs {
+  const float* rel;       // relative maps of the output frames [n_out][2w + 1][kRelStride]
+  const uint16_t* depth;  // stored depth planes
+  float a_x;              // -log2(e) / (2 sigma_xyz^2), 0 when the term is off
+  float fx_inv, fy_inv, cx, cy;
+};
+
+__global__ __launch_bounds__(kFilterThreads) void k_filter_xyz(
+    const uint2* __restrict__ rgbd_, int width, int height, int n_frames, int f0, int w, int64_t n_pix,
+    const int64_t* __restrict__ offsets_, const uint32_t* __restrict__ ids_, const uint2* __restrict__ crho_,
+    int64_t capacity, float a_d, float a_c, float a_t, const float* __restrict__ frame_w_, XyzArgs xa,
+    float* __restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kFilterThreads + threadIdx.x;
+  const int64_t pix = t / kLanes;
+  const int lane = static_cast<int>(t % kLanes);
+  gp<const uint32_t> ids = to_global(ids_);
+  gp<const uint2> crho = to_global(crho_);
+  gp<const float> frame_w = to_global(frame_w_);
+  gp<const uint16_t> depth = to_global(xa.depth);
+  gp<const uint2> rgbd = to_global(rgbd_);
+  const PixelSet p = pixel_set(rgbd, width, height, f0, n_pix, to_global(offsets_), capacity, pix);
+  const bool use_xyz = xa.a_x != 0.0f;
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const int64_t frame_px = static_cast<int64_t>(width) * height;
+  // the reference point: p's own stored depth
+  float dp = 0.0f, px = 0.0f, py = 0.0f;
+  bool no_ref = false;
+  gp<const float> relf = to_global(xa.rel);
+  if (p.live) {
+    const int y = static_cast<int>(p.self / width), x = static_cast<int>(p.self - static_cast<int64_t>(y) * width);
+    px = static_cast<float>(x);
+    py = static_cast<float>(y);
+    dp = h2f(depth[static_cast<size_t>(p.f) * pplane + padded_index(x, y, pw)]);
+    no_ref = use_xyz && !(dp > 0.0f && dp < INFINITY);
+    relf = relf + static_cast<size_t>(p.f - f0) * (2 * w + 1) * kRelStride;
+  }
+  const int jbase = p.f - w;
+  float wsum = 0.f, ar = 0.f, ag = 0.f, ab = 0.f;
+  int bad_id = 0;
+  const float inv_w = 1.0f / static_cast<float>(width);
+  auto accumulate = [&](uint2 rec, uint32_t id) {
+    const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y), rho = h2f(rec.y >> 16);
+    const int dj = static_cast<int>(id >> SG_ID_SHIFT);
+    const int j = jbase + dj;
+    const int64_t q = static_cast<int64_t>(id & kQMask);
+    if (j < 0 || j >= n_frames || q >= frame_px) {  // not an id of this clip and window
+      bad_id = 1;
+      return;
+    }
+    float arg = a_d * rho * rho;
+    const float er = r - p.cr, eg = g - p.cg, eb = b - p.cb;
+    arg = fmaf(a_c, fmaf(er, er, fmaf(eg, eg, eb * eb)), arg);
+    const float fdj = static_cast<float>(dj - w);
+    arg = fmaf(a_t, fdj * fdj, arg);
+    if (use_xyz) {
+      // q -> (q_x, q_y): float quotient, corrected to the exact one (q < 2^22)
+      const int qi = static_cast<int>(q);
+      int qy = static_cast<int>(static_cast<float>(qi) * inv_w);
+      int qx = qi - qy * width;
+      if (qx < 0) { --qy; qx += width; }
+      if (qx >= width) { ++qy; qx -= width; }
+      const float d = h2f(depth[static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw)]);
+      gp<const float> m = relf + dj * kRelStride;
+      const float y0 = fmaf(dp, fmaf(m[0], px, fmaf(m[1], py, m[2])), m[9]);
+      const float y1 = fmaf(dp, fmaf(m[3], px, fmaf(m[4], py, m[5])), m[10]);
+      const float z = fmaf(dp, fmaf(m[6], px, fmaf(m[7], py, m[8])), m[11]);
+      const float ex = fmaf(d, static_cast<float>(qx), -y0);
+      const float ey = fmaf(d, static_cast<float>(qy), -y1);
+      const float ez = d - z;
+      const float vx = fmaf(-xa.cx, ez, ex) * xa.fx_inv;
+      const float vy = fmaf(-xa.cy, ez, ey) * xa.fy_inv;
+      arg = fmaf(xa.a_x, fmaf(vx, vx, fmaf(vy, vy, ez * ez)), arg);
+    }
+    float wt = __builtin_amdgcn_exp2f(arg);
+    if (frame_w_ != nullptr) wt *= frame_w[j];
+    wsum += wt;
+    ar = fmaf(wt, r, ar);
+    ag = fmaf(wt, g, ag);
+    ab = fmaf(wt, b, ab);
+  };
+  if (!no_ref) {
+    // four records per lane in flight; each lane adds its records in order
+    int64_t i = p.s + lane;
+    for (; i + 3 * kLanes < p.e; i += 4 * kLanes) {
+      uint2 rec[4];
+      uint32_t id[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        rec[k] = ld2(crho + i + k * kLanes);
+        id[k] = ids[i + k * kLanes];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) accumulate(rec[k], id[k]);
+    }
+    for (; i < p.e; i += kLanes) accumulate(ld2(crho + i), ids[i]);
+  }
+  wsum = group_sum(wsum);
+  ar = group_sum(ar);
+  ag = group_sum(ag);
+  ab = group_sum(ab);
+  bad_id = group_or(bad_id);
+  if (p.live && lane == 0) {
+    if (p.bad || bad_id) {
+      const float nan = __builtin_nanf("");
+      store_rgb(to_global(out), pix, nan, nan, nan);
+    } else if (wsum > 0.f) {
+      const float inv = 1.0f / wsum;
+      store_rgb(to_global(out), pix, ar * inv, ag * inv, ab * inv);
+    } else {
+      store_rgb(to_global(out), pix, p.cr, p.cg, p.cb);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Inpainting: mean of the set, then `steps` weighted means around the current
 // estimate with masked source pixels left out.
 
 __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
     const uint2* __restrict__ rgbd_, int width, int height, int n_frames, int f0, int w, int64_t n_pix,
     const int64_t* __restrict__ offsets_, const uint32_t* __restrict__ ids_, const uint2* __restrict__ crho_,
-    int64_t capacity, const uint8_t* __restrict__ mask_, float a_c, int steps, float* __restrict__ out) {
+    int64_t capacity, const uint8_t* __restrict__ mask_, float a_c, float a_r, int steps, float* __restrict__ out) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kFilterThreads + threadIdx.x;
   const int64_t pix = t / kLanes;
   const int lane = static_cast<int>(t % kLanes);
@@ -280,7 +406,10 @@ __global__ __launch_bounds__(kFilterThreads) void k_inpaint(
         if (!use) return;
         const float r = h2f(rec.x), g = h2f(rec.x >> 16), b = h2f(rec.y);
         const float er = r - sr, eg = g - sg, eb = b - sb;
-        const float wt = __builtin_amdgcn_exp2f(a_c * fmaf(er, er, fmaf(eg, eg, eb * eb)));
+        // semi-transparency: the Gaussian around the input pixel (a_r = 0: inpainting alone)
+        const float ir = r - p.cr, ig = g - p.cg, ib = b - p.cb;
+        const float wt = __builtin_amdgcn_exp2f(
+            fmaf(a_r, fmaf(ir, ir, fmaf(ig, ig, ib * ib)), a_c * fmaf(er, er, fmaf(eg, eg, eb * eb))));
         wsum += wt;
         ar = fmaf(wt, r, ar);
         ag = fmaf(wt, g, ag);
@@ -438,20 +567,89 @@ sg_status scene_filter_frames(const sg_clip* clip, int32_t f0, int32_t f1, int32
   return hip_status(hipGetLastError());
 }
 
-sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window, const sg_sample_sets* sets,
-                        const uint8_t* mask, float sigma_rgb, int32_t steps, float* out_rgb, void* stream) {
+static sg_status inpaint_call(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window, const sg_sample_sets* sets,
+                              const uint8_t* mask, float sigma_rgb, float sigma_ref, int32_t steps, float* out_rgb,
+                              void* stream) {
   const sg_status s = sg::check_sets_call(clip, f0, f1, window, sets, mask, out_rgb);
   if (s != SG_OK) return s;
   if (!(sigma_rgb > 0.0f) || !isfinite(sigma_rgb)) return SG_E_INVALID;
+  if (!(sigma_ref > 0.0f)) return SG_E_INVALID;  // +INFINITY: no factor around the input pixel
   if (steps < 1) return SG_E_INVALID;
   if (steps > SG_MAX_INPAINT_STEPS) return SG_E_UNSUPPORTED;
   const double log2e = 1.4426950408889634;
   const float a_c = static_cast<float>(-log2e / (2.0 * sigma_rgb * static_cast<double>(sigma_rgb)));
+  const float a_r =
+      isfinite(sigma_ref) ? static_cast<float>(-log2e / (2.0 * sigma_ref * static_cast<double>(sigma_ref))) : 0.0f;
   const int64_t n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
   hipLaunchKernelGGL(sg::k_inpaint, dim3(static_cast<unsigned>(sg::filter_blocks(n_pix))), dim3(sg::kFilterThreads),
                      0, static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->width,
                      clip->height, clip->num_frames, f0, window, n_pix, sets->offsets, sets->ids,
-                     reinterpret_cast<const uint2*>(sets->crho), sets->capacity, mask, a_c, steps, out_rgb);
+                     reinterpret_cast<const uint2*>(sets->crho), sets->capacity, mask, a_c, a_r, steps, out_rgb);
+  return hip_status(hipGetLastError());
+}
+
+sg_status scene_inpaint(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window, const sg_sample_sets* sets,
+                        const uint8_t* mask, float sigma_rgb, int32_t steps, float* out_rgb, void* stream) {
+  return inpaint_call(clip, f0, f1, window, sets, mask, sigma_rgb, INFINITY, steps, out_rgb, stream);
+}
+
+sg_status scene_semi_transparent(const sg_clip* clip, int32_t f0, int32_t f1, int32_t window,
+                                 const sg_sample_sets* sets, const uint8_t* mask, float sigma_rgb, float sigma_ref,
+                                 int32_t steps, float* out_rgb, void* stream) {
+  return inpaint_call(clip, f0, f1, window, sets, mask, sigma_rgb, sigma_ref, steps, out_rgb, stream);
+}
+
+sg_status scene_filter_xyz(const sg_clip* clip, int32_t f0, int32_t f1, const sg_gather_params* gparams,
+                           const sg_sample_sets* sets, const sg_filter_params* params, float sigma_xyz,
+                           const float* frame_w, void* workspace, size_t workspace_bytes, float* out_rgb,
+                           void* stream) {
+  sg_status s = sg::check_clip(clip, true);
+  if (s != SG_OK) return s;
+  if ((s = sg::check_range(clip, f0, f1)) != SG_OK) return s;
+  if ((s = sg::check_params(gparams)) != SG_OK) return s;
+  if (sets == nullptr || sets->offsets == nullptr || params == nullptr || out_rgb == nullptr || workspace == nullptr)
+    return SG_E_INVALID;
+  if (sets->capacity < 0 || (sets->capacity > 0 && (sets->crho == nullptr || sets->ids == nullptr)))
+    return SG_E_INVALID;
+  if (!(sigma_xyz > 0.0f)) return SG_E_INVALID;  // +INFINITY disables the term
+  sg::FilterJob fj{};
+  if ((s = sg::filter_scales(params, &fj)) != SG_OK) return s;
+  size_t need = 0;
+  if ((s = scene_gather_workspace_size(clip, f0, f1, gparams, &need)) != SG_OK) return s;
+  if (workspace_bytes < need) return SG_E_INVALID;
+  const int64_t n_pix = static_cast<int64_t>(f1 - f0) * clip->width * clip->height;
+  if (sg::filter_blocks(n_pix) == 0) return SG_E_UNSUPPORTED;
+  // relative maps of every (f, J) pair in the workspace (the gather's pose prep)
+  sg::GatherJob jb{};
+  jb.width = clip->width;
+  jb.height = clip->height;
+  jb.n_frames = clip->num_frames;
+  jb.f0 = f0;
+  jb.n_out = f1 - f0;
+  jb.w = gparams->window;
+  jb.fx = clip->fx;
+  jb.fy = clip->fy;
+  jb.cx = clip->cx;
+  jb.cy = clip->cy;
+  jb.c2w = clip->cam_to_world;
+  jb.rel = static_cast<float*>(workspace);
+  jb.status = nullptr;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = hip_status(sg::launch_pose_prep(jb, st))) != SG_OK) return s;
+  sg::XyzArgs xa{};
+  xa.rel = jb.rel;
+  xa.depth = clip->depth;
+  const double log2e = 1.4426950408889634;
+  xa.a_x = isfinite(sigma_xyz) ? static_cast<float>(-log2e / (2.0 * sigma_xyz * static_cast<double>(sigma_xyz))) : 0.0f;
+  xa.fx_inv = static_cast<float>(1.0 / clip->fx);
+  xa.fy_inv = static_cast<float>(1.0 / clip->fy);
+  xa.cx = static_cast<float>(clip->cx);
+  xa.cy = static_cast<float>(clip->cy);
+  hipLaunchKernelGGL(sg::k_filter_xyz, dim3(static_cast<unsigned>(sg::filter_blocks(n_pix))),
+                     dim3(sg::kFilterThreads), 0, st, reinterpret_cast<const uint2*>(clip->rgbd), clip->width,
+                     clip->height, clip->num_frames, f0, gparams->window, n_pix, sets->offsets, sets->ids,
+                     reinterpret_cast<const uint2*>(sets->crho), sets->capacity, fj.a_d, fj.a_c, fj.a_t, frame_w, xa,
+                     out_rgb);
   return hip_status(hipGetLastError());
 }
 

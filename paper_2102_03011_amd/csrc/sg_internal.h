@@ -139,6 +139,7 @@ int64_t batch_filter_items(int64_t clip_pixels);  // filter work items of a clip
 
 hipError_t launch_filter_learned(const LearnedJob& lj, hipStream_t st);
 hipError_t launch_mlp_train(const LearnedJob& lj, const TrainJob& tj, hipStream_t st);
+hipError_t launch_standardise(const double* moments, float* mlp_b, hipStream_t st);
 hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,
                                   hipStream_t st);
 

@@ -1186,6 +1186,27 @@ static TrainArgs train_args(const LearnedJob& lj, const int32_t* pixel_idx, int 
   return ta;
 }
 
+// Feature standardisation from accumulated moments (count, sums, sums of squares):
+// mean = sum / n, variance = max(sum of squares / n - mean^2, 0) in float64; a
+// feature whose standard deviation is not above 1e-12 max(|mean|, 1) gets 1.
+// Writes the float32 mean and 1 / std into the MLP's parameter block.
+__global__ __launch_bounds__(64) void k_standardise(const double* __restrict__ moments, float* __restrict__ mb) {
+  const int k = threadIdx.x;
+  if (k >= kNF) return;
+  const double n = fmax(moments[0], 1.0);
+  const double mean = moments[1 + k] / n;
+  const double var = fmax(moments[1 + kNF + k] / n - mean * mean, 0.0);
+  double sd = sqrt(var);
+  if (!(sd > 1e-12 * fmax(fabs(mean), 1.0))) sd = 1.0;
+  mb[kOffMean + k] = static_cast<float>(mean);
+  mb[kOffMean + kNF + k] = static_cast<float>(1.0 / sd);
+}
+
+hipError_t launch_standardise(const double* moments, float* mlp_b, hipStream_t st) {
+  hipLaunchKernelGGL(k_standardise, dim3(1), dim3(64), 0, st, moments, mlp_b);
+  return hipGetLastError();
+}
+
 hipError_t launch_feature_moments(const LearnedJob& lj, const int32_t* pixel_idx, int n_pix, double* moments,
                                   hipStream_t st) {
   if (n_pix <= 0) return hipSuccess;

@@ -55,14 +55,17 @@ def load_mlp(path: str = DEFAULT_WEIGHTS, device="cuda") -> tuple[sg.MLPParams, 
     return sg.MLPParams(w.contiguous(), b.contiguous()), meta
 
 
-def init_params(mean, std, seed: int, device="cuda") -> sg.MLPParams:
-    """He initialisation (normal, fan-in), zero biases."""
+def init_params(moments: torch.Tensor, seed: int, device="cuda") -> sg.MLPParams:
+    """He initialisation (normal, fan-in), zero biases; the input standardisation
+    from the feature moments (computed by the library on the device)."""
     g = np.random.default_rng(seed)
     w1 = g.normal(size=(8, 64)) * math.sqrt(2.0 / 8)
     w2 = g.normal(size=(64, 64)) * math.sqrt(2.0 / 64)
     w3 = g.normal(size=64) * math.sqrt(1.0 / 64)
     z = np.zeros(64)
-    return sg.MLPParams.from_arrays(w1, z, w2, z, w3, 0.0, mean, std, device=device)
+    p = sg.MLPParams.from_arrays(w1, z, w2, z, w3, 0.0, np.zeros(8), np.ones(8), device=device)
+    sg.scene_mlp_standardise(moments, p)
+    return p
 
 
 # ---------------------------------------------------------------------------
@@ -158,9 +161,11 @@ def train(n_clips: int = 200, frames_per_clip: int = 4, steps_per_frame: int = 8
             fs = FrameSets(clip, staged, wl, f, window=int(rng.choice(windows)))
             moments = sg.scene_feature_moments(staged, fs.sets, fs.params, sample_pixels(fs, batch, gen),
                                                moments=moments, ws=fs.ws)
-    mean, std = sg.standardisation_from_moments(moments)
-    log(f"feature mean {np.array2string(mean, precision=4)} std {np.array2string(std, precision=4)}")
-    state = sg.MLPTrainState(init_params(mean, std, seed))
+    init = init_params(moments, seed)
+    std_b = init.b.detach().cpu().numpy()
+    log(f"feature mean {np.array2string(std_b[132:140], precision=4)} "
+        f"1/std {np.array2string(std_b[140:148], precision=4)}")
+    state = sg.MLPTrainState(init)
     total = n_clips * frames_per_clip * steps_per_frame
     losses = []
     step = 0
@@ -182,7 +187,7 @@ def train(n_clips: int = 200, frames_per_clip: int = 4, steps_per_frame: int = 8
                 f"{time.time() - t0:.0f}s")
     meta = {"clips": n_clips, "frames_per_clip": frames_per_clip, "steps": step, "batch": batch, "lr": lr,
             "lr_final": lr_final, "seed": seed, "windows": list(windows), "noise_mix": noise_mix,
-            "mean": mean.tolist(), "std": std.tolist(),
+            "mean": std_b[132:140].tolist(), "inv_std": std_b[140:148].tolist(),
             "final_loss": float(np.mean(losses[-20:])), "seconds": time.time() - t0}
     return state.params, meta
 

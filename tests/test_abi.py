@@ -565,3 +565,67 @@ def test_header_states_the_erf_gelu_the_oracle_and_kernels_use():
     assert "GELU(z) = z Phi(z)" in text and "0.044715" not in text
     assert abs(float(learned.gelu(1.0)) - 0.8413447460685429) < 1e-15
     assert abs(float(learned.gelu(-1.0)) + (1.0 - 0.8413447460685429)) < 1e-15
+
+
+def test_standardise_rejects_null_pointers(native):
+    mod, lib = native
+    assert lib.scene_mlp_standardise(None, 0x1000, None) == mod.SG_E_INVALID
+    assert lib.scene_mlp_standardise(0x1000, None, None) == mod.SG_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["null_clip", "bad_range", "null_gparams", "null_sets", "null_params", "null_out",
+                                  "null_ws", "small_ws", "sigma_xyz_zero", "sigma_xyz_nan", "sigma_d_zero"])
+def test_filter_xyz_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    g = mod.SgGatherParams(3, 1, 0.01, 0.01)
+    s = _sets(mod, 100)
+    fp = mod.SgFilterParams(0.01, math.inf, math.inf, 0.0)
+    f0, f1, sx = 0, 2, 0.1
+    need = ctypes.c_size_t(0)
+    assert lib.scene_gather_workspace_size(ctypes.byref(c), f0, f1, ctypes.byref(g), ctypes.byref(need)) == 0
+    cp, gp, sp, fpp, out, ws, wsb = ctypes.byref(c), ctypes.byref(g), ctypes.byref(s), ctypes.byref(fp), 0x90000, \
+        0xA0000, need.value
+    if case == "null_clip":
+        cp = None
+    elif case == "bad_range":
+        f1 = 0
+    elif case == "null_gparams":
+        gp = None
+    elif case == "null_sets":
+        sp = None
+    elif case == "null_params":
+        fpp = None
+    elif case == "null_out":
+        out = None
+    elif case == "null_ws":
+        ws = None
+    elif case == "small_ws":
+        wsb -= 1
+    elif case == "sigma_xyz_zero":
+        sx = 0.0
+    elif case == "sigma_xyz_nan":
+        sx = math.nan
+    elif case == "sigma_d_zero":
+        fp.sigma_d = 0.0
+    assert lib.scene_filter_xyz(cp, f0, f1, gp, sp, fpp, sx, None, ws, wsb, out, None) == mod.SG_E_INVALID, case
+
+
+@pytest.mark.parametrize("case", ["sigma_ref_zero", "sigma_ref_nan", "sigma_rgb_inf", "null_mask", "steps_zero"])
+def test_semi_transparent_rejects_bad_arguments(native, case):
+    mod, lib = native
+    c = _clip(mod)
+    s = _sets(mod, 100)
+    mask, srgb, sref, steps = 0xB0000, 0.2, 0.3, 2
+    if case == "sigma_ref_zero":
+        sref = 0.0
+    elif case == "sigma_ref_nan":
+        sref = math.nan
+    elif case == "sigma_rgb_inf":
+        srgb = math.inf
+    elif case == "null_mask":
+        mask = None
+    elif case == "steps_zero":
+        steps = 0
+    assert lib.scene_semi_transparent(ctypes.byref(c), 0, 2, 3, ctypes.byref(s), mask, srgb, sref, steps, 0x90000,
+                                      None) == mod.SG_E_INVALID, case

@@ -10,7 +10,7 @@ def test_checkpoint_round_trip(tmp_path):
     import paper_2102_03011_amd as sg
     from paper_2102_03011_amd import train
     m = learned.init_mlp(1, mean=np.arange(8.0), std=np.arange(1.0, 9.0))
-    p = sg.MLPParams.from_arrays(m.w1, m.b1, m.w2, m.b2, m.w3, 0.5, m.mean, m.std, device="cpu")
+    p = sg.MLPParams.from_arrays(m.w1, m.b1, m.w2, m.b2, m.w3, 0.5, m.mean, 1.0 / m.std, device="cpu")
     path = str(tmp_path / "w.npz")
     train.save_mlp(path, p, {"note": "x"})
     q, meta = train.load_mlp(path, device="cpu")

@@ -230,3 +230,108 @@ def test_box_mask_matches_oracle_and_feeds_inpainting(name, request):
     ref = ofilters.inpaint_mean_shift(orc, col[f], wl.window, want, sigma)
     if not near.any():
         assert _err(out, ref, band) <= parity.COLOUR_TOL
+
+
+# ---------------------------------------------------------------------------
+# Eq. 4 with its scene-space term (scene_filter_xyz) and semi-transparency
+
+def _scene_side(clip, dep):
+    """Side in metres of the cube the paper's scene scale refers to: the largest per-axis
+    5 %-95 % range of the scene points of every frame (10 scene units = this many metres)."""
+    cams = clip.cam_to_world.numpy()
+    valid = np.isfinite(dep) & (dep > 0)
+    pts = ofilters.scene_points(np.where(valid, dep, 1.0), cams, clip.fx, clip.fy, clip.cx, clip.cy)[valid]
+    return float(max(np.quantile(pts[:, k], 0.95) - np.quantile(pts[:, k], 0.05) for k in range(3)))
+
+
+def _own_sets(sets, orc_frame, n_pix):
+    """The GPU's own records as oracle sets (every output pixel of the frame)."""
+    g_off, g_ids, g_crho = parity.gpu_sets_to_host(sets, 0, n_pix)
+    return ogather.OracleSets(frame=orc_frame, pixels=np.arange(n_pix, dtype=np.int64), offsets=g_off,
+                              ids=g_ids.astype(np.uint32), rho=parity.f16_to_f64(g_crho[:, 3].copy()),
+                              colour=parity.f16_to_f64(g_crho[:, :3].copy()),
+                              marginal=np.zeros(g_ids.size, dtype=bool),
+                              maybe_offsets=np.zeros(n_pix + 1, dtype=np.int64),
+                              maybe_ids=np.zeros(0, dtype=np.uint32), maybe_rho=np.zeros(0))
+
+
+@pytest.mark.parametrize("name,preset", [("small", "xyz"), ("small", "paper"), ("small", "deblur"),
+                                          ("ragged", "xyz"), ("ragged", "deblur")])
+def test_scene_space_filter_matches_oracle(name, preset, request):
+    """Eq. 4 with sigma_xyz: a tight 0.1 m with the depth term; the paper's denoising
+    preset (sigma_rgb 40, sigma_xyz 10 scene units, sigma_f 6) and deblurring preset
+    (Eq. 5: 200, 10, 20, times B(J)) with the scene scale of the clip. Against the
+    oracle on its own sets (outside bands, 1e-3) and on the GPU's own records."""
+    wl, clip, staged, col, sets, orc, band = request.getfixturevalue(name)
+    sg = _sg()
+    f = orc.frame
+    dep = ostaging.depth_q(clip.depth.cpu().numpy())
+    cams = clip.cam_to_world.numpy()
+    side = _scene_side(clip, dep)
+    if preset == "xyz":
+        sd, sc, st, sx, fw = 0.01, math.inf, math.inf, 0.1, None
+    elif preset == "paper":
+        sd, sc, st, sx, fw = math.inf, 40.0 / 255.0, 6.0, side, None
+    else:
+        sd, sc, st, sx, fw = math.inf, 200.0 / 255.0, 20.0, side, sg.scene_frame_sharpness(staged)
+    gp = sg.GatherParams(window=wl.window, tol=wl.tol, z_near=wl.z_near)
+    got = sg.scene_filter_xyz(staged, sets, gp, sg.FilterParams(sigma_d=sd, sigma_c=sc, sigma_t=st), sx,
+                              frame_w=fw).cpu().numpy()
+    fw_h = None if fw is None else fw.cpu().numpy().astype(np.float64)
+    fw_o = None if fw is None else ofilters.frame_sharpness(col)
+    want = ofilters.scene_space_weighted_mean(orc, col[f], dep, cams, clip.fx, clip.fy, clip.cx, clip.cy,
+                                              wl.window, sd, sc, sx, st, frame_w=fw_o)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+    n_pix = clip.height * clip.width
+    own = ofilters.scene_space_weighted_mean(_own_sets(sets, f, n_pix), col[f], dep, cams, clip.fx, clip.fy,
+                                             clip.cx, clip.cy, wl.window, sd, sc, sx, st, frame_w=fw_h)
+    e = np.abs(got.reshape(-1, 3).astype(np.float64) - own).max()
+    assert e <= 1e-4, e
+    if name == "ragged":
+        # output pixels without a valid stored depth have no reference point
+        d = dep[f].reshape(-1)
+        nor = ~(np.isfinite(d) & (d > 0))
+        assert nor.any()
+        assert np.array_equal(got.reshape(-1, 3)[nor].astype(np.float64), col[f].reshape(-1, 3)[nor])
+
+
+def test_scene_space_filter_without_the_term_is_the_plain_filter(small):
+    wl, clip, staged, col, sets = small[:5]
+    sg = _sg()
+    gp = sg.GatherParams(window=wl.window, tol=wl.tol, z_near=wl.z_near)
+    for fp in (sg.FilterParams(sigma_d=0.01), sg.FilterParams(sigma_d=0.01, sigma_c=40.0 / 255.0, sigma_t=6.0)):
+        a = sg.scene_filter_xyz(staged, sets, gp, fp, math.inf)
+        b = sg.scene_filter(staged, sets, fp)
+        torch.cuda.synchronize()
+        assert float((a - b).abs().max()) <= 1e-6
+    b_j = sg.scene_frame_sharpness(staged)
+    fp = sg.FilterParams(sigma_d=math.inf, sigma_c=200.0 / 255.0, sigma_t=20.0)
+    a = sg.scene_filter_xyz(staged, sets, gp, fp, math.inf, frame_w=b_j)
+    b = sg.scene_filter_frames(staged, sets, fp, b_j)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max()) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_semi_transparency_matches_oracle(name, request):
+    wl, clip, staged, col, sets, orc, band = request.getfixturevalue(name)
+    sg = _sg()
+    f = orc.frame
+    n, h, w = clip.n_frames, clip.height, clip.width
+    mask = _moving_box_mask(n, h, w, x0=w // 5, y0=h // 4, bw=w // 3, bh=h // 3, dx=max(1, w // 40))
+    m = torch.from_numpy(mask).cuda()
+    sigma = 80.0 / 255.0
+    got = sg.scene_semi_transparent(staged, sets, m, sigma, sigma, steps=2).cpu().numpy()
+    want = ofilters.inpaint_mean_shift(orc, col[f], wl.window, mask.astype(bool), sigma, steps=2, sigma_ref=sigma)
+    assert _err(got, want, band) <= parity.COLOUR_TOL
+    keep = mask[f].reshape(-1) == 0
+    assert np.array_equal(got.reshape(-1, 3)[keep].astype(np.float64), col[f].reshape(-1, 3)[keep])
+    # the factor around the input pixel pulls the result toward it, against plain inpainting
+    plain = sg.scene_inpaint(staged, sets, m, sigma, steps=2).cpu().numpy().reshape(-1, 3)
+    cin = col[f].reshape(-1, 3)
+    d_semi = np.abs(got.reshape(-1, 3)[~keep] - cin[~keep]).sum(1)
+    d_plain = np.abs(plain[~keep] - cin[~keep]).sum(1)
+    assert d_semi.mean() < d_plain.mean()
+    # sigma_ref infinite is scene_inpaint, bit for bit
+    same = sg.scene_semi_transparent(staged, sets, m, sigma, math.inf, steps=2).cpu().numpy().reshape(-1, 3)
+    assert np.array_equal(same, plain)

@@ -73,7 +73,7 @@ class Case:
 
 def _device_mlp(m: learned.MLP):
     sg = _sg()
-    p = sg.MLPParams.from_arrays(m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, m.mean, m.std)
+    p = sg.MLPParams.from_arrays(m.w1, m.b1, m.w2, m.b2, m.w3, m.b3, m.mean, 1.0 / m.std)
     return p, learned_ref.oracle_mlp_from_device(p)
 
 
@@ -249,6 +249,51 @@ def test_train_step_gradient_loss_and_adam(small):
     assert torch.equal(state.params.b[129:], dev.b[129:])
 
 
+def test_three_adam_steps_match_the_oracle(small):
+    """Three device steps in a row. At each step t: the gradient the device used
+    (recovered from its first moments, g_t = (m_t - 0.9 m_{t-1}) / 0.1) matches the
+    oracle's backward at the device's current forward copy; the second moments follow
+    v_t = 0.999 v_{t-1} + 0.001 g_t^2; and the masters moved by Adam's step with the
+    bias corrections of step t, lr (m_t / (1 - 0.9^t)) / (sqrt(v_t / (1 - 0.999^t)) + 1e-8).
+    From t = 2 on, both decays and both corrections change the result."""
+    sg = _sg()
+    pixels = _train_batch(small, 512, 4)
+    off, x, col = small.features(pixels)
+    mean, std = _moments(x)
+    dev, _ = _device_mlp(learned_ref.random_mlp(23, mean, std))
+    clean = small.clip.clean[small.f].reshape(-1, 3).cpu().numpy().astype(np.float64)[pixels]
+    state = sg.MLPTrainState(dev)
+    lr = 1e-3
+    idx = torch.tensor(pixels, dtype=torch.int32, device="cuda")
+    clean_d = torch.tensor(clean, dtype=torch.float32, device="cuda")
+    sizes = [("w1", 512), ("w2", 4096), ("w3", 64), ("b1", 64), ("b2", 64), ("b3", 1)]
+    m_prev = np.zeros(sg.SG_MLP_NPARAM)
+    v_prev = np.zeros(sg.SG_MLP_NPARAM)
+    th_prev = state.master.cpu().numpy().astype(np.float64)
+    for t in (1, 2, 3):
+        om = learned_ref.oracle_mlp_from_device(state.params)
+        _, g, _ = learned.loss_and_grads(learned.standardise(x, om), col, off, small.c_ref(pixels), clean, om)
+        sg.scene_mlp_train_step(small.staged, small.sets, small.params, idx, clean_d, state, lr)
+        torch.cuda.synchronize()
+        assert state.t == t
+        m_t = state.adam_m.cpu().numpy().astype(np.float64)
+        v_t = state.adam_v.cpu().numpy().astype(np.float64)
+        th_t = state.master.cpu().numpy().astype(np.float64)
+        g_dev = (m_t - 0.9 * m_prev) / 0.1
+        pos = 0
+        for name, n in sizes:
+            if name != "b3":
+                want = np.ravel(g[name])
+                rel = np.linalg.norm(g_dev[pos:pos + n] - want) / max(np.linalg.norm(want), 1e-30)
+                assert rel <= GRAD_REL_TOL, (t, name, rel)
+            pos += n
+        want_v = 0.999 * v_prev + 0.001 * g_dev * g_dev
+        assert np.all(np.abs(v_t - want_v) <= 1e-4 * want_v + 1e-18), t
+        step = lr * (m_t / (1 - 0.9 ** t)) / (np.sqrt(v_t / (1 - 0.999 ** t)) + 1e-8)
+        assert np.allclose(th_t, th_prev - step, rtol=0, atol=lr * 1e-4), t
+        m_prev, v_prev, th_prev = m_t, v_t, th_t
+
+
 def test_training_lowers_loss(small):
     sg = _sg()
     pixels = _train_batch(small, 1024, 1, with_empty=False)
@@ -296,8 +341,27 @@ def test_feature_moments_match_oracle(small):
     # float32 features summed in float64: relative 1e-5 of the sum of magnitudes
     assert np.all(np.abs(got[1:9] - x2.sum(0)) <= 1e-5 * np.abs(x2).sum(0) + 1e-12)
     assert np.all(np.abs(got[9:] - (x2 * x2).sum(0)) <= 1e-5 * (x2 * x2).sum(0) + 1e-12)
-    mean, std = sg.standardisation_from_moments(mom)
-    assert np.allclose(mean, x2.mean(0), rtol=1e-5, atol=1e-9)
+    # the library's standardisation from those moments: mean and 1 / std (population
+    # standard deviation) of the features, written into the parameter block only
+    p = sg.MLPParams.from_arrays(np.zeros((8, 64)), np.zeros(64), np.zeros((64, 64)), np.zeros(64), np.zeros(64),
+                                 0.25, np.zeros(8), np.ones(8))
+    before = p.b.clone()
+    sg.scene_mlp_standardise(mom, p)
+    b = p.b.cpu().numpy().astype(np.float64)
+    assert np.allclose(b[132:140], x2.mean(0), rtol=1e-5, atol=1e-9)
+    assert np.allclose(b[140:148], 1.0 / x2.std(0), rtol=1e-5)
+    assert torch.equal(p.b[:132], before[:132])
+    # no spread (a constant feature) and no records: std taken as 1
+    m2 = torch.zeros(17, dtype=torch.float64, device="cuda")
+    m2[0], m2[1], m2[9] = 4.0, 8.0, 16.0          # feature 0: four records of value 2
+    m2[2], m2[10] = 4.0, 20.0                      # feature 1: mean 1, variance 4
+    sg.scene_mlp_standardise(m2, p)
+    b = p.b.cpu().numpy().astype(np.float64)
+    assert b[132] == 2.0 and b[140] == 1.0 and b[133] == 1.0 and b[141] == 0.5
+    assert np.all(b[134:140] == 0.0) and np.all(b[142:148] == 1.0)
+    sg.scene_mlp_standardise(torch.zeros(17, dtype=torch.float64, device="cuda"), p)
+    b = p.b.cpu().numpy()
+    assert np.all(b[132:140] == 0.0) and np.all(b[140:148] == 1.0)
 
 
 def test_training_driver_runs_and_checkpoint_loads(tmp_path):
