@@ -93,3 +93,67 @@ def estimate_depth(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: 
     if with_bands:
         return depth, best, band
     return depth, best
+
+
+def cost_intervals(colour: np.ndarray, cam_to_world: np.ndarray, fx: float, fy: float, cx: float, cy: float,
+                   f: int, window: int, hypotheses: np.ndarray, pixels: np.ndarray,
+                   rnd_band: float = RND_BAND) -> tuple[np.ndarray, np.ndarray]:
+    """For comparisons with a float32 evaluation: per listed pixel and hypothesis, the
+    range [lo, hi] of mean costs over every rounding that float32 may take. A
+    projection within rnd_band of a half-integer may round to either neighbour, so
+    the frame's patch cost is the least or largest SSD over those positions; when a
+    possible position changes whether the frame counts (its patch leaves the image),
+    the hypothesis is left open, [0, inf]. A hypothesis that no frame counts for (in
+    every rounding) gets [nan, nan]; the pixel's own patch outside the image gives
+    nan throughout. Same definitions as estimate_depth. Returns lo, hi [n, K]."""
+    n, h, w = colour.shape[:3]
+    k = _poses.intrinsics(fx, fy, cx, cy)
+    kinv = np.linalg.inv(k)
+    others = [j for j in range(max(0, f - window), min(n - 1, f + window) + 1) if j != f]
+    to_j = {j: np.linalg.inv(cam_to_world[j]) @ cam_to_world[f] for j in others}
+    pixels = np.asarray(pixels, dtype=np.int64)
+    lo = np.full((pixels.size, len(hypotheses)), np.nan)
+    hi = np.full((pixels.size, len(hypotheses)), np.nan)
+
+    def roundings(c):
+        r = int(np.floor(c + 0.5))
+        out = {r}
+        if abs(c + 0.5 - np.floor(c + 0.5)) <= rnd_band:
+            out.add(r - 1)
+        if abs(c + 0.5 - np.ceil(c + 0.5)) <= rnd_band:
+            out.add(r + 1)
+        return out
+
+    for i, p in enumerate(pixels):
+        y, x = int(p // w), int(p % w)
+        if not (1 <= x < w - 1 and 1 <= y < h - 1):
+            continue
+        ray = kinv @ np.array([x, y, 1.0])
+        for kk, d in enumerate(hypotheses):
+            if not (np.isfinite(d) and d > 0):
+                continue
+            xf = np.append(d * ray, 1.0)
+            lo_sum = hi_sum = 0.0
+            counted, open_ = 0, False
+            for j in others:
+                yj = to_j[j] @ xf
+                if yj[2] <= 0:
+                    continue
+                u = k[0, 0] * yj[0] / yj[2] + k[0, 2]
+                v = k[1, 1] * yj[1] / yj[2] + k[1, 2]
+                pos = [(qx, qy) for qx in roundings(u) for qy in roundings(v)]
+                ins = [1 <= qx < w - 1 and 1 <= qy < h - 1 for qx, qy in pos]
+                if any(ins) and not all(ins):
+                    open_ = True
+                    break
+                if not ins[0]:
+                    continue
+                ssd = [patch_ssd(colour[f], y, x, colour[j], qy, qx) for qx, qy in pos]
+                lo_sum += min(ssd)
+                hi_sum += max(ssd)
+                counted += 1
+            if open_:
+                lo[i, kk], hi[i, kk] = 0.0, np.inf
+            elif counted:
+                lo[i, kk], hi[i, kk] = lo_sum / counted, hi_sum / counted
+    return lo, hi

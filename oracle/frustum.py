@@ -63,6 +63,8 @@ class FrustumSets:
     colour: np.ndarray     # [S, 3] float64
     marginal: np.ndarray   # [S] bool: within a band of the L1 or depth-range bound
     near_miss: np.ndarray  # [n] bool: some non-member of p lies within such a band
+    near_offsets: np.ndarray | None = None  # [n + 1] CSR over the pixel list: those non-members,
+    near_ids: np.ndarray | None = None      # [M] ids, ascending per pixel
 
 
 def carried_into_output(depth_j: np.ndarray, c_j: np.ndarray, c_f: np.ndarray, k: np.ndarray):
@@ -96,6 +98,7 @@ def gather_frustum(colour: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarr
     slot[pixels] = np.arange(pixels.size)
     dp = depth[f].reshape(-1)
     parts = []     # (slot, id, rho, colour, marginal) per window frame and offset
+    near = []      # (slot, id) of non-members within a band
     near_miss = np.zeros(pixels.size, dtype=bool)
     j_lo, j_hi = max(0, f - prm.window), min(n_frames - 1, f + prm.window)
     for j in range(j_lo, j_hi + 1):
@@ -121,7 +124,10 @@ def gather_frustum(colour: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarr
                 dist = np.abs(ox - ax) + np.abs(oy - ay)
                 marg = zmq | (np.abs(dist - half) <= L1_BAND)
                 member = use & (dist < half) & inzq
-                near_miss[sl[use & ~member & marg]] = True
+                nm = use & ~member & marg
+                near_miss[sl[nm]] = True
+                if nm.any():
+                    near.append((sl[nm], ((j - f + prm.window) << ID_SHIFT) | cand[nm]))
                 if not member.any():
                     continue
                 q = cand[member]
@@ -143,9 +149,17 @@ def gather_frustum(colour: np.ndarray, depth: np.ndarray, cam_to_world: np.ndarr
     counts = np.bincount(slots, minlength=pixels.size)
     offsets = np.zeros(pixels.size + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(counts)
+    if near:
+        n_sl = np.concatenate([a for a, _ in near])
+        n_id = np.concatenate([b for _, b in near]).astype(np.int64)
+    else:
+        n_sl = n_id = np.zeros(0, dtype=np.int64)
+    n_order = np.lexsort((n_id, n_sl))
+    near_offsets = np.zeros(pixels.size + 1, dtype=np.int64)
+    near_offsets[1:] = np.cumsum(np.bincount(n_sl, minlength=pixels.size))
     return FrustumSets(frame=f, pixels=pixels, offsets=offsets, ids=idents[order].astype(np.uint32),
                        rho=rhos[order], colour=cols[order].reshape(-1, 3), marginal=margs[order],
-                       near_miss=near_miss)
+                       near_miss=near_miss, near_offsets=near_offsets, near_ids=n_id[n_order].astype(np.uint32))
 
 
 def _convex_hull(pts: np.ndarray) -> np.ndarray:

@@ -12,9 +12,9 @@
 //   bucket  -- counting sort of the kept q by b(q) (count, scan, atomic fill: the
 //              order inside a bucket is arbitrary);
 //   count / scatter -- each output pixel reads the buckets within L1 distance rb,
-//              applies Eq. 2, and (scatter) emits its members of J in ascending q
-//              by repeated minimum, so the records come out in canonical order
-//              whatever order the buckets hold.
+//              applies Eq. 2, and (scatter) orders its members of J by q in a small
+//              per-thread sort, so the records come out in canonical order whatever
+//              order the buckets hold.
 // The member counts are scanned into the caller's CSR offsets between the passes.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -214,13 +214,25 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __res
   to_global(counts)[p] = n;
 }
 
+// Members of one (p, J) pair held per thread while they are ordered: kSortSlots
+// entries of (q, z') in LDS, laid out [slot][thread] so that the threads of a wave
+// touch consecutive words.
+constexpr int kSortSlots = 24;
+
+// Scatter: per output pixel and window frame, one pass over the buckets collects the
+// members, an insertion sort on q orders them, and they are written in canonical
+// order. A pair with more than kSortSlots members (dense occluders) emits by repeated
+// minimum instead, one pass over the buckets per member.
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_, const Carried* __restrict__ carry,
     const int32_t* __restrict__ items, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
     int n_j, int rb, float half, int64_t n_pix, int64_t n_buckets, const int64_t* __restrict__ offsets_,
     uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity, uint32_t* __restrict__ status_) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (p >= n_pix) return;
+  __shared__ int32_t s_q[kSortSlots][kThreads];
+  __shared__ float s_z[kSortSlots][kThreads];
+  const int t = threadIdx.x;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + t;
+  if (p >= n_pix) return;  // no barrier below: threads are independent
   gp<uint32_t> status = to_global(status_);
   const int64_t start = to_global(offsets_)[p], end = to_global(offsets_)[p + 1];
   if (start < 0 || end < start) {
@@ -240,29 +252,56 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
   gp<uint32_t> ids = to_global(ids_);
   gp<uint2> crho = to_global(crho_);
   int64_t cur = start;
+  auto emit = [&](int j, uint32_t id_j, int32_t q, float z) {
+    if (cur < end) {  // a count that changed since pass 1 never writes past the segment
+      const int qy = q / width, qx = q - qy * width;
+      const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
+      const float rho = has_ref ? (z - dp) / dp : __builtin_nanf("");
+      st2(crho + cur, make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16)));
+      ids[cur] = id_j | static_cast<uint32_t>(q);
+    }
+    ++cur;
+  };
   for (int jn = 0; jn < n_j; ++jn) {
     const int j = jlo + jn;
     const uint32_t id_j = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
-    int32_t last = -1;
-    for (;;) {  // members of J in ascending q: the smallest one above the last emitted
-      int32_t best = INT_MAX;
-      float best_z = 0.0f;
-      for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
-        if (q > last && q < best) {
-          best = q;
-          best_z = c.z;
-        }
-      });
-      if (best == INT_MAX) break;
-      if (cur < end) {  // a count that changed since pass 1 never writes past the segment
-        const int qy = best / width, qx = best - qy * width;
-        const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
-        const float rho = has_ref ? (best_z - dp) / dp : __builtin_nanf("");
-        st2(crho + cur, make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16)));
-        ids[cur] = id_j | static_cast<uint32_t>(best);
+    int n = 0;
+    for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+      if (n < kSortSlots) {
+        s_q[n][t] = q;
+        s_z[n][t] = c.z;
       }
-      ++cur;
-      last = best;
+      ++n;
+    });
+    if (n <= kSortSlots) {
+      for (int a = 1; a < n; ++a) {  // insertion sort on q (q values are distinct)
+        const int32_t qa = s_q[a][t];
+        const float za = s_z[a][t];
+        int b = a - 1;
+        while (b >= 0 && s_q[b][t] > qa) {
+          s_q[b + 1][t] = s_q[b][t];
+          s_z[b + 1][t] = s_z[b][t];
+          --b;
+        }
+        s_q[b + 1][t] = qa;
+        s_z[b + 1][t] = za;
+      }
+      for (int a = 0; a < n; ++a) emit(j, id_j, s_q[a][t], s_z[a][t]);
+    } else {
+      int32_t last = -1;
+      for (;;) {  // the smallest member above the last emitted
+        int32_t best = INT_MAX;
+        float best_z = 0.0f;
+        for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+          if (q > last && q < best) {
+            best = q;
+            best_z = c.z;
+          }
+        });
+        if (best == INT_MAX) break;
+        emit(j, id_j, best, best_z);
+        last = best;
+      }
     }
   }
   if (cur != end) flag_or(status, SG_FLAG_INCONSISTENT);

@@ -108,3 +108,35 @@ def pixels_with_band_cases(orc: ogather.OracleSets) -> np.ndarray:
     flag[seg[orc.marginal]] = True
     flag |= np.diff(orc.maybe_offsets) > 0
     return flag
+
+
+def compare_frustum(orc, g_off, g_ids, g_crho, dp):
+    """Frustum sets, candidate by candidate: for every listed output pixel, the
+    oracle's members outside its bands are in the GPU's set, every GPU id is an
+    oracle member or one of its near-miss non-members, ids ascend, and each shared
+    member carries the source pixel's colour exactly and rho within binary16 rounding
+    (NaN when the pixel has no valid depth). dp: stored depth of each listed pixel.
+    Returns counts for the report."""
+    members_checked = extra = 0
+    for k, i in enumerate(orc.pixels):
+        a, b = g_off[i], g_off[i + 1]
+        got = g_ids[a:b]
+        assert np.all(np.diff(got.astype(np.int64)) > 0), i
+        c, d = orc.offsets[k], orc.offsets[k + 1]
+        ids = orc.ids[c:d]
+        certain = ids[~orc.marginal[c:d]]
+        near = orc.near_ids[orc.near_offsets[k]:orc.near_offsets[k + 1]]
+        assert np.all(np.isin(certain, got)), i
+        assert np.all(np.isin(got, np.concatenate([ids, near]))), i
+        shared, gi, oi = np.intersect1d(got, ids, assume_unique=True, return_indices=True)
+        assert np.array_equal(f16_to_f64(g_crho[a + gi, :3].copy()), orc.colour[c + oi]), i
+        got_rho = f16_to_f64(g_crho[a + gi, 3].copy())
+        want = orc.rho[c + oi]
+        if np.isfinite(dp[k]) and dp[k] > 0:
+            assert np.all(np.abs(got_rho - want) <= 2.0 ** -11 * np.abs(want) + 1e-5), i
+        else:
+            assert np.isnan(got_rho).all(), i
+        members_checked += shared.size
+        extra += got.size - shared.size
+    return {"pixels": int(orc.pixels.size), "members_checked": members_checked, "near_miss_members_on_gpu": extra,
+            "marginal": int(orc.marginal.sum())}

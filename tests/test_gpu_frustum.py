@@ -71,23 +71,10 @@ def test_frustum_sets_match_oracle(case):
     torch.cuda.synchronize()
     sets.check()
     g_off, g_ids, g_crho = parity.gpu_sets_to_host(sets, 0, h * w)
-    unsure = _unsure(orc)
-    assert unsure.mean() < 0.2
     assert orc.offsets[-1] > 5 * h * w          # depth-agnostic sets: several samples per pixel
-    dp = dep[f].reshape(-1)
-    for i in np.flatnonzero(~unsure):
-        a, b = g_off[i], g_off[i + 1]
-        c, d = orc.offsets[i], orc.offsets[i + 1]
-        assert np.array_equal(g_ids[a:b], orc.ids[c:d]), i
-        got_col = parity.f16_to_f64(g_crho[a:b, :3].copy())
-        assert np.array_equal(got_col, orc.colour[c:d]), i
-        got_rho = parity.f16_to_f64(g_crho[a:b, 3].copy())
-        want = orc.rho[c:d]
-        if not (np.isfinite(dp[i]) and dp[i] > 0):
-            assert np.isnan(got_rho).all() and np.isnan(want).all(), i
-        else:
-            # binary16 rounding of a float32 value: half an ulp (2^-11 relative) + float32 error
-            assert np.all(np.abs(got_rho - want) <= 2.0 ** -11 * np.abs(want) + 1e-5), i
+    st = parity.compare_frustum(orc, g_off, g_ids, g_crho, dep[f].reshape(-1)[orc.pixels])
+    assert st["members_checked"] > 0.95 * orc.offsets[-1]
+    print(st)
 
 
 def test_frustum_sets_filter_like_the_oracle(case):

@@ -72,3 +72,27 @@ def test_a_pixel_list_gives_the_same_estimates():
         np.testing.assert_array_equal(a.reshape(-1)[pix], b.reshape(-1)[pix])
     others = np.setdiff1d(np.arange(h * w), pix)
     assert np.isnan(part[0].reshape(-1)[others]).all()
+
+
+def test_cost_intervals_collapse_to_the_costs_away_from_rounding_bands():
+    """Without a band every interval is the exact mean cost of estimate_depth; with a
+    band wider than half a pixel every projection may take both neighbours, so each
+    interval contains the nominal cost."""
+    rng = np.random.default_rng(4)
+    h, w = 12, 16
+    col = rng.random((3, h, w, 3))
+    cams = np.stack([np.eye(4)] * 3)
+    cams[0, 0, 3], cams[2, 0, 3] = -0.05, 0.07
+    hyp = np.array([1.0, 1.7, 2.5, 4.0])
+    pixels = np.arange(h * w)
+    depth, best = odepth.estimate_depth(col, cams, 20.0, 20.0, 7.5, 5.5, 1, 1, hyp, pixels=pixels)
+    lo, hi = odepth.cost_intervals(col, cams, 20.0, 20.0, 7.5, 5.5, 1, 1, hyp, pixels, rnd_band=0.0)
+    fin = np.isfinite(lo)
+    assert np.array_equal(lo[fin], hi[fin])
+    got_best = np.where(fin, lo, np.inf).min(axis=1)
+    ok = np.isfinite(best.reshape(-1))
+    assert np.allclose(got_best[ok], best.reshape(-1)[ok], rtol=0, atol=1e-12)
+    lo2, hi2 = odepth.cost_intervals(col, cams, 20.0, 20.0, 7.5, 5.5, 1, 1, hyp, pixels, rnd_band=0.6)
+    both = fin & np.isfinite(hi2) & (hi2 > 0)
+    assert both.any()
+    assert np.all(lo2[both] <= lo[both] + 1e-12) and np.all(hi2[both] >= hi[both] - 1e-12)
