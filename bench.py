@@ -77,32 +77,134 @@ def _measured_traffic(kernel: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def cpu_baseline(clip, wl, f: int, row_step: int) -> dict:
-    """The float64 oracle on every `row_step`-th row of output frame f (one process)."""
+def _host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_worker(args):
+    """One process of the CPU baseline: the float64 oracle's gather and depth-weighted
+    filter for a chunk of output pixels, reading the window planes from shared memory."""
+    shm_name, shapes, f, prm, fx, fy, cx, cy, window, sigma_d, pixels = args
     import numpy as np
+    from multiprocessing import shared_memory
     from oracle import filters as ofilters
     from oracle import gather as ogather
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        (cs, ds, ms) = shapes
+        col = np.ndarray(cs, dtype=np.float64, buffer=shm.buf, offset=0)
+        dep = np.ndarray(ds, dtype=np.float64, buffer=shm.buf, offset=col.nbytes)
+        cams = np.ndarray(ms, dtype=np.float64, buffer=shm.buf, offset=col.nbytes + dep.nbytes)
+        t0 = time.perf_counter()
+        sets = ogather.gather_frame(col, dep, cams, fx, fy, cx, cy, f, ogather.GatherParams(**prm), pixels=pixels)
+        out = ofilters.filter_sets(sets, col[f], window, sigma_d)
+        dt = time.perf_counter() - t0
+        seg = np.repeat(np.arange(sets.pixels.size), np.diff(sets.offsets))
+        band = np.zeros(sets.pixels.size, bool)
+        band[seg[sets.marginal]] = True
+        band |= np.diff(sets.maybe_offsets) > 0
+        certain = sets.ids[~sets.marginal]
+        certain_off = np.concatenate([[0], np.cumsum(np.bincount(seg[~sets.marginal], minlength=sets.pixels.size))])
+        return {"pixels": pixels, "offsets": sets.offsets, "ids": sets.ids, "certain_off": certain_off,
+                "certain": certain, "maybe_off": sets.maybe_offsets, "maybe": sets.maybe_ids, "band": band,
+                "out": out, "seconds": dt, "samples": int(sets.ids.size)}
+    finally:
+        shm.close()
+
+
+def cpu_baseline(sg, clip, staged, wl, params, fparams, f: int, row_step: int, workers: int):
+    """The float64 oracle on every `row_step`-th row of output frame f, one process
+    per host core (spawned, reading the window planes from one shared-memory copy),
+    and its comparison with the GPU's sets and filtered colours of the same pixels.
+    Returns (cpu_baseline, oracle_error)."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from multiprocessing import get_context, shared_memory
     from oracle import staging as ostaging
 
-    lo, hi = max(0, f - wl.window), min(clip.n_frames - 1, f + wl.window)
+    # GPU side: the frame through the timed path's entry points, exact arena
+    sets = sg.scene_gather(staged, f, f + 1, params)
+    out = sg.scene_filter(staged, sets, fparams)
+    torch.cuda.synchronize()
+    sets.check()
     h, w = clip.height, clip.width
-    # only the window's frames, re-indexed from lo (ids are relative to f, so unchanged)
-    col = ostaging.colour_q(clip.rgb_u8[lo:hi + 1].cpu().numpy())
-    dep = ostaging.depth_q(clip.depth[lo:hi + 1].cpu().numpy())
-    cams = clip.cam_to_world[lo:hi + 1].cpu().numpy()
-    rows = np.arange(0, h, row_step)
-    pix = (rows[:, None] * w + np.arange(w)[None, :]).ravel()
-    prm = ogather.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
-    t0 = time.perf_counter()
-    sets = ogather.gather_frame(col, dep, cams, clip.fx, clip.fy, clip.cx, clip.cy, f - lo, prm, pixels=pix)
-    ofilters.filter_sets(sets, col[f - lo], wl.window, wl.sigma_d)
-    dt = time.perf_counter() - t0
-    s = int(sets.ids.size)
-    return {"value": s / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"frame {f}, every {row_step}th row ({pix.size} output pixels, {s} samples), "
-                      f"gather + depth-weighted filter, float64 numpy, {dt:.1f} s",
-            "seconds": dt, "host": platform.processor() or platform.machine(),
-            "host_cores": os.cpu_count()}
+    g_off = sets.offsets.cpu().numpy()
+    g_ids = sets.ids.cpu().numpy().view(np.uint32)
+    g_out = out[0].reshape(-1, 3).cpu().numpy().astype(np.float64)
+    del sets, out
+    lo, hi = max(0, f - wl.window), min(clip.n_frames - 1, f + wl.window)
+    n_win = hi - lo + 1
+    cshape, dshape, mshape = (n_win, h, w, 3), (n_win, h, w), (n_win, 4, 4)
+    nbytes = 8 * (int(np.prod(cshape)) + int(np.prod(dshape)) + int(np.prod(mshape)))
+    shm = shared_memory.SharedMemory(create=True, size=nbytes)
+    try:
+        col = np.ndarray(cshape, dtype=np.float64, buffer=shm.buf, offset=0)
+        dep = np.ndarray(dshape, dtype=np.float64, buffer=shm.buf, offset=col.nbytes)
+        cams = np.ndarray(mshape, dtype=np.float64, buffer=shm.buf, offset=col.nbytes + dep.nbytes)
+        for k in range(n_win):   # frame by frame: the staging conversion of the oracle
+            col[k] = ostaging.colour_q(clip.rgb_u8[lo + k].cpu().numpy())
+            dep[k] = ostaging.depth_q(clip.depth[lo + k].cpu().numpy())
+        cams[:] = clip.cam_to_world[lo:hi + 1].cpu().numpy()
+        rows = np.arange(0, h, row_step)
+        pix = (rows[:, None] * w + np.arange(w)[None, :]).ravel()
+        chunks = np.array_split(pix, 4 * workers)
+        prm = {"window": wl.window, "radius": wl.radius, "tol": wl.tol, "z_near": wl.z_near}
+        jobs = [(shm.name, (cshape, dshape, mshape), f - lo, prm, clip.fx, clip.fy, clip.cx, clip.cy, wl.window,
+                 wl.sigma_d, c) for c in chunks]
+        with ProcessPoolExecutor(max_workers=workers, mp_context=get_context("spawn")) as ex:
+            list(ex.map(_oracle_worker, jobs[:workers]))         # start-up and imports, untimed
+            t0 = time.perf_counter()
+            parts = list(ex.map(_oracle_worker, jobs))
+            dt = time.perf_counter() - t0
+    finally:
+        shm.close()
+        shm.unlink()
+    samples = sum(p["samples"] for p in parts)
+    cpu_s = sum(p["seconds"] for p in parts)
+    # oracle error of the GPU path on these pixels: membership (certain members
+    # subset of the GPU's set subset of members + float32-band candidates) and colour
+    bad_sets, checked, band_px, max_err, sum_err, n_err = 0, 0, 0, 0.0, 0.0, 0
+    for p in parts:
+        for k, q in enumerate(p["pixels"]):
+            got = set(g_ids[g_off[q]:g_off[q + 1]].tolist())
+            certain = set(p["certain"][p["certain_off"][k]:p["certain_off"][k + 1]].tolist())
+            allowed = set(p["ids"][p["offsets"][k]:p["offsets"][k + 1]].tolist()) | \
+                set(p["maybe"][p["maybe_off"][k]:p["maybe_off"][k + 1]].tolist())
+            checked += 1
+            if not (certain <= got <= allowed):
+                bad_sets += 1
+        e = np.abs(g_out[p["pixels"]] - p["out"]).max(axis=1)[~p["band"]]
+        band_px += int(p["band"].sum())
+        if e.size:
+            max_err = max(max_err, float(e.max()))
+            sum_err += float(e.sum())
+            n_err += e.size
+    base = {"value": samples / dt, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"frame {f}, every {row_step}th row ({pix.size} output pixels, {samples} samples), "
+                      f"gather + depth-weighted filter, float64 numpy, {workers} processes, {dt:.1f} s wall, "
+                      f"{cpu_s:.1f} s of process time",
+            "seconds": dt, "host": _host_cpu_model(), "host_cores": os.cpu_count(),
+            "samples_per_s_per_core": samples / cpu_s}
+    err = {"frame": f, "pixels": int(pix.size), "sets_outside_bands_differing": bad_sets, "sets_checked": checked,
+           "pixels_with_band_cases": band_px, "colour_max_abs_err": max_err,
+           "colour_mean_abs_err": sum_err / max(n_err, 1), "colour_tolerance": 1e-3,
+           "reference": "float64 oracle on the same binary16 planes (membership bands as the parity tests)"}
+    return base, err
+
+
+PAPER_REFERENCE = {
+    "value": 3.4, "unit": "s per output frame", "application": "denoising", "hardware":
+    "NVIDIA GeForce GTX 980 + Intel i7 3.2 GHz (Python with CUDA bindings)",
+    "workload": "real 720p hand-held video, about 500 samples per set", "source": "Tab. time (Sec. 6)",
+    "derived_samples_per_s": 1280 * 720 * 500 / 3.4,
+    "note": "context only: other hardware, real video, paper's own parameters"}
 
 
 MLP_FLOP_PER_SAMPLE = 2 * (8 * 64 + 64 * 64 + 64)   # 8 -> 64 -> 64 -> 1, multiply-adds x 2
@@ -196,6 +298,18 @@ def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
     ms_plain = timed(lambda: sg.scene_filter(staged, sets, fparams, out=out), reps)
     ms_deblur = timed(lambda: sg.scene_filter_frames(staged, sets, deblur, bj, out=out), reps)
     ms_inpaint = timed(lambda: sg.scene_inpaint(staged, sets, mask, 55.0 / 255.0, 2, out=out), reps)
+    ms_semi = timed(lambda: sg.scene_semi_transparent(staged, sets, mask, 80.0 / 255.0, 80.0 / 255.0, 2, out=out),
+                    reps)
+    # Eq. 4 with its scene-space term: the paper's sigma_xyz of 10 units of a scene scaled so
+    # that 90 % of its points lie in a 10^3 cube is that cube's side in metres here
+    side = scene_side_m(clip, staged)
+    gp = sg.GatherParams(window=wl.window, radius=wl.radius, tol=wl.tol, z_near=wl.z_near)
+    ws = sg.alloc_workspace(staged, f, f + 1, gp)
+    denoise7 = sg.FilterParams(sigma_d=math.inf, sigma_c=40.0 / 255.0, sigma_t=6.0)
+    deblur7 = sg.FilterParams(sigma_d=math.inf, sigma_c=200.0 / 255.0, sigma_t=20.0)
+    ms_xyz = timed(lambda: sg.scene_filter_xyz(staged, sets, gp, denoise7, side, ws=ws, out=out), reps)
+    ms_xyz_deblur = timed(lambda: sg.scene_filter_xyz(staged, sets, gp, deblur7, side, frame_w=bj, ws=ws, out=out),
+                          reps)
     alg = 12 * n_rec + 28 * h * w
     res = {"output_frame": f, "records": n_rec, "frames": n,
            "frame_sharpness_ms_per_clip": ms_sharp, "box_mask_ms_per_clip": ms_box,
@@ -203,11 +317,33 @@ def filters_leg(sg, clip, staged, wl, arena, f, fparams, reps: int) -> dict:
            "deblur_roofline": {"bound": "hbm", "achieved": alg / (ms_deblur / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": alg / (ms_deblur / 1e3) / 1e9 / HBM_PEAK_GBS,
                                "alg_bytes_per_launch": alg},
-           "inpaint_ms": ms_inpaint, "inpaint_masked_fraction": float(mask[f].float().mean().item())}
+           "inpaint_ms": ms_inpaint, "inpaint_masked_fraction": float(mask[f].float().mean().item()),
+           "semi_transparent_ms": ms_semi, "scene_side_m": side,
+           "eq4_scene_space_denoise_ms": ms_xyz, "eq5_scene_space_deblur_ms": ms_xyz_deblur}
     log(f"filters: B(J) {ms_sharp:.3f} ms/clip, box mask {ms_box:.3f} ms/clip, plain {ms_plain:.3f}, "
         f"deblur {ms_deblur:.3f}, "
-        f"inpaint {ms_inpaint:.3f} ms/frame")
+        f"inpaint {ms_inpaint:.3f}, semi-transparent {ms_semi:.3f}, Eq. 4 with sigma_xyz {ms_xyz:.3f}, "
+        f"Eq. 5 with sigma_xyz {ms_xyz_deblur:.3f} ms/frame")
     return res
+
+
+def scene_side_m(clip, staged) -> float:
+    """Side in metres of the cube that holds 90 % of the scene (the largest per-axis
+    5 %-95 % range of the scene points of every 10th frame, from the stored depths)."""
+    import torch
+    h, w = clip.height, clip.width
+    d = staged.depth_image()[::10].to(torch.float64)
+    ys, xs = torch.meshgrid(torch.arange(h, dtype=torch.float64, device=d.device),
+                            torch.arange(w, dtype=torch.float64, device=d.device), indexing="ij")
+    cams = staged.cam_to_world[::10].to(d.device)
+    pts = []
+    for k in range(d.shape[0]):
+        dk = d[k]
+        ok = torch.isfinite(dk) & (dk > 0)
+        xc = torch.stack([dk * (xs - clip.cx) / clip.fx, dk * (ys - clip.cy) / clip.fy, dk], -1)[ok]
+        pts.append(xc[::97] @ cams[k, :3, :3].T + cams[k, :3, 3])
+    p = torch.cat(pts)
+    return float(max(torch.quantile(p[:, k], 0.95) - torch.quantile(p[:, k], 0.05) for k in range(3)))
 
 
 def frustum_leg(sg, clip, staged, f, window: int, reps: int) -> dict:
@@ -514,22 +650,26 @@ def main() -> int:
     ap.add_argument("--chunk-rays", type=int, default=1 << 20,
                     help="rays per generation launch (larger = fewer launches, e.g. under a counter profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-row-step", type=int, default=16)
+    ap.add_argument("--cpu-row-step", type=int, default=4,
+                    help="the CPU baseline runs the oracle on every n-th row of one output frame")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes (0: one per host core available, at most 16)")
     ap.add_argument("--workload", choices=("full", "batched"), default="full",
                     help="full: the 1080p +-50 headline workload; batched: 32 uneven clips per step")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weight filter leg")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-fused", action="store_true", help="skip the fused gather + filter leg")
-    ap.add_argument("--depth-hypotheses", type=int, default=0,
+    ap.add_argument("--depth-hypotheses", type=int, default=32,
                     help="also time the data-term depth estimate with this many hypotheses (0: skip)")
-    ap.add_argument("--frustum-window", type=int, default=0,
+    ap.add_argument("--frustum-window", type=int, default=10,
                     help="also time the depth-agnostic frustum gather with this window (0: skip)")
     ap.add_argument("--no-filters", action="store_true",
                     help="skip the deblurring / inpainting filters leg")
     ap.add_argument("--no-curve", action="store_true",
                     help="learned leg at the workload's window only (no smaller-window curve)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="after timing, run one plain 1 GiB elementwise copy (counter calibration)")
+                    help="after timing, run one plain 1 GiB elementwise copy and one gather of 2^24 random "
+                         "64-byte rows (counter calibration for streaming and scattered reads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -683,10 +823,21 @@ def main() -> int:
         y = torch.empty_like(x)
         torch.neg(x, out=y)
         torch.cuda.synchronize()
-        del x, y
+        # scattered reads: 2^24 rows of 64 B (1 GiB) read in a random order, written in order
+        rows = x.view(1 << 24, 16)
+        idx = torch.randperm(1 << 24, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+        torch.cuda.synchronize()
+        torch.index_select(rows, 0, idx, out=y.view(1 << 24, 16))
+        torch.cuda.synchronize()
+        del x, y, rows, idx
+    res["paper_reference"] = PAPER_REFERENCE
     if not args.no_cpu_baseline:
-        log("timing the float64 oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline(clip, wl, timed[0], args.cpu_row_step)
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        log(f"timing the float64 oracle on a bounded sample ({workers} processes) and comparing it with the GPU")
+        res["cpu_baseline"], res["oracle_error"] = cpu_baseline(sg, clip, staged, wl, params, fparams, timed[0],
+                                                                args.cpu_row_step, workers)
+        log(f"oracle: {res['cpu_baseline']['value']:.3g} samples/s on {workers} processes; "
+            f"error {res['oracle_error']}")
     print(json.dumps(res), flush=True)
     return 0
 

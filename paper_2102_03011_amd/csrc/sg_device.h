@@ -60,9 +60,11 @@ __host__ __device__ __forceinline__ int stored_pitch(int width) {
 }
 __host__ __device__ __forceinline__ int stored_rows(int height) { return height + 2 * SG_APRON; }
 
-// Stored-plane index of image pixel (x, y).
-__device__ __forceinline__ size_t padded_index(int x, int y, int pw) {
-  return static_cast<size_t>(y + SG_APRON) * pw + (x + SG_APRON);
+// Stored-plane index of image pixel (x, y), for x, y at most SG_APRON outside the
+// image. A plane has fewer than 2^31 entries and both factors are below 2^24
+// (W * H <= 2^22), so the 24-bit multiply is exact and the index is 32-bit.
+__device__ __forceinline__ uint32_t padded_index(int x, int y, int pw) {
+  return __umul24(static_cast<uint32_t>(y + SG_APRON), static_cast<uint32_t>(pw)) + static_cast<uint32_t>(x + SG_APRON);
 }
 
 }  // namespace sg

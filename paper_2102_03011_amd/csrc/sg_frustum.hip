@@ -10,7 +10,8 @@
 //              b(q) = round(p'(q)) on a grid extended by the bucket radius rb
 //              (a member has |p - b(q)|_1 < l/2 + 1, so rb = ceil(l/2 + 1) - 1);
 //   bucket  -- counting sort of the kept q by b(q) (count, scan, atomic fill: the
-//              order inside a bucket is arbitrary);
+//              order inside a bucket is arbitrary), each filed with its carried
+//              position, so a row of buckets is one contiguous range of records;
 //   count / scatter -- each output pixel reads the buckets within L1 distance rb,
 //              applies Eq. 2, and (scatter) orders its members of J by q in a small
 //              per-thread sort, so the records come out in canonical order whatever
@@ -70,7 +71,7 @@ FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_param
   l.bfill = at;
   at += align_up(static_cast<size_t>(l.n_j) * l.n_buckets * sizeof(int32_t));
   l.items = at;
-  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(int32_t));
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Carried));
   l.partial = at;
   at += align_up(static_cast<size_t>((scan_a > scan_b ? scan_a : scan_b) + 1) * sizeof(int64_t));
   l.total = at;
@@ -159,11 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __re
   carry[static_cast<int64_t>(jn) * n_pix + q] = Carried{px, py, z, b};
 }
 
-// grid (pixels / 256, window frames): file every kept q in its bucket
+// grid (pixels / 256, window frames): file every kept q in its bucket, as its carried
+// position with q in place of the bucket index, so the count and scatter passes read
+// each bucket's candidates contiguously
 __global__ __launch_bounds__(kThreads) void k_frustum_bucket(const Carried* __restrict__ carry,
                                                              const int64_t* __restrict__ boff,
                                                              int32_t* __restrict__ bfill, int64_t n_pix,
-                                                             int64_t n_buckets, int32_t* __restrict__ items) {
+                                                             int64_t n_buckets, Carried* __restrict__ filed) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (q >= n_pix) return;
   const int jn = blockIdx.y;
@@ -172,36 +175,38 @@ __global__ __launch_bounds__(kThreads) void k_frustum_bucket(const Carried* __re
   if (b < 0) return;
   const int64_t e = static_cast<int64_t>(jn) * n_buckets + b;
   const int slot = atomicAdd(bfill + e, 1);
-  to_global(items)[to_global(boff)[e] + slot] = static_cast<int32_t>(q);
+  filed[to_global(boff)[e] + slot] = Carried{c.x, c.y, c.z, static_cast<int32_t>(q)};
 }
 
 // Calls fn(q, carried) for every q filed within L1 distance rb of output pixel
 // (x, y) in window frame jn and passing Eq. 2.
 template <typename Fn>
-__device__ __forceinline__ void for_members(const Carried* __restrict__ carry, const int32_t* __restrict__ items,
-                                            const int64_t* __restrict__ boff, int width, int rb, float half,
-                                            int64_t n_pix, int64_t n_buckets, int jn, int x, int y, Fn&& fn) {
-  const Carried* cj = carry + static_cast<int64_t>(jn) * n_pix;  // (struct copies take generic pointers)
+__device__ __forceinline__ void for_members(const Carried* __restrict__ filed_, const int64_t* __restrict__ boff,
+                                            int width, int rb, float half, int64_t n_buckets, int jn, int x, int y,
+                                            Fn&& fn) {
+  gp<const uint64_t> filed = reinterpret_cast<gp<const uint64_t>>(to_global(filed_));
   gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-  gp<const int32_t> it = to_global(items);
   const int ew = width + 2 * rb;
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
   for (int dy = -rb; dy <= rb; ++dy) {
     const int span = rb - (dy < 0 ? -dy : dy);
-    for (int dx = -span; dx <= span; ++dx) {
-      const int64_t b = static_cast<int64_t>(y + dy + rb) * ew + (x + dx + rb);
-      const int64_t e = bj[b + 1];
-      for (int64_t k = bj[b]; k < e; ++k) {
-        const int32_t q = it[k];
-        const Carried c = cj[q];
-        if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(q, c);
-      }
+    const int64_t row = static_cast<int64_t>(y + dy + rb) * ew + (x + rb);
+    // the buckets of this row are adjacent: one contiguous range of filed records
+    const int64_t k0 = bj[row - span], k1 = bj[row + span + 1];
+    for (int64_t k = k0; k < k1; ++k) {
+      // 16-byte record as two 8-byte words (struct copies take generic pointers)
+      const uint64_t lo = filed[2 * k], hi = filed[2 * k + 1];
+      Carried c;
+      c.x = __uint_as_float(static_cast<uint32_t>(lo));
+      c.y = __uint_as_float(static_cast<uint32_t>(lo >> 32));
+      c.z = __uint_as_float(static_cast<uint32_t>(hi));
+      c.b = static_cast<int32_t>(hi >> 32);
+      if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(c.b, c);
     }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __restrict__ carry,
-                                                            const int32_t* __restrict__ items,
+__global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __restrict__ filed,
                                                             const int64_t* __restrict__ boff, int width, int n_j,
                                                             int rb, float half, int64_t n_pix, int64_t n_buckets,
                                                             int64_t* __restrict__ counts) {
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __res
   const int y = static_cast<int>(p / width), x = static_cast<int>(p - static_cast<int64_t>(y) * width);
   int64_t n = 0;
   for (int jn = 0; jn < n_j; ++jn)
-    for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
+    for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
   to_global(counts)[p] = n;
 }
 
@@ -224,8 +229,8 @@ constexpr int kSortSlots = 24;
 // order. A pair with more than kSortSlots members (dense occluders) emits by repeated
 // minimum instead, one pass over the buckets per member.
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
-    const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_, const Carried* __restrict__ carry,
-    const int32_t* __restrict__ items, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
+    const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_,
+    const Carried* __restrict__ filed, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
     int n_j, int rb, float half, int64_t n_pix, int64_t n_buckets, const int64_t* __restrict__ offsets_,
     uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity, uint32_t* __restrict__ status_) {
   __shared__ int32_t s_q[kSortSlots][kThreads];
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     const int j = jlo + jn;
     const uint32_t id_j = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
     int n = 0;
-    for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+    for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
       if (n < kSortSlots) {
         s_q[n][t] = q;
         s_z[n][t] = c.z;
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       for (;;) {  // the smallest member above the last emitted
         int32_t best = INT_MAX;
         float best_z = 0.0f;
-        for_members(carry, items, boff, width, rb, half, n_pix, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+        for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
           if (q > last && q < best) {
             best = q;
             best_z = c.z;
@@ -326,7 +331,7 @@ struct FrustumCall {
   Carried* carry;
   int64_t* boff;
   int32_t* bfill;
-  int32_t* items;
+  Carried* filed;
   int64_t* partial;
 };
 
@@ -344,7 +349,7 @@ sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_param
   c->carry = reinterpret_cast<Carried*>(base + c->l.carry);
   c->boff = reinterpret_cast<int64_t*>(base + c->l.boff);
   c->bfill = reinterpret_cast<int32_t*>(base + c->l.bfill);
-  c->items = reinterpret_cast<int32_t*>(base + c->l.items);
+  c->filed = reinterpret_cast<Carried*>(base + c->l.items);
   c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
   return SG_OK;
 }
@@ -391,8 +396,8 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
                      c.carry, reinterpret_cast<unsigned long long*>(c.boff));
   if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
   hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st, c.carry, c.boff, c.bfill,
-                     l.n_pix, l.n_buckets, c.items);
-  hipLaunchKernelGGL(sg::k_frustum_count, per_pixel, dim3(sg::kThreads), 0, st, c.carry, c.items, c.boff,
+                     l.n_pix, l.n_buckets, c.filed);
+  hipLaunchKernelGGL(sg::k_frustum_count, per_pixel, dim3(sg::kThreads), 0, st, c.filed, c.boff,
                      clip->width, l.n_j, l.rb, half, l.n_pix, l.n_buckets, sets->offsets + 1);
   return hip_status(sg::launch_scan(sets->offsets, l.n_pix, c.partial, st));
 }
@@ -405,7 +410,7 @@ sg_status scene_frustum_scatter(const sg_clip* clip, int32_t f, const sg_frustum
   const sg::FrustumLayout& l = c.l;
   hipLaunchKernelGGL(sg::k_frustum_scatter, dim3(static_cast<unsigned>((l.n_pix + sg::kThreads - 1) / sg::kThreads)),
                      dim3(sg::kThreads), 0, static_cast<hipStream_t>(stream),
-                     reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.carry, c.items, c.boff, clip->width,
+                     reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.filed, c.boff, clip->width,
                      clip->height, f, params->window, l.jlo, l.n_j, l.rb, 0.5f * params->l, l.n_pix, l.n_buckets,
                      sets->offsets, sets->ids, reinterpret_cast<uint2*>(sets->crho), sets->capacity, sets->status);
   return hip_status(hipGetLastError());

@@ -40,13 +40,15 @@ struct RowLoad {
   static constexpr int kWords = (2 * R + 1 + 3) / 4;
 };
 
+// The block around plane entry `at` (32-bit offsets from the frame's plane, whose
+// address is the same for the whole wave).
 template <int R>
-__device__ __forceinline__ void load_block_depths(gp<const uint16_t> centre, int pw,
+__device__ __forceinline__ void load_block_depths(gp<const uint16_t> plane, uint32_t at, int pw,
                                                   uint32_t (&d)[2 * R + 1][2 * R + 1]) {
   constexpr int kW = RowLoad<R>::kWords;
 #pragma unroll
   for (int dy = -R; dy <= R; ++dy) {
-    gp<const uint16_t> rowp = centre + dy * pw - R;
+    gp<const uint16_t> rowp = plane + (at + static_cast<uint32_t>(dy * pw - R));
     uint64_t w[kW];
 #pragma unroll
     for (int c = 0; c < kW; ++c) w[c] = *reinterpret_cast<gp<const RowWord>>(rowp + 4 * c);
@@ -255,7 +257,7 @@ __device__ __forceinline__ int count_pixel(gp<const uint16_t> depth, gp<const fl
       if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p))
         continue;
       uint32_t d[2 * R + 1][2 * R + 1];
-      load_block_depths<R>(depth + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw), pw, d);
+      load_block_depths<R>(depth + static_cast<size_t>(j) * pplane, padded_index(p.iu, p.iv, pw), pw, d);
 #pragma unroll
       for (int dy = 0; dy <= 2 * R; ++dy)
 #pragma unroll
@@ -290,9 +292,10 @@ __device__ __forceinline__ int count_pixel_k(gp<const uint16_t> depth, gp<const 
         const int j = j0 + k;
         ok[k] = j <= jhi &&
                 project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p[k]);
-        const size_t at = ok[k] ? static_cast<size_t>(j) * pplane + padded_index(p[k].iu, p[k].iv, pw)
-                                : static_cast<size_t>(jlo) * pplane + padded_index(0, 0, pw);
-        load_block_depths<R>(depth + at, pw, d[k]);
+        // a frame past the window or a failed projection reads a valid block of frame jlo
+        const size_t plane = static_cast<size_t>(ok[k] ? j : jlo) * pplane;
+        const uint32_t at = ok[k] ? padded_index(p[k].iu, p[k].iv, pw) : padded_index(0, 0, pw);
+        load_block_depths<R>(depth + plane, at, pw, d[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -464,11 +467,12 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
     Mask mask = 0;
     int kept = 0;
     if (active && project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) {
-      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
+      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane;  // frame J's plane (uniform)
+      const uint32_t at = padded_index(p.iu, p.iv, pw);
 #pragma unroll
       for (int dy = 0; dy < kSide; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (dy - R) * pw + (dx - R));
+        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (at + static_cast<uint32_t>((dy - R) * pw + (dx - R))));
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k)
         mask |= static_cast<Mask>(accept16(px[k / kSide][k % kSide].y >> 16, p) ? 1 : 0) << k;
@@ -611,12 +615,13 @@ __global__ __launch_bounds__(256) void k_gather_filter(const uint2* __restrict__
     for (int j = jlo; j <= jhi; ++j) {
       Projected p;
       if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) continue;
-      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane + padded_index(p.iu, p.iv, pw);
+      gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane;  // frame J's plane (uniform)
+      const uint32_t at = padded_index(p.iu, p.iv, pw);
       uint2 px[kSide][kSide];
 #pragma unroll
       for (int dy = 0; dy < kSide; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (dy - R) * pw + (dx - R));
+        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (at + static_cast<uint32_t>((dy - R) * pw + (dx - R))));
       const float dj = static_cast<float>(j - f);
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k) {

@@ -66,3 +66,39 @@ def test_frustum_params_reach_the_library_checks(sg):
         with pytest.raises(sg.SceneGatherError):
             sg.scene_frustum_workspace_size(clip, 1, bad)
     assert sg.scene_frustum_workspace_size(clip, 1, sg.FrustumParams(window=1)) > 0
+
+
+def test_bench_oracle_worker_reads_shared_planes_and_matches_the_oracle():
+    """The CPU baseline's worker (one process per core in the benchmark) reads the
+    window planes from shared memory and returns the oracle's own sets and colours."""
+    import numpy as np
+    from multiprocessing import shared_memory
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle import filters as ofilters
+    from oracle import gather as ogather
+    from oracle import staging as ostaging
+    from scenegen import configs, generate
+    wl = configs.tiny(seed=2, width=24, height=16, n_frames=5, window=2)
+    clip = generate(wl.spec)
+    col = ostaging.colour_q(clip.rgb_u8.numpy())
+    dep = ostaging.depth_q(clip.depth.numpy())
+    cams = clip.cam_to_world.numpy()
+    shm = shared_memory.SharedMemory(create=True, size=col.nbytes + dep.nbytes + cams.nbytes)
+    try:
+        buf = np.ndarray(col.size + dep.size + cams.size, dtype=np.float64, buffer=shm.buf)
+        buf[:] = np.concatenate([col.ravel(), dep.ravel(), cams.ravel()])
+        pix = np.arange(0, 24 * 16, 3)
+        prm = {"window": 2, "radius": 1, "tol": wl.tol, "z_near": wl.z_near}
+        got = bench._oracle_worker((shm.name, (col.shape, dep.shape, cams.shape), 2, prm, clip.fx, clip.fy,
+                                    clip.cx, clip.cy, 2, wl.sigma_d, pix))
+    finally:
+        shm.close()
+        shm.unlink()
+    want = ogather.gather_frame(col, dep, cams, clip.fx, clip.fy, clip.cx, clip.cy, 2,
+                                ogather.GatherParams(**prm), pixels=pix)
+    assert np.array_equal(got["ids"], want.ids) and np.array_equal(got["offsets"], want.offsets)
+    assert np.array_equal(got["out"], ofilters.filter_sets(want, col[2], 2, wl.sigma_d))
+    assert got["samples"] == want.ids.size > 0
+    # certain members: the oracle's members outside its float32 bands
+    assert got["certain"].size == int((~want.marginal).sum())
