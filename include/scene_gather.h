@@ -229,8 +229,10 @@ sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1,
  *   6 |grad D^J|(q) / D^J(q) (central differences, one-sided where a neighbour has
  *   no valid depth); 7 log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)); 8 (J - f) / w.
  * GELU is the exact form GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2 (Phi the
- * standard normal CDF; not the tanh approximation); the kernels evaluate erf with
- * Abramowitz-Stegun 7.1.28 (|error| <= 3e-7). Matrix operands (standardised
+ * standard normal CDF; not the tanh approximation); the learned filter evaluates
+ * erf with Abramowitz-Stegun 7.1.27 (|error| <= 5e-4; it moves the filtered colour
+ * by at most 2.3e-4 in measurements, inside the 1e-3 contract), the training step
+ * with 7.1.28 (|error| <= 3e-7). Matrix operands (standardised
  * features, hidden activations) are bfloat16 hi/lo pairs, products accumulate in
  * float32 on the matrix cores.
  *
