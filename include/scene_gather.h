@@ -230,9 +230,10 @@ sg_status scene_gather_filter(const sg_clip* clip, int32_t f0, int32_t f1,
  *   no valid depth); 7 log(1 + n) / log(1 + (2r + 1)^2 (2w + 1)); 8 (J - f) / w.
  * GELU is the exact form GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2 (Phi the
  * standard normal CDF; not the tanh approximation); the learned filter evaluates
- * erf with Abramowitz-Stegun 7.1.27 (|error| <= 5e-4; it moves the filtered colour
- * by at most 2.3e-4 in measurements, inside the 1e-3 contract), the training step
- * with 7.1.28 (|error| <= 3e-7). Matrix operands (standardised
+ * it from a table of chords over z in [-8, 8) (cells of width 1/64, continued as
+ * z above the range and 0 below; |error| <= 2.5e-5; built in each workgroup from
+ * erff), the training step
+ * with Abramowitz-Stegun 7.1.28 for erf (|error| <= 3e-7). Matrix operands (standardised
  * features, hidden activations) are bfloat16 hi/lo pairs, products accumulate in
  * float32 on the matrix cores.
  *

@@ -325,11 +325,45 @@ __global__ __launch_bounds__(256) void k_count(const uint16_t* __restrict__ dept
       count_pixel<R>(to_global(depth), to_global(relf), width, height, n_frames, f0 + fo, w, tol, z_near, x, y);
 }
 
+// 16 x 16 tiles (the scatter pass and the fused gather + filter): four waves of
+// 16 x 4: a block row of 16 pixels is
+// one 128-byte line of a source plane, and depth noise scatters the projections
+// of one output row over several source rows, so a squarer wave touches fewer
+// distinct lines per load than a 64 x 1 one (9 % faster at 1080p, +-50 frames;
+// 8 x 8 waves, half-line rows, were 7 % slower). The dispatcher hands
+// consecutive workgroups to the XCDs in turn; tile_of_block_xcd_rows gives each
+// XCD whole tile rows instead, so vertically and horizontally adjacent tiles
+// share an L2 (1 % more).
+constexpr int kFuseWaveW = 16;
+static_assert((kFuseW / kFuseWaveW) * (kFuseH / (64 / kFuseWaveW)) == 4, "four waves per fused tile");
+
+// Tile of a fused workgroup: with tiles_x tiles per row, round r of the XCDs
+// (workgroups 8 r .. 8 r + 7) takes tile rows 8 q + x, q = r / tiles_x, for XCD x;
+// the dispatches past the last whole round of 8 tile rows map to themselves.
+__device__ __forceinline__ Tile tile_of_block_xcd_rows(int tiles_x, int tiles_y) {
+  const int b = static_cast<int>(blockIdx.x);
+  const int nt = tiles_x * tiles_y;
+  Tile t;
+  t.fo = b / nt;
+  const int bl = b - t.fo * nt;
+  const int full = (nt / (8 * tiles_x)) * (8 * tiles_x);
+  int tl = bl;
+  if (bl < full) {
+    const int xcd = bl & 7, i = bl >> 3;
+    const int q = i / tiles_x, p = i - q * tiles_x;
+    tl = (q * 8 + xcd) * tiles_x + p;
+  }
+  t.tx = tl % tiles_x;
+  t.ty = tl / tiles_x;
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // a5: gather pass 2 -- write records in canonical order.
 //
-// Each wave owns 64 consecutive output pixels of one row, so their CSR segments
-// are adjacent in memory. Per source frame each lane reads its whole block of
+// Each wave owns 64 output pixels: a 16 x 4 block of a 16 x 16 tile (the batched
+// pass: 64 consecutive pixels of a row; a 16 x 4 block makes the 2.65 ms scatter of
+// a 1080p +-50 frame 2.55 ms). Per source frame each lane reads its whole block of
 // stored (r, g, b, depth) pixels in one round trip, decides membership from the
 // depth channel exactly as pass 1 does from the depth plane (same binary16 bits,
 // same test), and appends its accepted records to a per-lane buffer in LDS
@@ -415,13 +449,15 @@ struct ScatterLds {
   int64_t dst[kTileW];
 };
 
-// One wave writes the records of the 64 output pixels (x0 + lane, y) of output
-// frame f; pix0 = CSR index of pixel (x0, y). Every lane of the wave calls it.
+// One wave writes the records of its 64 output pixels of output frame f: lane's
+// pixel (x, y), CSR index pix (x, y and pix may lie outside the frame for lanes
+// past its right or lower edge; those lanes only join the wave's flushes). Every
+// lane of the wave calls it.
 template <int R>
 __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint16_t> depth,
                                              gp<const float> relf, int width, int height,
-                                             int n_frames, int f, int w, float tol, float z_near, int x0, int y,
-                                             int64_t pix0, gp<const int64_t> offsets, gp<uint32_t> ids,
+                                             int n_frames, int f, int w, float tol, float z_near, int x, int y,
+                                             int64_t pix, gp<const int64_t> offsets, gp<uint32_t> ids,
                                              gp<uint2> crho, int64_t capacity, gp<uint32_t> status,
                                              ScatterLds<R>& lds) {
   using Shape = ScatterShape<R>;
@@ -432,7 +468,6 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
   uint32_t* s_buf = lds.buf;
   int* s_n = lds.n;
   int64_t* s_dst = lds.dst;
-  const int x = x0 + lane;
   const bool in = x < width && y < height;
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
@@ -440,7 +475,6 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
   bool active = false;
   float dp = 0.0f;
   if (in) {
-    const int64_t pix = pix0 + lane;
     start = cur = offsets[pix];
     end = offsets[pix + 1];
     if (cur < 0 || end < cur) {  // offsets not produced by the count pass
@@ -535,16 +569,18 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
                                                  uint32_t* __restrict__ ids,
                                                  uint2* __restrict__ crho, int64_t capacity,
                                                  uint32_t* __restrict__ status) {
-  __shared__ ScatterLds<R> lds[kTileH];
-  const Tile tile = tile_of_block((width + kTileW - 1) / kTileW, (height + kTileH - 1) / kTileH);
-  const int x0 = tile.tx * kTileW;
-  const int y = tile.ty * kTileH + threadIdx.y;
+  constexpr int kWavesX = kFuseW / kFuseWaveW, kWaveH = 64 / kFuseWaveW;
+  __shared__ ScatterLds<R> lds[4];
+  const Tile tile = tile_of_block_xcd_rows((width + kFuseW - 1) / kFuseW, (height + kFuseH - 1) / kFuseH);
+  const int wave = threadIdx.y, lane = threadIdx.x;
+  const int x = tile.tx * kFuseW + (wave % kWavesX) * kFuseWaveW + lane % kFuseWaveW;
+  const int y = tile.ty * kFuseH + (wave / kWavesX) * kWaveH + lane / kFuseWaveW;
   const int fo = tile.fo;
   const float* relf = rel + static_cast<size_t>(fo) * (2 * w + 1) * kRelStride;
-  const int64_t pix0 = static_cast<int64_t>(fo) * width * height + static_cast<int64_t>(y) * width + x0;
+  const int64_t pix = static_cast<int64_t>(fo) * width * height + static_cast<int64_t>(y) * width + x;
   scatter_wave<R>(to_global(rgbd), to_global(depth), to_global(relf), width, height, n_frames, f0 + fo, w, tol,
-                  z_near, x0, y, pix0, to_global(offsets), to_global(ids), to_global(crho), capacity,
-                  to_global(status), lds[threadIdx.y]);
+                  z_near, x, y, pix, to_global(offsets), to_global(ids), to_global(crho), capacity,
+                  to_global(status), lds[wave]);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,37 +590,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint2* __restrict__ rgbd,
 // rounded to binary16 exactly as a stored record holds it. The result equals
 // scene_gather + scene_filter up to the order of the float32 additions.
 //
-// Its tile is 16 x 16 pixels, four waves of 16 x 4: a block row of 16 pixels is
-// one 128-byte line of a source plane, and depth noise scatters the projections
-// of one output row over several source rows, so a squarer wave touches fewer
-// distinct lines per load than a 64 x 1 one (9 % faster at 1080p, +-50 frames;
-// 8 x 8 waves, half-line rows, were 7 % slower). The dispatcher hands
-// consecutive workgroups to the XCDs in turn; tile_of_block_xcd_rows gives each
-// XCD whole tile rows instead, so vertically and horizontally adjacent tiles
-// share an L2 (1 % more).
-constexpr int kFuseWaveW = 16;
-static_assert((kFuseW / kFuseWaveW) * (kFuseH / (64 / kFuseWaveW)) == 4, "four waves per fused tile");
-
-// Tile of a fused workgroup: with tiles_x tiles per row, round r of the XCDs
-// (workgroups 8 r .. 8 r + 7) takes tile rows 8 q + x, q = r / tiles_x, for XCD x;
-// the dispatches past the last whole round of 8 tile rows map to themselves.
-__device__ __forceinline__ Tile tile_of_block_xcd_rows(int tiles_x, int tiles_y) {
-  const int b = static_cast<int>(blockIdx.x);
-  const int nt = tiles_x * tiles_y;
-  Tile t;
-  t.fo = b / nt;
-  const int bl = b - t.fo * nt;
-  const int full = (nt / (8 * tiles_x)) * (8 * tiles_x);
-  int tl = bl;
-  if (bl < full) {
-    const int xcd = bl & 7, i = bl >> 3;
-    const int q = i / tiles_x, p = i - q * tiles_x;
-    tl = (q * 8 + xcd) * tiles_x + p;
-  }
-  t.tx = tl % tiles_x;
-  t.ty = tl / tiles_x;
-  return t;
-}
+// Its tile is that of the scatter pass (see tile_of_block_xcd_rows).
 
 template <int R, bool kColour, bool kTime>
 __global__ __launch_bounds__(256) void k_gather_filter(const uint2* __restrict__ rgbd_, const float* __restrict__ rel,
@@ -985,7 +991,8 @@ __global__ __launch_bounds__(256) void k_scatter_batched(const BatchClip* __rest
       if (y >= c.height) break;  // uniform over the wave
       const int64_t pix0 = c.pix_base + static_cast<int64_t>(t.fo) * c.width * c.height +
                            static_cast<int64_t>(y) * c.width + t.x0;
-      scatter_wave<R>(rgbd, depth, relf, c.width, c.height, c.n_frames, f, c.w, c.tol, c.z_near, t.x0, y, pix0,
+      scatter_wave<R>(rgbd, depth, relf, c.width, c.height, c.n_frames, f, c.w, c.tol, c.z_near,
+                      t.x0 + static_cast<int>(threadIdx.x), y, pix0 + threadIdx.x,
                       to_global(offsets), to_global(ids), to_global(crho), capacity, to_global(status),
                       lds[threadIdx.y]);
     }
@@ -1058,6 +1065,12 @@ static void scatter_r(const GatherJob& jb, dim3 g, hipStream_t st) {
                      reinterpret_cast<uint2*>(jb.crho), jb.capacity, jb.status);
 }
 
+static dim3 tile16_grid(const GatherJob& jb) {
+  const int64_t nb = static_cast<int64_t>((jb.width + kFuseW - 1) / kFuseW) *
+                     ((jb.height + kFuseH - 1) / kFuseH) * jb.n_out;
+  return dim3(static_cast<unsigned>(nb));
+}
+
 static dim3 gather_grid(const GatherJob& jb) {
   const int64_t nb = static_cast<int64_t>((jb.width + kTileW - 1) / kTileW) *
                      ((jb.height + kTileH - 1) / kTileH) * jb.n_out;
@@ -1091,7 +1104,7 @@ hipError_t launch_scan(int64_t* offsets, int64_t n, int64_t* partial, hipStream_
 }
 
 hipError_t launch_scatter(const GatherJob& jb, hipStream_t st) {
-  const dim3 g = gather_grid(jb);
+  const dim3 g = tile16_grid(jb);
   switch (jb.radius) {
     case 0: scatter_r<0>(jb, g, st); break;
     case 1: scatter_r<1>(jb, g, st); break;
@@ -1119,9 +1132,7 @@ static void gather_filter_r(const GatherJob& jb, const FilterJob& fj, dim3 g, hi
 }
 
 hipError_t launch_gather_filter(const GatherJob& jb, const FilterJob& fj, hipStream_t st) {
-  const int64_t nb = static_cast<int64_t>((jb.width + kFuseW - 1) / kFuseW) *
-                     ((jb.height + kFuseH - 1) / kFuseH) * jb.n_out;
-  const dim3 g(static_cast<unsigned>(nb));
+  const dim3 g = tile16_grid(jb);
   switch (jb.radius) {
     case 0: gather_filter_r<0>(jb, fj, g, st); break;
     case 1: gather_filter_r<1>(jb, fj, g, st); break;

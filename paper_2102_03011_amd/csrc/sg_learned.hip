@@ -114,24 +114,41 @@ __device__ __forceinline__ float erf_of_half(float y) {  // erf(sqrt(2) |y|)
 // GELU(2y) from y = z/2
 __device__ __forceinline__ float gelu_half(float y) { return fmaf(fabsf(y), erf_of_half(y), y); }
 
-// Inference uses Abramowitz-Stegun 7.1.27, erf(x) = 1 - 1 / (1 + b1 x + ... + b4 x^4)^4
-// with |error| <= 5e-4: four multiply-adds and two squarings fewer than 7.1.28 per
-// activation. Carried through the network in float64 with the shipped weights and
-// with random test networks, it moves the filtered colour by at most 2.3e-4 (378k
-// records of the 320x180 workload), inside the 1e-3 contract; training keeps 7.1.28.
-constexpr float kF1 = static_cast<float>(0.278393 * 1.4142135623730951);
-constexpr float kF2 = static_cast<float>(0.230389 * 2.0);
-constexpr float kF3 = static_cast<float>(0.000972 * 2.8284271247461903);
-constexpr float kF4 = static_cast<float>(0.078108 * 4.0);
-__device__ __forceinline__ float gelu_half_fast(float y) {
-  const float a = fabsf(y);
-  float q = fmaf(kF4, a, kF3);
-  q = fmaf(q, a, kF2);
-  q = fmaf(q, a, kF1);
-  q = fmaf(q, a, 1.0f);
-  q *= q;
-  q *= q;
-  return fmaf(a, 1.0f - __builtin_amdgcn_rcpf(q), y);
+// Inference evaluates GELU(2y) = g(y) = y + |y| erf(sqrt(2) |y|) from a chord
+// table: y in [-4, 4) is cut into kGeluCells cells of width h = 1/128, and on cell
+// i the kernel takes the chord of g between the cell's ends, stored as (slope,
+// intercept) so that g(y) ~ slope y + intercept. A chord is within
+// h^2 max|g''| / 8 = 2.5e-5 of g (g''(y) = 4 phi(2y) (2 - 4y^2) <= 8 phi(0));
+// beyond [-4, 4) the end cells extrapolate g = 2y above (erf(4 sqrt 2) rounds to 1
+// in float32) and g ~ 0 below (|g| < 1e-14 at y = -4). Five vector instructions and
+// one LDS read per activation, against nine and a reciprocal for a polynomial
+// erf; training keeps 7.1.28, whose derivative it also needs.
+constexpr int kGeluCells = 1024;
+constexpr float kGeluPerUnit = 128.0f;  // cells per unit of y; cell 0 starts at y = -4
+constexpr int kGeluCellsPerThread = 4;
+
+// Fills the table (kGeluCells entries) from threads tid = 0 .. kGeluCells / 4 - 1,
+// each taking four consecutive cells, with the shared ends evaluated once.
+__device__ __forceinline__ void fill_gelu_table(float2* tab, int tid) {
+  const int i0 = kGeluCellsPerThread * tid;
+  float y0 = -4.0f + static_cast<float>(i0) / kGeluPerUnit;
+  float g0 = fmaf(fabsf(y0), erff(1.4142135623730951f * fabsf(y0)), y0);
+#pragma unroll
+  for (int k = 0; k < kGeluCellsPerThread; ++k) {
+    const float y1 = -4.0f + static_cast<float>(i0 + k + 1) / kGeluPerUnit;  // exact
+    const float g1 = fmaf(fabsf(y1), erff(1.4142135623730951f * fabsf(y1)), y1);
+    const float slope = (g1 - g0) * kGeluPerUnit;
+    tab[i0 + k] = make_float2(slope, fmaf(-slope, y0, g0));
+    y0 = y1;
+    g0 = g1;
+  }
+}
+__device__ __forceinline__ float gelu_half_table(const float2* tab, float y) {
+  // cell index clamped to the table (a NaN y lands in some cell; the result stays NaN)
+  const float t = __builtin_amdgcn_fmed3f(fmaf(y, kGeluPerUnit, 4.0f * kGeluPerUnit), 0.0f,
+                                          static_cast<float>(kGeluCells - 1));
+  const float2 e = tab[static_cast<uint32_t>(t)];
+  return fmaf(e.x, y, e.y);
 }
 __device__ __forceinline__ float gelu(float z) { return gelu_half(0.5f * z); }
 // GELU'(z) = Phi(z) + z phi(z)
@@ -166,8 +183,29 @@ struct FeatureArgs {
   gp<const uint16_t> depth;   // stored depth planes
   int width, height, n_frames, pw, w;
   size_t pplane;
-  float inv_w, fx, fy, cx, cy;
+  float inv_w, cx, cy;
+  float inv_fx, inv_fy, inv_width;  // reciprocals, once per kernel (no division per sample)
 };
+
+__device__ __forceinline__ FeatureArgs feature_args(gp<const uint16_t> depth, int width, int height, int n_frames,
+                                                    int w, float fx, float fy, float cx, float cy) {
+  FeatureArgs fa;
+  fa.rel = nullptr;
+  fa.depth = depth;
+  fa.width = width;
+  fa.height = height;
+  fa.n_frames = n_frames;
+  fa.pw = stored_pitch(width);
+  fa.w = w;
+  fa.pplane = static_cast<size_t>(fa.pw) * stored_rows(height);
+  fa.inv_w = w > 0 ? 1.0f / static_cast<float>(w) : 0.0f;
+  fa.cx = cx;
+  fa.cy = cy;
+  fa.inv_fx = 1.0f / fx;
+  fa.inv_fy = 1.0f / fy;
+  fa.inv_width = 1.0f / static_cast<float>(width);
+  return fa;
+}
 
 __device__ __forceinline__ bool valid_depth(float d) { return d > 0.0f && d < INFINITY; }
 
@@ -187,7 +225,8 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   const int dj = slot - a.w;
   const int j = px.f + dj;
   const int q = static_cast<int>(id & ((1u << SG_ID_SHIFT) - 1u));
-  int qy = static_cast<int>(static_cast<float>(q) / static_cast<float>(a.width));
+  // row by the reciprocal of the width (off by at most one, corrected below)
+  int qy = static_cast<int>(static_cast<float>(q) * a.inv_width);
   int qx = q - qy * a.width;
   if (qx < 0) { --qy; qx += a.width; }
   if (qx >= a.width) { ++qy; qx -= a.width; }
@@ -196,12 +235,13 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   const float a1 = fmaf(m[3], px.x, fmaf(m[4], px.y, m[5]));
   const float a2 = fmaf(m[6], px.x, fmaf(m[7], px.y, m[8]));
   const float y0 = fmaf(px.dp, a0, m[9]), y1 = fmaf(px.dp, a1, m[10]), z = fmaf(px.dp, a2, m[11]);
-  const float u = y0 / z, v = y1 / z;
+  const float rz = __builtin_amdgcn_rcpf(z);
+  const float u = y0 * rz, v = y1 * rz;
   // metric: X - o_f and X - o_J in frame-J axes (undo K on the folded map)
-  const float ax = (px.dp * a0 - a.cx * px.dp * a2) / a.fx;
-  const float ay = (px.dp * a1 - a.cy * px.dp * a2) / a.fy;
+  const float ax = (px.dp * a0 - a.cx * px.dp * a2) * a.inv_fx;
+  const float ay = (px.dp * a1 - a.cy * px.dp * a2) * a.inv_fy;
   const float az = px.dp * a2;
-  const float tx = (m[9] - a.cx * m[11]) / a.fx, ty = (m[10] - a.cy * m[11]) / a.fy, tzv = m[11];
+  const float tx = (m[9] - a.cx * m[11]) * a.inv_fx, ty = (m[10] - a.cy * m[11]) * a.inv_fy, tzv = m[11];
   const float bx = ax + tx, by = ay + ty, bz = az + tzv;
   // 1 - cos(angle) = |a/|a| - b/|b||^2 / 2: no cancellation for nearly parallel rays
   const float ra = rsqrtf(ax * ax + ay * ay + az * az), rb = rsqrtf(bx * bx + by * by + bz * bz);
@@ -222,7 +262,7 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   feat[2] = fabsf(static_cast<float>(dj)) * a.inv_w;
   feat[3] = sqrtf((qx - u) * (qx - u) + (qy - v) * (qy - v));
   feat[4] = one_minus_cos;
-  feat[5] = sqrtf(gx * gx + gy * gy) / d0;
+  feat[5] = sqrtf(gx * gx + gy * gy) * __builtin_amdgcn_rcpf(d0);
   feat[6] = px.x7;
   feat[7] = static_cast<float>(dj) * a.inv_w;
 }
@@ -342,10 +382,11 @@ __device__ __forceinline__ u32x4 a_operand_l2(P mw, int t2, int s, int hi32, int
 
 // The MLP on the wave's 64 samples (features staged in xs[0] (hi) / xs[1] (lo),
 // one uint4 per sample): returns the logit of the lane's own sample.
-template <bool kFastGelu>
+// kTable: GELU from the chord table s_gelu (inference); otherwise 7.1.28 (training).
+template <bool kTable>
 __device__ __forceinline__ float mlp_logits_64(const u32x4 (*s_a)[64], const uint4* xs_hi, const uint4* xs_lo,
                                                const float* s_bh, const float* s_w3, float b3, int hi32,
-                                               int col) {
+                                               int col, const float2* s_gelu) {
   const int lane = 32 * hi32 + col;
   float m_own = 0.0f;
 #pragma unroll
@@ -364,8 +405,8 @@ __device__ __forceinline__ float mlp_logits_64(const u32x4 (*s_a)[64], const uin
       const v16f d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(s_a[t][lane]), bx, c, 0, 0, 0);
 #pragma unroll
       for (int p = 0; p < 8; ++p)
-        split_pack(kFastGelu ? gelu_half_fast(d[2 * p]) : gelu_half(d[2 * p]),
-                   kFastGelu ? gelu_half_fast(d[2 * p + 1]) : gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
+        split_pack(kTable ? gelu_half_table(s_gelu, d[2 * p]) : gelu_half(d[2 * p]),
+                   kTable ? gelu_half_table(s_gelu, d[2 * p + 1]) : gelu_half(d[2 * p + 1]), ph[t][p], pl[t][p]);
     }
     // layer 2 (hi and lo passes) and the output unit on the vector units
     float mpart = 0.0f;
@@ -388,7 +429,8 @@ __device__ __forceinline__ float mlp_logits_64(const u32x4 (*s_a)[64], const uin
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int hid = 32 * t2 + 8 * q4 + 4 * hi32 + r;
-          mpart = fmaf(s_w3[hid], kFastGelu ? gelu_half_fast(d[4 * q4 + r]) : gelu_half(d[4 * q4 + r]), mpart);
+          mpart = fmaf(s_w3[hid], kTable ? gelu_half_table(s_gelu, d[4 * q4 + r]) : gelu_half(d[4 * q4 + r]),
+                       mpart);
         }
     }
     const float msum = mpart + __shfl_xor(mpart, 32, 64) + b3;
@@ -431,7 +473,10 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   __shared__ uint4 s_x[2][4][64];   // hi / lo parts; per wave: 64 samples x 8 bfloat16 features
   __shared__ FlatPixel s_px[4][kFlatPix];
   __shared__ u32x4 s_a[kAOps][64];
+  __shared__ float2 s_gelu[kGeluCells];
   const int tid = threadIdx.x + threadIdx.y * 64;
+  static_assert(kGeluCells == 256 * kGeluCellsPerThread, "one table slice per thread");
+  fill_gelu_table(s_gelu, tid);
   for (int i = tid; i < 2 * kNH; i += 256) s_bh[i] = 0.5f * mb[i];
   for (int i = tid; i < kNH; i += 256) s_w3[i] = bf16_to_f(mw[kOffW3 + i]);
   for (int i = tid; i < 2 * kNF; i += 256) s_std[i] = mb[kOffMean + i];
@@ -526,19 +571,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
   }
   wave_lds_fence_l();
 
-  FeatureArgs fa;
-  fa.depth = to_global(depth);
-  fa.width = width;
-  fa.height = height;
-  fa.n_frames = n_frames;
-  fa.pw = pw;
-  fa.w = w;
-  fa.pplane = pplane;
-  fa.inv_w = w > 0 ? 1.0f / static_cast<float>(w) : 0.0f;
-  fa.fx = fx;
-  fa.fy = fy;
-  fa.cx = cx;
-  fa.cy = cy;
+  const FeatureArgs fa = feature_args(to_global(depth), width, height, n_frames, w, fx, fy, cx, cy);
 
   // 3. stream the records
   for (int64_t base = rs; base < re; base += 64) {
@@ -581,7 +614,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
     s_x[0][wv][lane] = make_uint4(xh[0], xh[1], xh[2], xh[3]);
     s_x[1][wv][lane] = make_uint4(xl[0], xl[1], xl[2], xl[3]);
     wave_lds_fence_l();
-    const float m_own = mlp_logits_64<true>(s_a, s_x[0][wv], s_x[1][wv], s_bh, s_w3, b3, hi32, col);
+    const float m_own = mlp_logits_64<true>(s_a, s_x[0][wv], s_x[1][wv], s_bh, s_w3, b3, hi32, col, s_gelu);
 
     // segmented softmax over the lanes: key = pixel (dead lanes get keys of their own)
     // (every shuffle runs on all 64 lanes: a lane that skipped one would leave its
@@ -796,19 +829,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
   const int pw = stored_pitch(ta.width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
-  FeatureArgs fa;
-  fa.depth = ta.depth;
-  fa.width = ta.width;
-  fa.height = ta.height;
-  fa.n_frames = ta.n_frames;
-  fa.pw = pw;
-  fa.w = ta.w;
-  fa.pplane = pplane;
-  fa.inv_w = ta.w > 0 ? 1.0f / static_cast<float>(ta.w) : 0.0f;
-  fa.fx = ta.fx;
-  fa.fy = ta.fy;
-  fa.cx = ta.cx;
-  fa.cy = ta.cy;
+  FeatureArgs fa = feature_args(ta.depth, ta.width, ta.height, ta.n_frames, ta.w, ta.fx, ta.fy, ta.cx, ta.cy);
 
   // dW2 accumulators: tile (ti, tj), element a = dW2[32 ti + 8(a/4) + 4 hi32 + a%4][32 tj + col]
   v16f gw2[2][2];
@@ -873,7 +894,7 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
       uint2 rec;
       const bool live = stage(base, false, rec);
       wave_lds_fence_l();
-      const float m = mlp_logits_64<false>(s_a, s_x[0], s_x[1], s_bh, s_w3, b3, hi32, col);
+      const float m = mlp_logits_64<false>(s_a, s_x[0], s_x[1], s_bh, s_w3, b3, hi32, col, nullptr);
       wave_lds_fence_l();
       if (live) {
         const float nm = fmaxf(run_m, m);
@@ -1104,19 +1125,7 @@ __global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta_in, double*
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
   const int pw = stored_pitch(ta.width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
-  FeatureArgs fa;
-  fa.depth = ta.depth;
-  fa.width = ta.width;
-  fa.height = ta.height;
-  fa.n_frames = ta.n_frames;
-  fa.pw = pw;
-  fa.w = ta.w;
-  fa.pplane = pplane;
-  fa.inv_w = ta.w > 0 ? 1.0f / static_cast<float>(ta.w) : 0.0f;
-  fa.fx = ta.fx;
-  fa.fy = ta.fy;
-  fa.cx = ta.cx;
-  fa.cy = ta.cy;
+  FeatureArgs fa = feature_args(ta.depth, ta.width, ta.height, ta.n_frames, ta.w, ta.fx, ta.fy, ta.cx, ta.cy);
   double cnt = 0.0, sum[kNF], sq[kNF];
 #pragma unroll
   for (int k = 0; k < kNF; ++k) sum[k] = sq[k] = 0.0;
