@@ -206,23 +206,167 @@ __device__ __forceinline__ void for_members(const Carried* __restrict__ filed_, 
   }
 }
 
+// Count and scatter run on 16 x 16 tiles of output pixels, one thread each. Per
+// window frame the workgroup first copies the buckets its pixels can reach (kTile +
+// 2 rb rows of kTile + 2 rb buckets; each row is one contiguous range of filed
+// records) into LDS with loads spread over all its threads, then every thread reads
+// its 2 rb (rb + 1) + 1 buckets from there. A frame whose reachable records do not
+// fit (more than kStageCap: points of a wide depth range crowding into few buckets)
+// is read from global memory by every thread instead, as for_members does.
+constexpr int kTile = 16;
+constexpr int kMaxRb = 4;  // bucket_radius(SG_MAX_FRUSTUM_L)
+constexpr int kStageSide = kTile + 2 * kMaxRb;
+constexpr int kStageCap = 1024;
+constexpr int kBoundsPerThread = (kStageSide * (kStageSide + 1) + kThreads - 1) / kThreads;
+static_assert(kThreads == kTile * kTile, "one thread per pixel of a tile");
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 16-byte stores at 8- and 4-byte aligned positions (global memory takes unaligned
+// dword accesses)
+typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+struct StageLds {
+  u32x4 rec[kStageCap];                        // filed records of the staged rows, row after row
+  int32_t loc[kStageSide][kStageSide + 1];     // rec index of bucket (row, column); [r][ncols] = row end
+  int32_t base[kStageSide + 1];                // rec index of each row's first record; [nrows] = total
+  int64_t first[kStageSide];                   // filed index of each row's first record
+};
+
+struct TileGeom {
+  int tx0, ty0;       // first output pixel of the tile = first staged bucket (extended grid)
+  int nrows, ncols;   // staged bucket rows and columns that exist in the extended grid
+};
+
+__device__ __forceinline__ TileGeom tile_geom(int width, int height, int rb) {
+  const int tiles_x = (width + kTile - 1) / kTile;
+  TileGeom g;
+  g.tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * kTile;
+  g.ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * kTile;
+  g.nrows = min(kTile + 2 * rb, height + 2 * rb - g.ty0);
+  g.ncols = min(kTile + 2 * rb, width + 2 * rb - g.tx0);
+  return g;
+}
+
+// Stages window frame jn's reachable records; false (nothing staged) when they
+// number more than kStageCap. Every thread of the workgroup calls it; it ends on a
+// barrier either way, and the caller puts one between its last read of the staged
+// records and the next call.
+__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, int rb, const TileGeom& g,
+                            StageLds& s) {
+  const int t = threadIdx.x;
+  if (t < g.nrows) {
+    const int64_t row = static_cast<int64_t>(g.ty0 + t) * ew + g.tx0;
+    const int64_t a = bj[row], e = bj[row + g.ncols];
+    s.first[t] = a;
+    s.base[t + 1] = static_cast<int32_t>(min(e - a, static_cast<int64_t>(kStageCap) + 1));
+  }
+  __syncthreads();
+  if (t == 0) {  // row starts (at most kStageSide rows; clamped counts cannot overflow)
+    int acc = 0;
+    s.base[0] = 0;
+    for (int r = 0; r < g.nrows; ++r) {
+      acc = min(acc + s.base[r + 1], kStageCap + 1);
+      s.base[r + 1] = acc;
+    }
+  }
+  __syncthreads();
+  const int total = s.base[g.nrows];
+  if (total > kStageCap) {  // uniform: every thread read the same LDS word
+    __syncthreads();        // ... before the next call rewrites it
+    return false;
+  }
+  // bucket starts relative to the staged rows, and the records, loads issued together
+  int64_t gb[kBoundsPerThread];
+  int ib[kBoundsPerThread];
+#pragma unroll
+  for (int k = 0; k < kBoundsPerThread; ++k) {
+    const int i = t + k * kThreads;
+    ib[k] = i < g.nrows * (g.ncols + 1) ? i : -1;
+    if (ib[k] >= 0) {
+      const int r = i / (g.ncols + 1), c = i - r * (g.ncols + 1);
+      gb[k] = bj[static_cast<int64_t>(g.ty0 + r) * ew + g.tx0 + c];
+    }
+  }
+  constexpr int kRecPerThread = kStageCap / kThreads;
+  static_assert(kRecPerThread * kThreads == kStageCap, "whole records per thread");
+  u32x4 v[kRecPerThread];
+#pragma unroll
+  for (int k = 0; k < kRecPerThread; ++k) {
+    const int i = t + k * kThreads;
+    if (i < total) {
+      int lo = 0, hi = g.nrows - 1;  // row r with base[r] <= i < base[r + 1]
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.base[mid] <= i) lo = mid; else hi = mid - 1;
+      }
+      v[k] = filed[s.first[lo] + (i - s.base[lo])];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kBoundsPerThread; ++k) {
+    if (ib[k] >= 0) {
+      const int r = ib[k] / (g.ncols + 1), c = ib[k] - r * (g.ncols + 1);
+      s.loc[r][c] = s.base[r] + static_cast<int32_t>(gb[k] - s.first[r]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kRecPerThread; ++k)
+    if (t + k * kThreads < total) s.rec[t + k * kThreads] = v[k];
+  __syncthreads();
+  return true;
+}
+
+// for_members over the staged records (thread's pixel (x, y) = (tx0 + tx, ty0 + ty)).
+template <typename Fn>
+__device__ __forceinline__ void for_members_staged(const StageLds& s, int rb, float half, int tx, int ty, int x,
+                                                   int y, Fn&& fn) {
+  const float fx = static_cast<float>(x), fy = static_cast<float>(y);
+  for (int dy = -rb; dy <= rb; ++dy) {
+    const int span = rb - (dy < 0 ? -dy : dy);
+    const int r = ty + dy + rb;
+    const int k0 = s.loc[r][tx + rb - span], k1 = s.loc[r][tx + rb + span + 1];
+    for (int k = k0; k < k1; ++k) {
+      const u32x4 w = s.rec[k];
+      Carried c;
+      c.x = __uint_as_float(w[0]);
+      c.y = __uint_as_float(w[1]);
+      c.z = __uint_as_float(w[2]);
+      c.b = static_cast<int32_t>(w[3]);
+      if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(c.b, c);
+    }
+  }
+}
+
+// grid: 16 x 16 tiles of the output frame
 __global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __restrict__ filed,
-                                                            const int64_t* __restrict__ boff, int width, int n_j,
-                                                            int rb, float half, int64_t n_pix, int64_t n_buckets,
+                                                            const int64_t* __restrict__ boff, int width, int height,
+                                                            int n_j, int rb, float half, int64_t n_buckets,
                                                             int64_t* __restrict__ counts) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  if (p >= n_pix) return;
-  const int y = static_cast<int>(p / width), x = static_cast<int>(p - static_cast<int64_t>(y) * width);
+  __shared__ StageLds s;
+  const TileGeom g = tile_geom(width, height, rb);
+  const int tx = static_cast<int>(threadIdx.x) % kTile, ty = static_cast<int>(threadIdx.x) / kTile;
+  const int x = g.tx0 + tx, y = g.ty0 + ty;
+  const bool in = x < width && y < height;
+  const int ew = width + 2 * rb;
+  gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t n = 0;
-  for (int jn = 0; jn < n_j; ++jn)
-    for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
-  to_global(counts)[p] = n;
+  for (int jn = 0; jn < n_j; ++jn) {
+    gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
+    if (stage_frame(filed4, bj, ew, rb, g, s)) {
+      if (in) for_members_staged(s, rb, half, tx, ty, x, y, [&](int32_t, Carried) { ++n; });
+      __syncthreads();
+    } else if (in) {
+      for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
+    }
+  }
+  if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
 }
 
 // Members of one (p, J) pair held per thread while they are ordered: kSortSlots
 // entries of (q, z') in LDS, laid out [slot][thread] so that the threads of a wave
 // touch consecutive words.
-constexpr int kSortSlots = 24;
+constexpr int kSortSlots = 16;
 
 // Scatter: per output pixel and window frame, one pass over the buckets collects the
 // members, an insertion sort on q orders them, and they are written in canonical
@@ -231,47 +375,98 @@ constexpr int kSortSlots = 24;
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_,
     const Carried* __restrict__ filed, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
-    int n_j, int rb, float half, int64_t n_pix, int64_t n_buckets, const int64_t* __restrict__ offsets_,
+    int n_j, int rb, float half, int64_t n_buckets, const int64_t* __restrict__ offsets_,
     uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity, uint32_t* __restrict__ status_) {
+  __shared__ StageLds s;
   __shared__ int32_t s_q[kSortSlots][kThreads];
   __shared__ float s_z[kSortSlots][kThreads];
   const int t = threadIdx.x;
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * kThreads + t;
-  if (p >= n_pix) return;  // no barrier below: threads are independent
+  const TileGeom g = tile_geom(width, height, rb);
+  const int tx = t % kTile, ty = t / kTile;
+  const int x = g.tx0 + tx, y = g.ty0 + ty;
+  const int ew = width + 2 * rb;
   gp<uint32_t> status = to_global(status_);
-  const int64_t start = to_global(offsets_)[p], end = to_global(offsets_)[p + 1];
-  if (start < 0 || end < start) {
-    flag_or(status, SG_FLAG_INCONSISTENT);
-    return;
+  // a thread outside the image, or whose segment cannot be written, only joins the
+  // staging (every thread reaches every barrier)
+  bool live = x < width && y < height;
+  const int64_t p = static_cast<int64_t>(y) * width + x;
+  int64_t start = 0, end = 0;
+  if (live) {
+    start = to_global(offsets_)[p];
+    end = to_global(offsets_)[p + 1];
+    if (start < 0 || end < start) {
+      flag_or(status, SG_FLAG_INCONSISTENT);
+      live = false;
+    } else if (end > capacity) {
+      if (end > start) flag_or(status, SG_FLAG_CAPACITY);
+      live = false;
+    }
   }
-  if (end > capacity) {
-    if (end > start) flag_or(status, SG_FLAG_CAPACITY);
-    return;
-  }
-  const int y = static_cast<int>(p / width), x = static_cast<int>(p - static_cast<int64_t>(y) * width);
   const int pw = stored_pitch(width);
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float dp = h2f(to_global(depth_)[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+  const float dp = live ? h2f(to_global(depth_)[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]) : 0.0f;
   const bool has_ref = dp > 0.0f && dp < INFINITY;
+  const float inv_width = 1.0f / static_cast<float>(width);
   gp<const uint2> rgbd = to_global(rgbd_);
   gp<uint32_t> ids = to_global(ids_);
   gp<uint2> crho = to_global(crho_);
+  gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t cur = start;
+  // one record: source pixel q of window frame j, carried depth z
+  auto make = [&](int j, uint32_t id_j, int32_t q, float z, uint32_t (&r)[3]) {
+    int qy = static_cast<int>(static_cast<float>(q) * inv_width);  // off by at most one
+    int qx = q - qy * width;
+    if (qx < 0) { --qy; qx += width; }
+    if (qx >= width) { ++qy; qx -= width; }
+    const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
+    const float rho = has_ref ? (z - dp) / dp : __builtin_nanf("");
+    r[0] = v.x;
+    r[1] = (v.y & 0xFFFFu) | (f2h(rho) << 16);
+    r[2] = id_j | static_cast<uint32_t>(q);
+  };
   auto emit = [&](int j, uint32_t id_j, int32_t q, float z) {
     if (cur < end) {  // a count that changed since pass 1 never writes past the segment
-      const int qy = q / width, qx = q - qy * width;
-      const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
-      const float rho = has_ref ? (z - dp) / dp : __builtin_nanf("");
-      st2(crho + cur, make_uint2(v.x, (v.y & 0xFFFFu) | (f2h(rho) << 16)));
-      ids[cur] = id_j | static_cast<uint32_t>(q);
+      uint32_t r[3];
+      make(j, id_j, q, z, r);
+      st2(crho + cur, make_uint2(r[0], r[1]));
+      ids[cur] = r[2];
     }
     ++cur;
   };
-  for (int jn = 0; jn < n_j; ++jn) {
+  // the sorted members in slots [0, n) of this thread, four at a time: the colour
+  // loads of a group are in flight together, and a whole group goes out as two
+  // 16-byte colour stores and one 16-byte id store (a segment position is 8-byte
+  // aligned in crho, 4-byte in ids)
+  auto emit_slots = [&](int j, uint32_t id_j, int n) {
+    for (int a0 = 0; a0 < n; a0 += 4) {
+      const int c = min(4, n - a0);
+      uint32_t r[4][3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < c) make(j, id_j, s_q[a0 + i][t], s_z[a0 + i][t], r[i]);
+      const int64_t room = end - cur;
+      if (c == 4 && room >= 4) {
+        gp<u32x4a8> cr = reinterpret_cast<gp<u32x4a8>>(crho + cur);
+        cr[0] = u32x4a8{r[0][0], r[0][1], r[1][0], r[1][1]};
+        cr[1] = u32x4a8{r[2][0], r[2][1], r[3][0], r[3][1]};
+        *reinterpret_cast<gp<u32x4a4>>(ids + cur) = u32x4a4{r[0][2], r[1][2], r[2][2], r[3][2]};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < c && i < room) {
+            st2(crho + cur + i, make_uint2(r[i][0], r[i][1]));
+            ids[cur + i] = r[i][2];
+          }
+      }
+      cur += c;
+    }
+  };
+  // one window frame's members of this pixel, from the staged records or global memory
+  auto frame = [&](int jn, auto&& members) {
     const int j = jlo + jn;
     const uint32_t id_j = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
     int n = 0;
-    for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+    members([&](int32_t q, Carried c) {
       if (n < kSortSlots) {
         s_q[n][t] = q;
         s_z[n][t] = c.z;
@@ -291,13 +486,13 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
         s_q[b + 1][t] = qa;
         s_z[b + 1][t] = za;
       }
-      for (int a = 0; a < n; ++a) emit(j, id_j, s_q[a][t], s_z[a][t]);
+      emit_slots(j, id_j, n);
     } else {
       int32_t last = -1;
       for (;;) {  // the smallest member above the last emitted
         int32_t best = INT_MAX;
         float best_z = 0.0f;
-        for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t q, Carried c) {
+        members([&](int32_t q, Carried c) {
           if (q > last && q < best) {
             best = q;
             best_z = c.z;
@@ -308,8 +503,17 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
         last = best;
       }
     }
+  };
+  for (int jn = 0; jn < n_j; ++jn) {
+    gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
+    if (stage_frame(filed4, bj, ew, rb, g, s)) {
+      if (live) frame(jn, [&](auto&& fn) { for_members_staged(s, rb, half, tx, ty, x, y, fn); });
+      __syncthreads();
+    } else if (live) {
+      frame(jn, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); });
+    }
   }
-  if (cur != end) flag_or(status, SG_FLAG_INCONSISTENT);
+  if (live && cur != end) flag_or(status, SG_FLAG_INCONSISTENT);
 }
 
 sg_status check_frustum(const sg_clip* clip, int32_t f, const sg_frustum_params* p) {
@@ -352,6 +556,10 @@ sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_param
   c->filed = reinterpret_cast<Carried*>(base + c->l.items);
   c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
   return SG_OK;
+}
+
+dim3 tile_grid(const sg_clip* clip) {
+  return dim3(static_cast<unsigned>(((clip->width + kTile - 1) / kTile) * ((clip->height + kTile - 1) / kTile)));
 }
 
 unsigned zero_blocks(int64_t n) {
@@ -397,8 +605,8 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
   if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
   hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st, c.carry, c.boff, c.bfill,
                      l.n_pix, l.n_buckets, c.filed);
-  hipLaunchKernelGGL(sg::k_frustum_count, per_pixel, dim3(sg::kThreads), 0, st, c.filed, c.boff,
-                     clip->width, l.n_j, l.rb, half, l.n_pix, l.n_buckets, sets->offsets + 1);
+  hipLaunchKernelGGL(sg::k_frustum_count, sg::tile_grid(clip), dim3(sg::kThreads), 0, st, c.filed, c.boff,
+                     clip->width, clip->height, l.n_j, l.rb, half, l.n_buckets, sets->offsets + 1);
   return hip_status(sg::launch_scan(sets->offsets, l.n_pix, c.partial, st));
 }
 
@@ -408,10 +616,10 @@ sg_status scene_frustum_scatter(const sg_clip* clip, int32_t f, const sg_frustum
   const sg_status s = sg::frustum_prepare(clip, f, params, sets, workspace, workspace_bytes, true, &c);
   if (s != SG_OK) return s;
   const sg::FrustumLayout& l = c.l;
-  hipLaunchKernelGGL(sg::k_frustum_scatter, dim3(static_cast<unsigned>((l.n_pix + sg::kThreads - 1) / sg::kThreads)),
-                     dim3(sg::kThreads), 0, static_cast<hipStream_t>(stream),
-                     reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.filed, c.boff, clip->width,
-                     clip->height, f, params->window, l.jlo, l.n_j, l.rb, 0.5f * params->l, l.n_pix, l.n_buckets,
+  hipLaunchKernelGGL(sg::k_frustum_scatter, sg::tile_grid(clip), dim3(sg::kThreads), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->depth,
+                     c.filed, c.boff, clip->width, clip->height, f, params->window, l.jlo, l.n_j, l.rb,
+                     0.5f * params->l, l.n_buckets,
                      sets->offsets, sets->ids, reinterpret_cast<uint2*>(sets->crho), sets->capacity, sets->status);
   return hip_status(hipGetLastError());
 }
