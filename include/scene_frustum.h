@@ -42,19 +42,22 @@ typedef struct sg_frustum_params {
 } sg_frustum_params;
 
 /* Bytes of device workspace for output frame f: per window frame, every pixel's
- * carried position (16 B) and bucket entry (4 B), and the bucket grid's offsets. */
+ * bucket and slot (8 B) and filed record (32 B: carried position and depth, pixel
+ * index, stored colour), and the bucket grid's offsets. */
 sg_status scene_frustum_workspace_size(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
                                        size_t* bytes);
 
 /* Pass 1: carry every pixel of every window frame into the output view, bucket
- * them by nearest output pixel, count each output pixel's members and scan the
- * counts into sets->offsets (total at offsets[P]). Clears *sets->status (as
- * scene_gather_count does). Needs clip->depth. */
+ * them by nearest output pixel (each filed with its stored colour), count each
+ * output pixel's members and scan the counts into sets->offsets (total at
+ * offsets[P]). Clears *sets->status (as scene_gather_count does). Needs
+ * clip->depth and clip->rgbd. */
 sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
                               sg_sample_sets* sets, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Pass 2: write each member's record at its CSR slot (ascending id). Needs the
- * offsets and the workspace left by scene_frustum_count with identical arguments.
+ * offsets and the workspace left by scene_frustum_count with identical arguments
+ * (the colours come from the workspace) and clip->depth.
  * A pixel whose records would pass `capacity` writes none and sets
  * SG_FLAG_CAPACITY; a count that differs from pass 1 sets SG_FLAG_INCONSISTENT. */
 sg_status scene_frustum_scatter(const sg_clip* clip, int32_t f, const sg_frustum_params* params,

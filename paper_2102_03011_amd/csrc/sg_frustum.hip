@@ -9,9 +9,12 @@
 //              and near <= z' <= far, and filed under its nearest output pixel
 //              b(q) = round(p'(q)) on a grid extended by the bucket radius rb
 //              (a member has |p - b(q)|_1 < l/2 + 1, so rb = ceil(l/2 + 1) - 1);
-//   bucket  -- counting sort of the kept q by b(q) (count, scan, atomic fill: the
-//              order inside a bucket is arbitrary), each filed with its carried
-//              position, so a row of buckets is one contiguous range of records;
+//              the bucket's counter hands q its slot (the order inside a bucket is
+//              arbitrary);
+//   bucket  -- after a scan of the counters, q is filed at its bucket's start plus
+//              its slot, with p'(q), z'(q) (computed again, the same float32
+//              arithmetic) and its stored colour, so a row of buckets is one
+//              contiguous range of records and the scatter reads no source plane;
 //   count / scatter -- each output pixel reads the buckets within L1 distance rb,
 //              applies Eq. 2, and (scatter) orders its members of J by q in a small
 //              per-thread sort, so the records come out in canonical order whatever
@@ -32,14 +35,23 @@
 namespace sg {
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 16-byte stores at 8- and 4-byte aligned positions (global memory takes unaligned
+// dword accesses)
+typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
 constexpr int kMapFloats = 16;  // per window frame: M (3x3, row-major), k (3), padding
 constexpr int kThreads = 256;
 
-// a source pixel carried into the output view: p' = (x, y), z', bucket (-1: not kept)
-struct __attribute__((aligned(16))) Carried {
+// a filed source pixel: p' = (x, y), z', q, and its stored r, g, b, depth (binary16)
+struct __attribute__((aligned(32))) Filed {
   float x, y, z;
-  int32_t b;
+  int32_t q;
+  uint32_t rg, bd;
+  uint32_t pad[2];
 };
+static_assert(sizeof(Filed) == 32, "two 16-byte words per record");
 
 int bucket_radius(float l) { return static_cast<int>(ceilf(0.5f * l + 1.0f)) - 1; }
 
@@ -48,7 +60,7 @@ size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
 struct FrustumLayout {
   int jlo, n_j, rb;
   int64_t n_pix, n_buckets;  // per window frame
-  size_t maps, carry, boff, bfill, items, partial, total;
+  size_t maps, slots, boff, items, partial, total;
 };
 
 FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_params* p) {
@@ -64,14 +76,12 @@ FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_param
   size_t at = 0;
   l.maps = at;
   at += align_up(static_cast<size_t>(l.n_j) * kMapFloats * sizeof(float));
-  l.carry = at;
-  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Carried));
+  l.slots = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(int2));
   l.boff = at;
   at += align_up((static_cast<size_t>(l.n_j) * l.n_buckets + 1) * sizeof(int64_t));
-  l.bfill = at;
-  at += align_up(static_cast<size_t>(l.n_j) * l.n_buckets * sizeof(int32_t));
   l.items = at;
-  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Carried));
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Filed));
   l.partial = at;
   at += align_up(static_cast<size_t>((scan_a > scan_b ? scan_a : scan_b) + 1) * sizeof(int64_t));
   l.total = at;
@@ -123,68 +133,86 @@ __global__ __launch_bounds__(64) void k_frustum_pose(const double* __restrict__ 
   }
 }
 
-// grid (pixels / 256, window frames)
-__global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __restrict__ depth_,
+// p'(q), z'(q) of source pixel (x, y) of window frame jn; its bucket, or -1 when q is
+// not kept (invalid depth, z' outside [near, far], or p' beyond the extended grid).
+// The carry and bucket passes both call it, so both see the same floats.
+__device__ __forceinline__ int carry_point(gp<const uint16_t> depth, gp<const float> m, int width, int height,
+                                           int jn_plane_frame, int x, int y, int rb, float near_z, float far_z,
+                                           float& px, float& py, float& z) {
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const float d = h2f(depth[static_cast<size_t>(jn_plane_frame) * pplane + padded_index(x, y, pw)]);
+  px = py = z = 0.0f;
+  if (!(d > 0.0f && d < INFINITY)) return -1;
+  const float fx = static_cast<float>(x), fy = static_cast<float>(y);
+  const float y0 = fmaf(d, fmaf(m[0], fx, fmaf(m[1], fy, m[2])), m[9]);
+  const float y1 = fmaf(d, fmaf(m[3], fx, fmaf(m[4], fy, m[5])), m[10]);
+  z = fmaf(d, fmaf(m[6], fx, fmaf(m[7], fy, m[8])), m[11]);
+  if (!(z >= near_z && z <= far_z)) return -1;
+  px = y0 / z;
+  py = y1 / z;
+  const float ex = px + 0.5f, ey = py + 0.5f;
+  // NaN fails every comparison; the bounds keep b inside the extended grid
+  if (!(ex >= static_cast<float>(-rb) && ex < static_cast<float>(width + rb) && ey >= static_cast<float>(-rb) &&
+        ey < static_cast<float>(height + rb)))
+    return -1;
+  const int bx = static_cast<int>(floorf(ex)), by = static_cast<int>(floorf(ey));
+  return (by + rb) * (width + 2 * rb) + (bx + rb);
+}
+
+// grid (pixels / 256, window frames): the bucket of every q and its slot in it
+__global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __restrict__ depth,
                                                             const float* __restrict__ maps, int width, int height,
                                                             int jlo, int rb, float near_z, float far_z, int64_t n_pix,
-                                                            int64_t n_buckets, Carried* __restrict__ carry,
+                                                            int64_t n_buckets, int2* __restrict__ slots,
                                                             unsigned long long* __restrict__ bcount) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (q >= n_pix) return;
   const int jn = blockIdx.y;
   const int y = static_cast<int>(q / width), x = static_cast<int>(q - static_cast<int64_t>(y) * width);
-  const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float d = h2f(to_global(depth_)[static_cast<size_t>(jlo + jn) * pplane + padded_index(x, y, pw)]);
-  const float* m = maps + jn * kMapFloats;
-  int b = -1;
-  float px = 0.0f, py = 0.0f, z = 0.0f;
-  if (d > 0.0f && d < INFINITY) {
-    const float fx = static_cast<float>(x), fy = static_cast<float>(y);
-    const float y0 = fmaf(d, fmaf(m[0], fx, fmaf(m[1], fy, m[2])), m[9]);
-    const float y1 = fmaf(d, fmaf(m[3], fx, fmaf(m[4], fy, m[5])), m[10]);
-    z = fmaf(d, fmaf(m[6], fx, fmaf(m[7], fy, m[8])), m[11]);
-    if (z >= near_z && z <= far_z) {
-      px = y0 / z;
-      py = y1 / z;
-      const float ex = px + 0.5f, ey = py + 0.5f;
-      // NaN fails every comparison; the bounds keep b inside the extended grid
-      if (ex >= static_cast<float>(-rb) && ex < static_cast<float>(width + rb) && ey >= static_cast<float>(-rb) &&
-          ey < static_cast<float>(height + rb)) {
-        const int bx = static_cast<int>(floorf(ex)), by = static_cast<int>(floorf(ey));
-        b = (by + rb) * (width + 2 * rb) + (bx + rb);
-        atomicAdd(bcount + 1 + static_cast<int64_t>(jn) * n_buckets + b, 1ull);
-      }
-    }
-  }
-  carry[static_cast<int64_t>(jn) * n_pix + q] = Carried{px, py, z, b};
+  float px, py, z;
+  const int b = carry_point(to_global(depth), to_global(maps) + jn * kMapFloats, width, height, jlo + jn, x, y, rb,
+                            near_z, far_z, px, py, z);
+  int slot = 0;
+  if (b >= 0)
+    slot = static_cast<int>(atomicAdd(bcount + 1 + static_cast<int64_t>(jn) * n_buckets + b, 1ull));
+  slots[static_cast<int64_t>(jn) * n_pix + q] = make_int2(b, slot);
 }
 
-// grid (pixels / 256, window frames): file every kept q in its bucket, as its carried
-// position with q in place of the bucket index, so the count and scatter passes read
-// each bucket's candidates contiguously
-__global__ __launch_bounds__(kThreads) void k_frustum_bucket(const Carried* __restrict__ carry,
-                                                             const int64_t* __restrict__ boff,
-                                                             int32_t* __restrict__ bfill, int64_t n_pix,
-                                                             int64_t n_buckets, Carried* __restrict__ filed) {
+// grid (pixels / 256, window frames): file every kept q at its bucket's start plus its
+// slot, so the count and scatter passes read each bucket's candidates contiguously
+__global__ __launch_bounds__(kThreads) void k_frustum_bucket(const uint2* __restrict__ rgbd,
+                                                             const uint16_t* __restrict__ depth,
+                                                             const float* __restrict__ maps, int width, int height,
+                                                             int jlo, int rb, float near_z, float far_z,
+                                                             const int2* __restrict__ slots,
+                                                             const int64_t* __restrict__ boff, int64_t n_pix,
+                                                             int64_t n_buckets, Filed* __restrict__ filed) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (q >= n_pix) return;
   const int jn = blockIdx.y;
-  const Carried c = carry[static_cast<int64_t>(jn) * n_pix + q];
-  const int b = c.b;
-  if (b < 0) return;
-  const int64_t e = static_cast<int64_t>(jn) * n_buckets + b;
-  const int slot = atomicAdd(bfill + e, 1);
-  filed[to_global(boff)[e] + slot] = Carried{c.x, c.y, c.z, static_cast<int32_t>(q)};
+  const int2 bs = slots[static_cast<int64_t>(jn) * n_pix + q];
+  if (bs.x < 0) return;
+  const int y = static_cast<int>(q / width), x = static_cast<int>(q - static_cast<int64_t>(y) * width);
+  float px, py, z;
+  carry_point(to_global(depth), to_global(maps) + jn * kMapFloats, width, height, jlo + jn, x, y, rb, near_z, far_z,
+              px, py, z);
+  const int pw = stored_pitch(width);
+  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const uint2 c = ld2(to_global(rgbd) + static_cast<size_t>(jlo + jn) * pplane + padded_index(x, y, pw));
+  const int64_t at = to_global(boff)[static_cast<int64_t>(jn) * n_buckets + bs.x] + bs.y;
+  gp<u32x4> out = reinterpret_cast<gp<u32x4>>(to_global(filed) + at);
+  out[0] = u32x4{__float_as_uint(px), __float_as_uint(py), __float_as_uint(z), static_cast<uint32_t>(q)};
+  out[1] = u32x4{c.x, c.y, 0u, 0u};
 }
 
-// Calls fn(q, carried) for every q filed within L1 distance rb of output pixel
-// (x, y) in window frame jn and passing Eq. 2.
+// Calls fn(q, z', k) for every q filed (at index k) within L1 distance rb of output
+// pixel (x, y) in window frame jn and passing Eq. 2.
 template <typename Fn>
-__device__ __forceinline__ void for_members(const Carried* __restrict__ filed_, const int64_t* __restrict__ boff,
+__device__ __forceinline__ void for_members(const Filed* __restrict__ filed_, const int64_t* __restrict__ boff,
                                             int width, int rb, float half, int64_t n_buckets, int jn, int x, int y,
                                             Fn&& fn) {
-  gp<const uint64_t> filed = reinterpret_cast<gp<const uint64_t>>(to_global(filed_));
+  gp<const u32x4> filed = reinterpret_cast<gp<const u32x4>>(to_global(filed_));
   gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
   const int ew = width + 2 * rb;
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
@@ -194,14 +222,9 @@ __device__ __forceinline__ void for_members(const Carried* __restrict__ filed_, 
     // the buckets of this row are adjacent: one contiguous range of filed records
     const int64_t k0 = bj[row - span], k1 = bj[row + span + 1];
     for (int64_t k = k0; k < k1; ++k) {
-      // 16-byte record as two 8-byte words (struct copies take generic pointers)
-      const uint64_t lo = filed[2 * k], hi = filed[2 * k + 1];
-      Carried c;
-      c.x = __uint_as_float(static_cast<uint32_t>(lo));
-      c.y = __uint_as_float(static_cast<uint32_t>(lo >> 32));
-      c.z = __uint_as_float(static_cast<uint32_t>(hi));
-      c.b = static_cast<int32_t>(hi >> 32);
-      if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(c.b, c);
+      const u32x4 w = filed[2 * k];
+      if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
+        fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
     }
   }
 }
@@ -220,17 +243,14 @@ constexpr int kStageCap = 1024;
 constexpr int kBoundsPerThread = (kStageSide * (kStageSide + 1) + kThreads - 1) / kThreads;
 static_assert(kThreads == kTile * kTile, "one thread per pixel of a tile");
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-// 16-byte stores at 8- and 4-byte aligned positions (global memory takes unaligned
-// dword accesses)
-typedef uint32_t u32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
-typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
-
+// records staged per window frame (kColour: with their colours, for the scatter)
+template <bool kColour>
 struct StageLds {
-  u32x4 rec[kStageCap];                        // filed records of the staged rows, row after row
-  int32_t loc[kStageSide][kStageSide + 1];     // rec index of bucket (row, column); [r][ncols] = row end
-  int32_t base[kStageSide + 1];                // rec index of each row's first record; [nrows] = total
-  int64_t first[kStageSide];                   // filed index of each row's first record
+  u32x4 rec[kStageCap];                     // x, y, z', q of the staged rows, row after row
+  uint2 col[kColour ? kStageCap : 1];       // their r, g, b, depth
+  int32_t loc[kStageSide][kStageSide + 1];  // rec index of bucket (row, column); [r][ncols] = row end
+  int32_t base[kStageSide + 1];             // rec index of each row's first record; [nrows] = total
+  int64_t first[kStageSide];                // filed index of each row's first record
 };
 
 struct TileGeom {
@@ -252,8 +272,9 @@ __device__ __forceinline__ TileGeom tile_geom(int width, int height, int rb) {
 // number more than kStageCap. Every thread of the workgroup calls it; it ends on a
 // barrier either way, and the caller puts one between its last read of the staged
 // records and the next call.
-__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, int rb, const TileGeom& g,
-                            StageLds& s) {
+template <bool kColour>
+__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g,
+                            StageLds<kColour>& s) {
   const int t = threadIdx.x;
   if (t < g.nrows) {
     const int64_t row = static_cast<int64_t>(g.ty0 + t) * ew + g.tx0;
@@ -291,6 +312,7 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
   constexpr int kRecPerThread = kStageCap / kThreads;
   static_assert(kRecPerThread * kThreads == kStageCap, "whole records per thread");
   u32x4 v[kRecPerThread];
+  uint2 cv[kRecPerThread];
 #pragma unroll
   for (int k = 0; k < kRecPerThread; ++k) {
     const int i = t + k * kThreads;
@@ -300,7 +322,12 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
         const int mid = (lo + hi + 1) >> 1;
         if (s.base[mid] <= i) lo = mid; else hi = mid - 1;
       }
-      v[k] = filed[s.first[lo] + (i - s.base[lo])];
+      const int64_t at = s.first[lo] + (i - s.base[lo]);
+      v[k] = filed[2 * at];
+      if (kColour) {
+        const u32x4 w = filed[2 * at + 1];
+        cv[k] = make_uint2(w[0], w[1]);
+      }
     }
   }
 #pragma unroll
@@ -312,15 +339,19 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
   }
 #pragma unroll
   for (int k = 0; k < kRecPerThread; ++k)
-    if (t + k * kThreads < total) s.rec[t + k * kThreads] = v[k];
+    if (t + k * kThreads < total) {
+      s.rec[t + k * kThreads] = v[k];
+      if (kColour) s.col[t + k * kThreads] = cv[k];
+    }
   __syncthreads();
   return true;
 }
 
-// for_members over the staged records (thread's pixel (x, y) = (tx0 + tx, ty0 + ty)).
-template <typename Fn>
-__device__ __forceinline__ void for_members_staged(const StageLds& s, int rb, float half, int tx, int ty, int x,
-                                                   int y, Fn&& fn) {
+// for_members over the staged records: fn(q, z', staged index) (thread's pixel
+// (x, y) = (tx0 + tx, ty0 + ty)).
+template <bool kColour, typename Fn>
+__device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, int rb, float half, int tx, int ty,
+                                                   int x, int y, Fn&& fn) {
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
   for (int dy = -rb; dy <= rb; ++dy) {
     const int span = rb - (dy < 0 ? -dy : dy);
@@ -328,22 +359,18 @@ __device__ __forceinline__ void for_members_staged(const StageLds& s, int rb, fl
     const int k0 = s.loc[r][tx + rb - span], k1 = s.loc[r][tx + rb + span + 1];
     for (int k = k0; k < k1; ++k) {
       const u32x4 w = s.rec[k];
-      Carried c;
-      c.x = __uint_as_float(w[0]);
-      c.y = __uint_as_float(w[1]);
-      c.z = __uint_as_float(w[2]);
-      c.b = static_cast<int32_t>(w[3]);
-      if (fabsf(fx - c.x) + fabsf(fy - c.y) < half) fn(c.b, c);
+      if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
+        fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
     }
   }
 }
 
 // grid: 16 x 16 tiles of the output frame
-__global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __restrict__ filed,
+__global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restrict__ filed,
                                                             const int64_t* __restrict__ boff, int width, int height,
                                                             int n_j, int rb, float half, int64_t n_buckets,
                                                             int64_t* __restrict__ counts) {
-  __shared__ StageLds s;
+  __shared__ StageLds<false> s;
   const TileGeom g = tile_geom(width, height, rb);
   const int tx = static_cast<int>(threadIdx.x) % kTile, ty = static_cast<int>(threadIdx.x) / kTile;
   const int x = g.tx0 + tx, y = g.ty0 + ty;
@@ -353,33 +380,36 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Carried* __res
   int64_t n = 0;
   for (int jn = 0; jn < n_j; ++jn) {
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    if (stage_frame(filed4, bj, ew, rb, g, s)) {
-      if (in) for_members_staged(s, rb, half, tx, ty, x, y, [&](int32_t, Carried) { ++n; });
+    if (stage_frame(filed4, bj, ew, g, s)) {
+      if (in) for_members_staged(s, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
       __syncthreads();
     } else if (in) {
-      for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, Carried) { ++n; });
+      for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, float, int64_t) { ++n; });
     }
   }
   if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
 }
 
-// Members of one (p, J) pair held per thread while they are ordered: kSortSlots
-// entries of (q, z') in LDS, laid out [slot][thread] so that the threads of a wave
-// touch consecutive words.
-constexpr int kSortSlots = 16;
+// Members of one (p, J) pair held per thread while they are ordered: kSortSlots keys
+// (q << 10 | staged index, so the order of the keys is that of q) in LDS, laid out
+// [slot][thread] so that the threads of a wave touch consecutive words.
+constexpr int kSortSlots = 24;
+constexpr int kIdxBits = 10;
+static_assert(kStageCap <= (1 << kIdxBits) && SG_ID_SHIFT + kIdxBits <= 32, "key = q, staged index");
 
-// Scatter: per output pixel and window frame, one pass over the buckets collects the
-// members, an insertion sort on q orders them, and they are written in canonical
-// order. A pair with more than kSortSlots members (dense occluders) emits by repeated
-// minimum instead, one pass over the buckets per member.
+// Scatter: per output pixel and window frame, one pass over the staged buckets
+// collects the members, an insertion sort orders them by q, and they are written in
+// canonical order from the staged records (no source plane is read). A pair with
+// more than kSortSlots members (dense occluders), and every pair of a frame read
+// from global memory, is emitted by repeated minimum instead, one pass over the
+// buckets per member.
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
-    const uint2* __restrict__ rgbd_, const uint16_t* __restrict__ depth_,
-    const Carried* __restrict__ filed, const int64_t* __restrict__ boff, int width, int height, int f, int w, int jlo,
-    int n_j, int rb, float half, int64_t n_buckets, const int64_t* __restrict__ offsets_,
-    uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity, uint32_t* __restrict__ status_) {
-  __shared__ StageLds s;
-  __shared__ int32_t s_q[kSortSlots][kThreads];
-  __shared__ float s_z[kSortSlots][kThreads];
+    const uint16_t* __restrict__ depth_, const Filed* __restrict__ filed, const int64_t* __restrict__ boff,
+    int width, int height, int f, int w, int jlo, int n_j, int rb, float half, int64_t n_buckets,
+    const int64_t* __restrict__ offsets_, uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity,
+    uint32_t* __restrict__ status_) {
+  __shared__ StageLds<true> s;
+  __shared__ uint32_t s_key[kSortSlots][kThreads];
   const int t = threadIdx.x;
   const TileGeom g = tile_geom(width, height, rb);
   const int tx = t % kTile, ty = t / kTile;
@@ -406,44 +436,40 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
   const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
   const float dp = live ? h2f(to_global(depth_)[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]) : 0.0f;
   const bool has_ref = dp > 0.0f && dp < INFINITY;
-  const float inv_width = 1.0f / static_cast<float>(width);
-  gp<const uint2> rgbd = to_global(rgbd_);
   gp<uint32_t> ids = to_global(ids_);
   gp<uint2> crho = to_global(crho_);
   gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t cur = start;
-  // one record: source pixel q of window frame j, carried depth z
-  auto make = [&](int j, uint32_t id_j, int32_t q, float z, uint32_t (&r)[3]) {
-    int qy = static_cast<int>(static_cast<float>(q) * inv_width);  // off by at most one
-    int qx = q - qy * width;
-    if (qx < 0) { --qy; qx += width; }
-    if (qx >= width) { ++qy; qx -= width; }
-    const uint2 v = ld2(rgbd + static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw));
+  // one record from a member's stored colour (r, g, b, depth) and carried depth z
+  auto make = [&](uint32_t id, uint2 c, float z, uint32_t (&r)[3]) {
     const float rho = has_ref ? (z - dp) / dp : __builtin_nanf("");
-    r[0] = v.x;
-    r[1] = (v.y & 0xFFFFu) | (f2h(rho) << 16);
-    r[2] = id_j | static_cast<uint32_t>(q);
+    r[0] = c.x;
+    r[1] = (c.y & 0xFFFFu) | (f2h(rho) << 16);
+    r[2] = id;
   };
-  auto emit = [&](int j, uint32_t id_j, int32_t q, float z) {
+  auto emit = [&](uint32_t id, uint2 c, float z) {
     if (cur < end) {  // a count that changed since pass 1 never writes past the segment
       uint32_t r[3];
-      make(j, id_j, q, z, r);
+      make(id, c, z, r);
       st2(crho + cur, make_uint2(r[0], r[1]));
       ids[cur] = r[2];
     }
     ++cur;
   };
-  // the sorted members in slots [0, n) of this thread, four at a time: the colour
-  // loads of a group are in flight together, and a whole group goes out as two
-  // 16-byte colour stores and one 16-byte id store (a segment position is 8-byte
-  // aligned in crho, 4-byte in ids)
-  auto emit_slots = [&](int j, uint32_t id_j, int n) {
+  // the sorted members in slots [0, n) of this thread, four at a time: a whole group
+  // goes out as two 16-byte colour stores and one 16-byte id store (a segment
+  // position is 8-byte aligned in crho, 4-byte in ids)
+  auto emit_slots = [&](uint32_t id_j, int n) {
     for (int a0 = 0; a0 < n; a0 += 4) {
       const int c = min(4, n - a0);
       uint32_t r[4][3];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (i < c) make(j, id_j, s_q[a0 + i][t], s_z[a0 + i][t], r[i]);
+        if (i < c) {
+          const uint32_t key = s_key[a0 + i][t];
+          const int k = static_cast<int>(key & ((1u << kIdxBits) - 1u));
+          make(id_j | (key >> kIdxBits), s.col[k], __uint_as_float(s.rec[k][2]), r[i]);
+        }
       const int64_t room = end - cur;
       if (c == 4 && room >= 4) {
         gp<u32x4a8> cr = reinterpret_cast<gp<u32x4a8>>(crho + cur);
@@ -461,56 +487,60 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       cur += c;
     }
   };
-  // one window frame's members of this pixel, from the staged records or global memory
-  auto frame = [&](int jn, auto&& members) {
-    const int j = jlo + jn;
-    const uint32_t id_j = static_cast<uint32_t>(j - f + w) << SG_ID_SHIFT;
-    int n = 0;
-    members([&](int32_t q, Carried c) {
-      if (n < kSortSlots) {
-        s_q[n][t] = q;
-        s_z[n][t] = c.z;
-      }
-      ++n;
-    });
-    if (n <= kSortSlots) {
-      for (int a = 1; a < n; ++a) {  // insertion sort on q (q values are distinct)
-        const int32_t qa = s_q[a][t];
-        const float za = s_z[a][t];
-        int b = a - 1;
-        while (b >= 0 && s_q[b][t] > qa) {
-          s_q[b + 1][t] = s_q[b][t];
-          s_z[b + 1][t] = s_z[b][t];
-          --b;
+  // repeated minimum over one pair's members; colour(k) gives a member's stored colour
+  auto emit_by_minimum = [&](uint32_t id_j, auto&& members, auto&& colour) {
+    int32_t last = -1;
+    for (;;) {  // the smallest member above the last emitted
+      int32_t best = INT_MAX;
+      float best_z = 0.0f;
+      int64_t best_k = 0;
+      members([&](int32_t q, float z, int64_t k) {
+        if (q > last && q < best) {
+          best = q;
+          best_z = z;
+          best_k = k;
         }
-        s_q[b + 1][t] = qa;
-        s_z[b + 1][t] = za;
-      }
-      emit_slots(j, id_j, n);
-    } else {
-      int32_t last = -1;
-      for (;;) {  // the smallest member above the last emitted
-        int32_t best = INT_MAX;
-        float best_z = 0.0f;
-        members([&](int32_t q, Carried c) {
-          if (q > last && q < best) {
-            best = q;
-            best_z = c.z;
-          }
-        });
-        if (best == INT_MAX) break;
-        emit(j, id_j, best, best_z);
-        last = best;
-      }
+      });
+      if (best == INT_MAX) break;
+      emit(id_j | static_cast<uint32_t>(best), colour(best_k), best_z);
+      last = best;
     }
   };
   for (int jn = 0; jn < n_j; ++jn) {
+    const uint32_t id_j = static_cast<uint32_t>(jlo + jn - f + w) << SG_ID_SHIFT;
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    if (stage_frame(filed4, bj, ew, rb, g, s)) {
-      if (live) frame(jn, [&](auto&& fn) { for_members_staged(s, rb, half, tx, ty, x, y, fn); });
+    if (stage_frame(filed4, bj, ew, g, s)) {
+      if (live) {
+        auto members = [&](auto&& fn) { for_members_staged(s, rb, half, tx, ty, x, y, fn); };
+        int n = 0;
+        members([&](int32_t q, float, int k) {
+          if (n < kSortSlots) s_key[n][t] = (static_cast<uint32_t>(q) << kIdxBits) | static_cast<uint32_t>(k);
+          ++n;
+        });
+        if (n <= kSortSlots) {
+          for (int a = 1; a < n; ++a) {  // insertion sort (keys are distinct)
+            const uint32_t ka = s_key[a][t];
+            int b = a - 1;
+            while (b >= 0 && s_key[b][t] > ka) {
+              s_key[b + 1][t] = s_key[b][t];
+              --b;
+            }
+            s_key[b + 1][t] = ka;
+          }
+          emit_slots(id_j, n);
+        } else {
+          emit_by_minimum(id_j, [&](auto&& fn) { members([&](int32_t q, float z, int k) { fn(q, z, k); }); },
+                          [&](int64_t k) { return s.col[k]; });
+        }
+      }
       __syncthreads();
     } else if (live) {
-      frame(jn, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); });
+      emit_by_minimum(
+          id_j, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); },
+          [&](int64_t k) {
+            const u32x4 c = filed4[2 * k + 1];
+            return make_uint2(c[0], c[1]);
+          });
     }
   }
   if (live && cur != end) flag_or(status, SG_FLAG_INCONSISTENT);
@@ -532,10 +562,9 @@ sg_status check_frustum(const sg_clip* clip, int32_t f, const sg_frustum_params*
 struct FrustumCall {
   FrustumLayout l;
   float* maps;
-  Carried* carry;
+  int2* slots;
   int64_t* boff;
-  int32_t* bfill;
-  Carried* filed;
+  Filed* filed;
   int64_t* partial;
 };
 
@@ -550,10 +579,9 @@ sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_param
   if (ws_bytes < c->l.total) return SG_E_INVALID;
   char* base = static_cast<char*>(ws);
   c->maps = reinterpret_cast<float*>(base + c->l.maps);
-  c->carry = reinterpret_cast<Carried*>(base + c->l.carry);
+  c->slots = reinterpret_cast<int2*>(base + c->l.slots);
   c->boff = reinterpret_cast<int64_t*>(base + c->l.boff);
-  c->bfill = reinterpret_cast<int32_t*>(base + c->l.bfill);
-  c->filed = reinterpret_cast<Carried*>(base + c->l.items);
+  c->filed = reinterpret_cast<Filed*>(base + c->l.items);
   c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
   return SG_OK;
 }
@@ -596,15 +624,15 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
   const float half = 0.5f * params->l;
   hipLaunchKernelGGL(sg::k_zero<int64_t>, dim3(sg::zero_blocks(n_bk + 1)), dim3(sg::kThreads), 0, st, c.boff,
                      n_bk + 1);
-  hipLaunchKernelGGL(sg::k_zero<int32_t>, dim3(sg::zero_blocks(n_bk)), dim3(sg::kThreads), 0, st, c.bfill, n_bk);
   hipLaunchKernelGGL(sg::k_frustum_pose, dim3(1), dim3(64), 0, st, clip->cam_to_world, f, l.jlo, l.n_j, clip->fx,
                      clip->fy, clip->cx, clip->cy, c.maps, sets->status);
   hipLaunchKernelGGL(sg::k_frustum_carry, per_pixel_frame, dim3(sg::kThreads), 0, st, clip->depth, c.maps,
                      clip->width, clip->height, l.jlo, l.rb, params->near_z, params->far_z, l.n_pix, l.n_buckets,
-                     c.carry, reinterpret_cast<unsigned long long*>(c.boff));
+                     c.slots, reinterpret_cast<unsigned long long*>(c.boff));
   if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
-  hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st, c.carry, c.boff, c.bfill,
-                     l.n_pix, l.n_buckets, c.filed);
+  hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st,
+                     reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.maps, clip->width, clip->height,
+                     l.jlo, l.rb, params->near_z, params->far_z, c.slots, c.boff, l.n_pix, l.n_buckets, c.filed);
   hipLaunchKernelGGL(sg::k_frustum_count, sg::tile_grid(clip), dim3(sg::kThreads), 0, st, c.filed, c.boff,
                      clip->width, clip->height, l.n_j, l.rb, half, l.n_buckets, sets->offsets + 1);
   return hip_status(sg::launch_scan(sets->offsets, l.n_pix, c.partial, st));
@@ -617,7 +645,7 @@ sg_status scene_frustum_scatter(const sg_clip* clip, int32_t f, const sg_frustum
   if (s != SG_OK) return s;
   const sg::FrustumLayout& l = c.l;
   hipLaunchKernelGGL(sg::k_frustum_scatter, sg::tile_grid(clip), dim3(sg::kThreads), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const uint2*>(clip->rgbd), clip->depth,
+                     static_cast<hipStream_t>(stream), clip->depth,
                      c.filed, c.boff, clip->width, clip->height, f, params->window, l.jlo, l.n_j, l.rb,
                      0.5f * params->l, l.n_buckets,
                      sets->offsets, sets->ids, reinterpret_cast<uint2*>(sets->crho), sets->capacity, sets->status);
