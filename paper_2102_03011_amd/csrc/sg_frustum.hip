@@ -268,19 +268,33 @@ __device__ __forceinline__ TileGeom tile_geom(int width, int height, int rb) {
   return g;
 }
 
-// Stages window frame jn's reachable records; false (nothing staged) when they
-// number more than kStageCap. Every thread of the workgroup calls it; it ends on a
-// barrier either way, and the caller puts one between its last read of the staged
-// records and the next call.
+// The first and end filed index of staged row t (threads t < nrows) of a window
+// frame: loaded one frame ahead, while the workgroup works on the frame before.
+struct RowSpan {
+  int64_t a, e;
+};
+__device__ __forceinline__ RowSpan row_span(gp<const int64_t> bj, int ew, const TileGeom& g) {
+  const int t = threadIdx.x;
+  RowSpan r{0, 0};
+  if (t < g.nrows) {
+    const int64_t row = static_cast<int64_t>(g.ty0 + t) * ew + g.tx0;
+    r.a = bj[row];
+    r.e = bj[row + g.ncols];
+  }
+  return r;
+}
+
+// Stages window frame jn's reachable records (rs: this thread's row_span of jn);
+// false (nothing staged) when they number more than kStageCap. Every thread of the
+// workgroup calls it; it ends on a barrier either way, and the caller puts one
+// between its last read of the staged records and the next call.
 template <bool kColour>
-__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g,
+__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g, RowSpan rs,
                             StageLds<kColour>& s) {
   const int t = threadIdx.x;
   if (t < g.nrows) {
-    const int64_t row = static_cast<int64_t>(g.ty0 + t) * ew + g.tx0;
-    const int64_t a = bj[row], e = bj[row + g.ncols];
-    s.first[t] = a;
-    s.base[t + 1] = static_cast<int32_t>(min(e - a, static_cast<int64_t>(kStageCap) + 1));
+    s.first[t] = rs.a;
+    s.base[t + 1] = static_cast<int32_t>(min(rs.e - rs.a, static_cast<int64_t>(kStageCap) + 1));
   }
   __syncthreads();
   if (t == 0) {  // row starts (at most kStageSide rows; clamped counts cannot overflow)
@@ -378,9 +392,12 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restr
   const int ew = width + 2 * rb;
   gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t n = 0;
+  RowSpan next = row_span(to_global(boff), ew, g);
   for (int jn = 0; jn < n_j; ++jn) {
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    if (stage_frame(filed4, bj, ew, g, s)) {
+    const RowSpan rs = next;
+    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g);
+    if (stage_frame(filed4, bj, ew, g, rs, s)) {
       if (in) for_members_staged(s, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
       __syncthreads();
     } else if (in) {
@@ -390,26 +407,46 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restr
   if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
 }
 
-// Members of one (p, J) pair held per thread while they are ordered: kSortSlots keys
-// (q << 10 | staged index, so the order of the keys is that of q) in LDS, laid out
-// [slot][thread] so that the threads of a wave touch consecutive words.
-constexpr int kSortSlots = 24;
+// Members of one (p, J) pair held per thread while they are ordered: up to
+// kSortSlots keys (q << 10 | staged index, so the order of the keys is that of q) in
+// registers, put in order by a sorting network.
+constexpr int kSortSlots = 16;
 constexpr int kIdxBits = 10;
 static_assert(kStageCap <= (1 << kIdxBits) && SG_ID_SHIFT + kIdxBits <= 32, "key = q, staged index");
 
+// Bitonic sorting network over keys k[0 .. N) (ascending; N a power of two); fully
+// unrolled, so every compare-exchange is one minimum and one maximum.
+template <int N>
+__device__ __forceinline__ void sort_keys(uint32_t (&k)[kSortSlots]) {
+  static_assert(N <= kSortSlots && (N & (N - 1)) == 0, "power of two within the slots");
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ stride;
+        if (l > i) {
+          const uint32_t a = k[i], b = k[l];
+          const bool up = (i & size) == 0;
+          k[i] = up ? min(a, b) : max(a, b);
+          k[l] = up ? max(a, b) : min(a, b);
+        }
+      }
+}
+
 // Scatter: per output pixel and window frame, one pass over the staged buckets
-// collects the members, an insertion sort orders them by q, and they are written in
-// canonical order from the staged records (no source plane is read). A pair with
-// more than kSortSlots members (dense occluders), and every pair of a frame read
-// from global memory, is emitted by repeated minimum instead, one pass over the
-// buckets per member.
+// collects the members' keys, a sorting network orders them by q, and they are
+// written in canonical order from the staged records (no source plane is read). A
+// pair with more than kSortSlots members (dense occluders), and every pair of a
+// frame read from global memory, is emitted by repeated minimum instead, one pass
+// over the buckets per member.
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     const uint16_t* __restrict__ depth_, const Filed* __restrict__ filed, const int64_t* __restrict__ boff,
     int width, int height, int f, int w, int jlo, int n_j, int rb, float half, int64_t n_buckets,
     const int64_t* __restrict__ offsets_, uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity,
     uint32_t* __restrict__ status_) {
   __shared__ StageLds<true> s;
-  __shared__ uint32_t s_key[kSortSlots][kThreads];
   const int t = threadIdx.x;
   const TileGeom g = tile_geom(width, height, rb);
   const int tx = t % kTile, ty = t / kTile;
@@ -456,17 +493,19 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     }
     ++cur;
   };
-  // the sorted members in slots [0, n) of this thread, four at a time: a whole group
-  // goes out as two 16-byte colour stores and one 16-byte id store (a segment
-  // position is 8-byte aligned in crho, 4-byte in ids)
-  auto emit_slots = [&](uint32_t id_j, int n) {
-    for (int a0 = 0; a0 < n; a0 += 4) {
+  // the sorted keys key[0 .. n), four at a time: a whole group goes out as two
+  // 16-byte colour stores and one 16-byte id store (a segment position is 8-byte
+  // aligned in crho, 4-byte in ids)
+  auto emit_sorted = [&](uint32_t id_j, const uint32_t (&keys)[kSortSlots], int n) {
+#pragma unroll
+    for (int a0 = 0; a0 < kSortSlots; a0 += 4) {
+      if (a0 >= n) break;
       const int c = min(4, n - a0);
       uint32_t r[4][3];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (i < c) {
-          const uint32_t key = s_key[a0 + i][t];
+          const uint32_t key = keys[a0 + i];
           const int k = static_cast<int>(key & ((1u << kIdxBits) - 1u));
           make(id_j | (key >> kIdxBits), s.col[k], __uint_as_float(s.rec[k][2]), r[i]);
         }
@@ -506,28 +545,32 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       last = best;
     }
   };
+  RowSpan next = row_span(to_global(boff), ew, g);
   for (int jn = 0; jn < n_j; ++jn) {
     const uint32_t id_j = static_cast<uint32_t>(jlo + jn - f + w) << SG_ID_SHIFT;
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    if (stage_frame(filed4, bj, ew, g, s)) {
+    const RowSpan rs = next;
+    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g);
+    if (stage_frame(filed4, bj, ew, g, rs, s)) {
       if (live) {
         auto members = [&](auto&& fn) { for_members_staged(s, rb, half, tx, ty, x, y, fn); };
+        // keys pushed in front (static register indices); UINT32_MAX pads the rest
+        uint32_t keys[kSortSlots];
+#pragma unroll
+        for (int i = 0; i < kSortSlots; ++i) keys[i] = 0xFFFFFFFFu;
         int n = 0;
         members([&](int32_t q, float, int k) {
-          if (n < kSortSlots) s_key[n][t] = (static_cast<uint32_t>(q) << kIdxBits) | static_cast<uint32_t>(k);
+#pragma unroll
+          for (int i = kSortSlots - 1; i > 0; --i) keys[i] = keys[i - 1];
+          keys[0] = (static_cast<uint32_t>(q) << kIdxBits) | static_cast<uint32_t>(k);
           ++n;
         });
         if (n <= kSortSlots) {
-          for (int a = 1; a < n; ++a) {  // insertion sort (keys are distinct)
-            const uint32_t ka = s_key[a][t];
-            int b = a - 1;
-            while (b >= 0 && s_key[b][t] > ka) {
-              s_key[b + 1][t] = s_key[b][t];
-              --b;
-            }
-            s_key[b + 1][t] = ka;
-          }
-          emit_slots(id_j, n);
+          if (__any(n > kSortSlots / 2))
+            sort_keys<kSortSlots>(keys);
+          else
+            sort_keys<kSortSlots / 2>(keys);
+          emit_sorted(id_j, keys, n);
         } else {
           emit_by_minimum(id_j, [&](auto&& fn) { members([&](int32_t q, float z, int k) { fn(q, z, k); }); },
                           [&](int64_t k) { return s.col[k]; });
