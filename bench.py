@@ -359,11 +359,13 @@ def frustum_leg(sg, clip, staged, f, window: int, reps: int) -> dict:
     total = sets.total()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    for _ in range(reps):
-        sg.scene_gather_frustum(staged, f, prm, capacity=total, ws=ws)
+    for _ in range(reps):   # count + scatter into the same arena, as the plain step reuses its own
+        sg.scene_gather_frustum(staged, f, prm, ws=ws, sets=sets)
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
+    sets.check()
+    assert sets.total() == total
     n_pix = clip.height * clip.width
     res = {"window": window, "output_frame": f, "ms_per_frame": ms, "records": total,
            "records_per_pixel": total / n_pix, "records_per_s": total / (ms / 1e3),

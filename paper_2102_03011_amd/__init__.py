@@ -284,23 +284,30 @@ def scene_frustum_workspace_size(clip: StagedClip, f: int, params: FrustumParams
 
 
 def scene_gather_frustum(clip: StagedClip, f: int, params: FrustumParams, capacity: int | None = None,
-                         ws: torch.Tensor | None = None) -> SampleSets:
+                         ws: torch.Tensor | None = None, sets: SampleSets | None = None) -> SampleSets:
     """Sample sets of output frame f by the depth-agnostic frustum test (every
     observation along each pixel's ray). capacity None: count, synchronise, size
     the arena exactly, scatter; otherwise the arena holds `capacity` records (check
-    `sets.check()` afterwards)."""
+    `sets.check()` afterwards). `sets`: an arena of output frame f to fill in place
+    (no allocation, no synchronisation; capacity is then its own)."""
     if ws is None:
         ws = torch.empty(scene_frustum_workspace_size(clip, f, params), dtype=torch.uint8, device=clip.rgbd.device)
     _need_gpu(ws, "workspace", torch.uint8)
     cc, pp = clip.c_struct(), params.c_struct()
-    tmp = alloc_sets(clip, f, f + 1, params.window, 0)
+    if sets is not None:
+        if sets.f0 != f or sets.f1 != f + 1 or sets.window != params.window:
+            raise ValueError("sets must hold output frame f with the window of params")
+        tmp = sets
+    else:
+        tmp = alloc_sets(clip, f, f + 1, params.window, 0)
     ts = tmp.c_struct()
     _check(_lib.scene_frustum_count(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ts), ws.data_ptr(),
                                     ws.numel(), _stream_handle()), "scene_frustum_count")
-    if capacity is None:
-        capacity = tmp.total()
-    sets = alloc_sets(clip, f, f + 1, params.window, capacity)
-    sets.offsets.copy_(tmp.offsets)
+    if sets is None:
+        if capacity is None:
+            capacity = tmp.total()
+        sets = alloc_sets(clip, f, f + 1, params.window, capacity)
+        sets.offsets.copy_(tmp.offsets)
     ss = sets.c_struct()
     _check(_lib.scene_frustum_scatter(ctypes.byref(cc), f, ctypes.byref(pp), ctypes.byref(ss), ws.data_ptr(),
                                       ws.numel(), _stream_handle()), "scene_frustum_scatter")

@@ -190,3 +190,28 @@ def test_frustum_dense_frame_matches_oracle():
     st = parity.compare_frustum(orc, g_off, g_ids, g_crho, dep[f].reshape(-1)[orc.pixels])
     assert st["members_checked"] > 0.95 * orc.offsets[-1]
     print(st, "tile reach", reach)
+
+
+def test_frustum_in_place_arena_matches_fresh_sets():
+    """scene_gather_frustum(sets=...) fills a given arena without allocating or
+    synchronising; twice in a row into the same arena it gives the fresh call's sets."""
+    wl, clip, staged, col, dep, f, orc = _case("ragged")
+    sg = _sg()
+    prm = sg.FrustumParams(window=wl.window)
+    exact = sg.scene_gather_frustum(staged, f, prm)
+    total = exact.total()
+    arena = sg.alloc_sets(staged, f, f + 1, wl.window, total + 17)
+    ws = torch.empty(sg.scene_frustum_workspace_size(staged, f, prm), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        arena.ids.fill_(-3)
+        out = sg.scene_gather_frustum(staged, f, prm, ws=ws, sets=arena)
+        assert out is arena
+        torch.cuda.synchronize()
+        arena.check()
+        assert torch.equal(arena.offsets, exact.offsets)
+        assert torch.equal(arena.ids[:total], exact.ids[:total])
+        # bit patterns: rho is NaN for pixels without a valid depth of their own
+        assert torch.equal(arena.crho[:total].view(torch.int16), exact.crho[:total].view(torch.int16))
+        assert bool((arena.ids[total:] == -3).all())
+    with pytest.raises(ValueError):
+        sg.scene_gather_frustum(staged, f + 1, prm, ws=ws, sets=arena)
