@@ -48,12 +48,12 @@ def hd_plain(seed: int = 1, n_frames: int = 120) -> Workload:
 
 
 def full_scale(seed: int = 5, n_frames: int = 300) -> Workload:
-    """1920x1080, 300 frames, 60 static + 5 moving boxes, window +-50."""
+    """1920x1080, 300 frames (n_frames: a shorter version), 60 static + 5 moving boxes, window +-50."""
     rot, tr = _pose_scaled(1920)
     spec = SceneSpec(width=1920, height=1080, n_frames=n_frames, n_static=60, n_moving=5,
                      colour_sigma=10 / 255, depth_noise=0.03, outlier_frac=0.02,
                      pose_rot_deg=rot, pose_trans_m=tr, seed=seed)
-    return Workload("denoise-1920x1080-300f-w50", spec, window=50)
+    return Workload(f"denoise-1920x1080-{n_frames}f-w50", spec, window=50)
 
 
 def batched_clips(n_clips: int = 32, seed0: int = 100) -> list[Workload]:
