@@ -60,7 +60,7 @@ size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
 struct FrustumLayout {
   int jlo, n_j, rb;
   int64_t n_pix, n_buckets;  // per window frame
-  size_t maps, slots, boff, items, partial, total;
+  size_t maps, slots, counts, boff, items, partial, total;
 };
 
 FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_params* p) {
@@ -78,6 +78,8 @@ FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_param
   at += align_up(static_cast<size_t>(l.n_j) * kMapFloats * sizeof(float));
   l.slots = at;
   at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(int2));
+  l.counts = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_buckets * sizeof(uint32_t));
   l.boff = at;
   at += align_up((static_cast<size_t>(l.n_j) * l.n_buckets + 1) * sizeof(int64_t));
   l.items = at;
@@ -93,6 +95,15 @@ __global__ __launch_bounds__(kThreads) void k_zero(T* __restrict__ p, int64_t n)
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads)
     p[i] = T(0);
+}
+
+// offsets[0] = 0, offsets[1 + i] = counts[i]: the 32-bit bucket counters widened for
+// the 64-bit scan
+__global__ __launch_bounds__(kThreads) void k_widen(const uint32_t* __restrict__ counts, int64_t n,
+                                                    int64_t* __restrict__ offsets) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i <= n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    offsets[i] = i == 0 ? 0 : static_cast<int64_t>(counts[i - 1]);
 }
 
 // (C^f)^-1 C^J in float64 (rigid: the inverse rotation is the transpose), folded
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __re
                                                             const float* __restrict__ maps, int width, int height,
                                                             int jlo, int rb, float near_z, float far_z, int64_t n_pix,
                                                             int64_t n_buckets, int2* __restrict__ slots,
-                                                            unsigned long long* __restrict__ bcount) {
+                                                            unsigned int* __restrict__ bcount) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (q >= n_pix) return;
   const int jn = blockIdx.y;
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_carry(const uint16_t* __re
                             near_z, far_z, px, py, z);
   int slot = 0;
   if (b >= 0)
-    slot = static_cast<int>(atomicAdd(bcount + 1 + static_cast<int64_t>(jn) * n_buckets + b, 1ull));
+    slot = static_cast<int>(atomicAdd(bcount + static_cast<int64_t>(jn) * n_buckets + b, 1u));
   slots[static_cast<int64_t>(jn) * n_pix + q] = make_int2(b, slot);
 }
 
@@ -239,7 +250,7 @@ __device__ __forceinline__ void for_members(const Filed* __restrict__ filed_, co
 constexpr int kTile = 16;
 constexpr int kMaxRb = 4;  // bucket_radius(SG_MAX_FRUSTUM_L)
 constexpr int kStageSide = kTile + 2 * kMaxRb;
-constexpr int kStageCap = 1024;
+constexpr int kStageCap = 768;
 constexpr int kBoundsPerThread = (kStageSide * (kStageSide + 1) + kThreads - 1) / kThreads;
 static_assert(kThreads == kTile * kTile, "one thread per pixel of a tile");
 
@@ -273,26 +284,28 @@ __device__ __forceinline__ TileGeom tile_geom(int width, int height, int rb) {
 struct RowSpan {
   int64_t a, e;
 };
-__device__ __forceinline__ RowSpan row_span(gp<const int64_t> bj, int ew, const TileGeom& g) {
+__device__ __forceinline__ RowSpan row_span(gp<const int64_t> bj, int ew, const TileGeom& g, int r0, int r1) {
   const int t = threadIdx.x;
   RowSpan r{0, 0};
-  if (t < g.nrows) {
-    const int64_t row = static_cast<int64_t>(g.ty0 + t) * ew + g.tx0;
+  if (t < r1 - r0) {
+    const int64_t row = static_cast<int64_t>(g.ty0 + r0 + t) * ew + g.tx0;
     r.a = bj[row];
     r.e = bj[row + g.ncols];
   }
   return r;
 }
 
-// Stages window frame jn's reachable records (rs: this thread's row_span of jn);
-// false (nothing staged) when they number more than kStageCap. Every thread of the
-// workgroup calls it; it ends on a barrier either way, and the caller puts one
-// between its last read of the staged records and the next call.
+// Stages the tile's bucket rows [r0, r1) of one window frame (rs: this thread's
+// row_span of those rows); false (nothing staged) when their records number more
+// than kStageCap. Every thread of the workgroup calls it; it ends on a barrier
+// either way, and the caller puts one between its last read of the staged records
+// and the next call.
 template <bool kColour>
-__device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g, RowSpan rs,
-                            StageLds<kColour>& s) {
+__device__ bool stage_rows(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g, int r0, int r1,
+                           RowSpan rs, StageLds<kColour>& s) {
   const int t = threadIdx.x;
-  if (t < g.nrows) {
+  const int nr = r1 - r0;
+  if (t < nr) {
     s.first[t] = rs.a;
     s.base[t + 1] = static_cast<int32_t>(min(rs.e - rs.a, static_cast<int64_t>(kStageCap) + 1));
   }
@@ -300,13 +313,13 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
   if (t == 0) {  // row starts (at most kStageSide rows; clamped counts cannot overflow)
     int acc = 0;
     s.base[0] = 0;
-    for (int r = 0; r < g.nrows; ++r) {
+    for (int r = 0; r < nr; ++r) {
       acc = min(acc + s.base[r + 1], kStageCap + 1);
       s.base[r + 1] = acc;
     }
   }
   __syncthreads();
-  const int total = s.base[g.nrows];
+  const int total = s.base[nr];
   if (total > kStageCap) {  // uniform: every thread read the same LDS word
     __syncthreads();        // ... before the next call rewrites it
     return false;
@@ -317,10 +330,10 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
 #pragma unroll
   for (int k = 0; k < kBoundsPerThread; ++k) {
     const int i = t + k * kThreads;
-    ib[k] = i < g.nrows * (g.ncols + 1) ? i : -1;
+    ib[k] = i < nr * (g.ncols + 1) ? i : -1;
     if (ib[k] >= 0) {
       const int r = i / (g.ncols + 1), c = i - r * (g.ncols + 1);
-      gb[k] = bj[static_cast<int64_t>(g.ty0 + r) * ew + g.tx0 + c];
+      gb[k] = bj[static_cast<int64_t>(g.ty0 + r0 + r) * ew + g.tx0 + c];
     }
   }
   constexpr int kRecPerThread = kStageCap / kThreads;
@@ -331,7 +344,7 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
   for (int k = 0; k < kRecPerThread; ++k) {
     const int i = t + k * kThreads;
     if (i < total) {
-      int lo = 0, hi = g.nrows - 1;  // row r with base[r] <= i < base[r + 1]
+      int lo = 0, hi = nr - 1;  // row r with base[r] <= i < base[r + 1]
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s.base[mid] <= i) lo = mid; else hi = mid - 1;
@@ -361,20 +374,58 @@ __device__ bool stage_frame(gp<const u32x4> filed, gp<const int64_t> bj, int ew,
   return true;
 }
 
-// for_members over the staged records: fn(q, z', staged index) (thread's pixel
-// (x, y) = (tx0 + tx, ty0 + ty)).
+// for_members over the staged records of rows [r0, ...): fn(q, z', staged index)
+// (thread's pixel (x, y) = (tx0 + tx, ty0 + ty)).
 template <bool kColour, typename Fn>
-__device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, int rb, float half, int tx, int ty,
-                                                   int x, int y, Fn&& fn) {
+__device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, int r0, int rb, float half, int tx,
+                                                   int ty, int x, int y, Fn&& fn) {
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
   for (int dy = -rb; dy <= rb; ++dy) {
     const int span = rb - (dy < 0 ? -dy : dy);
-    const int r = ty + dy + rb;
+    const int r = ty + dy + rb - r0;
     const int k0 = s.loc[r][tx + rb - span], k1 = s.loc[r][tx + rb + span + 1];
     for (int k = k0; k < k1; ++k) {
       const u32x4 w = s.rec[k];
       if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
         fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
+    }
+  }
+}
+
+// Runs body(staged, r0, mine) for one window frame over the staged records: the
+// whole tile at once or, when its reachable records outgrow the stage, halves,
+// quarters, ... of its pixel rows one after the other (pixel rows [r0, r0 + n)
+// need staged bucket rows [r0, r0 + n + 2 rb)); a single pixel row that still does
+// not fit runs body with staged = false (read from global memory). Every thread
+// calls it, and body runs for every thread of the workgroup (mine: the thread's
+// pixel row belongs to the current part); body may not use barriers.
+template <bool kColour, typename Body>
+__device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const int64_t> bj, int ew, int rb,
+                                                 int height, const TileGeom& g, int ty, RowSpan rs,
+                                                 StageLds<kColour>& s, Body&& body) {
+  if (stage_rows(filed, bj, ew, g, 0, g.nrows, rs, s)) {
+    body(true, 0, true);
+    __syncthreads();
+    return;
+  }
+  const int prows = min(kTile, height - g.ty0);  // pixel rows of the tile inside the image
+  uint32_t todo = (1u << prows) - 1u;            // pixel rows not yet done (uniform)
+#pragma unroll 1
+  for (int np = kTile / 2; np >= 1 && todo != 0u; np >>= 1) {
+#pragma unroll 1
+    for (int r0 = 0; r0 < kTile; r0 += np) {
+      const uint32_t part = ((1u << np) - 1u) << r0;
+      if ((todo & part) == 0u) continue;  // done, or no pixel rows
+      const int r1 = min(g.nrows, r0 + np + 2 * rb);
+      const bool mine = ty >= r0 && ty < r0 + np;
+      if (stage_rows(filed, bj, ew, g, r0, r1, row_span(bj, ew, g, r0, r1), s)) {
+        body(true, r0, mine);
+        __syncthreads();
+        todo &= ~part;
+      } else if (np == 1) {
+        body(false, r0, mine);
+        todo &= ~part;
+      }
     }
   }
 }
@@ -392,17 +443,18 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restr
   const int ew = width + 2 * rb;
   gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t n = 0;
-  RowSpan next = row_span(to_global(boff), ew, g);
+  RowSpan next = row_span(to_global(boff), ew, g, 0, g.nrows);
   for (int jn = 0; jn < n_j; ++jn) {
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
     const RowSpan rs = next;
-    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g);
-    if (stage_frame(filed4, bj, ew, g, rs, s)) {
-      if (in) for_members_staged(s, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
-      __syncthreads();
-    } else if (in) {
-      for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, float, int64_t) { ++n; });
-    }
+    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
+    for_frame_staged(filed4, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
+      if (!in || !mine) return;
+      if (staged)
+        for_members_staged(s, r0, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
+      else
+        for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, float, int64_t) { ++n; });
+    });
   }
   if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
 }
@@ -435,26 +487,81 @@ __device__ __forceinline__ void sort_keys(uint32_t (&k)[kSortSlots]) {
       }
 }
 
+// Records held per lane between window frames (odd: the lanes' appends at one slot
+// index fall in different LDS banks), written out as runs.
+constexpr int kBufSlots = 9;
+constexpr int kRunLanes = 16;  // lanes writing one run (>= kBufSlots)
+static_assert(kBufSlots <= kRunLanes && (kBufSlots & 1) == 1, "a run fits its lane group; odd stride");
+
+struct RecordBuf {
+  uint32_t rec[3 * 64 * kBufSlots];  // lane l, slot i: colour + rho (2 words), id at 3 (l kBufSlots + i)
+  int n[64];
+  int64_t dst[64];
+};
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Writes the nflush buffered records of every lane (0: the lane keeps its
+// records) to [cur, cur + nflush) of its segment; every lane of the wave calls
+// it. The flushing lanes' (count, destination) pairs are compacted into a list,
+// and each group of kRunLanes lanes writes one list entry's run, so a store
+// instruction writes 64 / kRunLanes runs instead of 64 scattered pieces.
+__device__ __forceinline__ void flush_records(int nflush, int64_t& cur, int& fill, RecordBuf& b, gp<uint32_t> ids,
+                                              gp<uint2> crho) {
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const uint64_t flushing = __ballot(nflush > 0);
+  const int n_list = __popcll(flushing);
+  if (nflush > 0) {
+    const int rank = __popcll(flushing & ((static_cast<uint64_t>(1) << lane) - 1));
+    b.n[rank] = (lane << 8) | nflush;
+    b.dst[rank] = cur;
+  }
+  wave_fence();
+  const int sub = lane % kRunLanes, grp = lane / kRunLanes;
+  for (int base = 0; base < n_list; base += 64 / kRunLanes) {
+    const int e = base + grp;
+    if (e < n_list) {
+      const int on = b.n[e];
+      const int own = on >> 8, cnt = on & 0xFF;
+      if (sub < cnt) {
+        const int64_t dst = b.dst[e] + sub;
+        const uint32_t* slot = b.rec + 3 * (own * kBufSlots + sub);
+        st2(crho + dst, make_uint2(slot[0], slot[1]));
+        ids[dst] = slot[2];
+      }
+    }
+  }
+  wave_fence();
+  cur += nflush;
+  fill -= nflush;
+}
+
 // Scatter: per output pixel and window frame, one pass over the staged buckets
-// collects the members' keys, a sorting network orders them by q, and they are
-// written in canonical order from the staged records (no source plane is read). A
-// pair with more than kSortSlots members (dense occluders), and every pair of a
-// frame read from global memory, is emitted by repeated minimum instead, one pass
-// over the buckets per member.
+// collects the members' keys and a sorting network orders them by q; the records
+// (colour and carried depth from the staged records, no source plane is read) go
+// to a per-lane buffer in LDS, written out in runs when a lane's buffer cannot take
+// the next frame's members. A pair with more members than the buffer holds is
+// written directly after the lane's buffer (by repeated minimum past kSortSlots
+// members, as is every pair of a half-tile read from global memory).
 __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     const uint16_t* __restrict__ depth_, const Filed* __restrict__ filed, const int64_t* __restrict__ boff,
     int width, int height, int f, int w, int jlo, int n_j, int rb, float half, int64_t n_buckets,
     const int64_t* __restrict__ offsets_, uint32_t* __restrict__ ids_, uint2* __restrict__ crho_, int64_t capacity,
     uint32_t* __restrict__ status_) {
   __shared__ StageLds<true> s;
-  const int t = threadIdx.x;
+  __shared__ RecordBuf s_buf[kThreads / 64];
+  const int t = threadIdx.x, lane = t & 63;
+  RecordBuf& buf = s_buf[t >> 6];
   const TileGeom g = tile_geom(width, height, rb);
   const int tx = t % kTile, ty = t / kTile;
   const int x = g.tx0 + tx, y = g.ty0 + ty;
   const int ew = width + 2 * rb;
   gp<uint32_t> status = to_global(status_);
   // a thread outside the image, or whose segment cannot be written, only joins the
-  // staging (every thread reaches every barrier)
+  // staging and its wave's flushes (every thread reaches every barrier)
   bool live = x < width && y < height;
   const int64_t p = static_cast<int64_t>(y) * width + x;
   int64_t start = 0, end = 0;
@@ -476,7 +583,9 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
   gp<uint32_t> ids = to_global(ids_);
   gp<uint2> crho = to_global(crho_);
   gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
-  int64_t cur = start;
+  int64_t cur = start;  // segment position of the buffer's first record
+  int fill = 0;         // records in the buffer
+  int64_t found = 0;    // members met (the count pass's total when nothing changed)
   // one record from a member's stored colour (r, g, b, depth) and carried depth z
   auto make = [&](uint32_t id, uint2 c, float z, uint32_t (&r)[3]) {
     const float rho = has_ref ? (z - dp) / dp : __builtin_nanf("");
@@ -484,8 +593,9 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     r[1] = (c.y & 0xFFFFu) | (f2h(rho) << 16);
     r[2] = id;
   };
+  // direct writes at cur (the buffer is empty), never past the segment
   auto emit = [&](uint32_t id, uint2 c, float z) {
-    if (cur < end) {  // a count that changed since pass 1 never writes past the segment
+    if (cur < end) {
       uint32_t r[3];
       make(id, c, z, r);
       st2(crho + cur, make_uint2(r[0], r[1]));
@@ -493,40 +603,6 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     }
     ++cur;
   };
-  // the sorted keys key[0 .. n), four at a time: a whole group goes out as two
-  // 16-byte colour stores and one 16-byte id store (a segment position is 8-byte
-  // aligned in crho, 4-byte in ids)
-  auto emit_sorted = [&](uint32_t id_j, const uint32_t (&keys)[kSortSlots], int n) {
-#pragma unroll
-    for (int a0 = 0; a0 < kSortSlots; a0 += 4) {
-      if (a0 >= n) break;
-      const int c = min(4, n - a0);
-      uint32_t r[4][3];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i < c) {
-          const uint32_t key = keys[a0 + i];
-          const int k = static_cast<int>(key & ((1u << kIdxBits) - 1u));
-          make(id_j | (key >> kIdxBits), s.col[k], __uint_as_float(s.rec[k][2]), r[i]);
-        }
-      const int64_t room = end - cur;
-      if (c == 4 && room >= 4) {
-        gp<u32x4a8> cr = reinterpret_cast<gp<u32x4a8>>(crho + cur);
-        cr[0] = u32x4a8{r[0][0], r[0][1], r[1][0], r[1][1]};
-        cr[1] = u32x4a8{r[2][0], r[2][1], r[3][0], r[3][1]};
-        *reinterpret_cast<gp<u32x4a4>>(ids + cur) = u32x4a4{r[0][2], r[1][2], r[2][2], r[3][2]};
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < c && i < room) {
-            st2(crho + cur + i, make_uint2(r[i][0], r[i][1]));
-            ids[cur + i] = r[i][2];
-          }
-      }
-      cur += c;
-    }
-  };
-  // repeated minimum over one pair's members; colour(k) gives a member's stored colour
   auto emit_by_minimum = [&](uint32_t id_j, auto&& members, auto&& colour) {
     int32_t last = -1;
     for (;;) {  // the smallest member above the last emitted
@@ -545,48 +621,81 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       last = best;
     }
   };
-  RowSpan next = row_span(to_global(boff), ew, g);
+  RowSpan next = row_span(to_global(boff), ew, g, 0, g.nrows);
   for (int jn = 0; jn < n_j; ++jn) {
     const uint32_t id_j = static_cast<uint32_t>(jlo + jn - f + w) << SG_ID_SHIFT;
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
     const RowSpan rs = next;
-    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g);
-    if (stage_frame(filed4, bj, ew, g, rs, s)) {
-      if (live) {
-        auto members = [&](auto&& fn) { for_members_staged(s, rb, half, tx, ty, x, y, fn); };
-        // keys pushed in front (static register indices); UINT32_MAX pads the rest
-        uint32_t keys[kSortSlots];
+    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
+    for_frame_staged(filed4, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
+      const bool act = live && mine;
+      uint32_t keys[kSortSlots];
 #pragma unroll
-        for (int i = 0; i < kSortSlots; ++i) keys[i] = 0xFFFFFFFFu;
-        int n = 0;
-        members([&](int32_t q, float, int k) {
+      for (int i = 0; i < kSortSlots; ++i) keys[i] = 0xFFFFFFFFu;
+      int n = 0;
+      auto members = [&](auto&& fn) { for_members_staged(s, r0, rb, half, tx, ty, x, y, fn); };
+      if (act && staged)
+        members([&](int32_t q, float, int k) {  // keys pushed in front (static register indices)
 #pragma unroll
           for (int i = kSortSlots - 1; i > 0; --i) keys[i] = keys[i - 1];
           keys[0] = (static_cast<uint32_t>(q) << kIdxBits) | static_cast<uint32_t>(k);
           ++n;
         });
-        if (n <= kSortSlots) {
-          if (__any(n > kSortSlots / 2))
-            sort_keys<kSortSlots>(keys);
-          else
-            sort_keys<kSortSlots / 2>(keys);
-          emit_sorted(id_j, keys, n);
-        } else {
-          emit_by_minimum(id_j, [&](auto&& fn) { members([&](int32_t q, float z, int k) { fn(q, z, k); }); },
-                          [&](int64_t k) { return s.col[k]; });
-        }
+      const bool buffered = act && staged && n <= kBufSlots;
+      // a lane whose buffer cannot take this frame's members writes it out first
+      // (all of it when the members go out directly)
+      const int nflush = act && (!buffered || fill + n > kBufSlots) ? fill : 0;
+      if (__any(nflush > 0)) flush_records(nflush, cur, fill, buf, ids, crho);
+      if (act && staged && n <= kSortSlots) {
+        if (__any(n > kSortSlots / 2))
+          sort_keys<kSortSlots>(keys);
+        else
+          sort_keys<kSortSlots / 2>(keys);
       }
-      __syncthreads();
-    } else if (live) {
-      emit_by_minimum(
-          id_j, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); },
-          [&](int64_t k) {
-            const u32x4 c = filed4[2 * k + 1];
-            return make_uint2(c[0], c[1]);
-          });
-    }
+      if (buffered) {
+        found += n;
+        const int64_t room = end - cur - fill;  // fewer only when the planes changed since pass 1
+        uint32_t* slot = buf.rec + 3 * (lane * kBufSlots + fill);
+#pragma unroll
+        for (int i = 0; i < kBufSlots; ++i)
+          if (i < n && i < room) {
+            const uint32_t key = keys[i];
+            const int k = static_cast<int>(key & ((1u << kIdxBits) - 1u));
+            uint32_t r[3];
+            make(id_j | (key >> kIdxBits), s.col[k], __uint_as_float(s.rec[k][2]), r);
+            slot[3 * i] = r[0];
+            slot[3 * i + 1] = r[1];
+            slot[3 * i + 2] = r[2];
+          }
+        fill += static_cast<int>(min(static_cast<int64_t>(n), max(room, static_cast<int64_t>(0))));
+      } else if (act && staged && n <= kSortSlots) {
+        found += n;
+#pragma unroll
+        for (int i = 0; i < kSortSlots; ++i)
+          if (i < n) {
+            const uint32_t key = keys[i];
+            const int k = static_cast<int>(key & ((1u << kIdxBits) - 1u));
+            emit(id_j | (key >> kIdxBits), s.col[k], __uint_as_float(s.rec[k][2]));
+          }
+      } else if (act && staged) {
+        found += n;
+        emit_by_minimum(id_j, [&](auto&& fn) { members([&](int32_t q, float z, int k) { fn(q, z, k); }); },
+                        [&](int64_t k) { return s.col[k]; });
+      } else if (act) {
+        const int64_t before = cur;
+        emit_by_minimum(
+            id_j, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); },
+            [&](int64_t k) {
+              const u32x4 c = filed4[2 * k + 1];
+              return make_uint2(c[0], c[1]);
+            });
+        found += cur - before;
+      }
+    });
   }
-  if (live && cur != end) flag_or(status, SG_FLAG_INCONSISTENT);
+  const int nflush = fill;
+  if (__any(nflush > 0)) flush_records(nflush, cur, fill, buf, ids, crho);
+  if (live && found != end - start) flag_or(status, SG_FLAG_INCONSISTENT);
 }
 
 sg_status check_frustum(const sg_clip* clip, int32_t f, const sg_frustum_params* p) {
@@ -606,6 +715,7 @@ struct FrustumCall {
   FrustumLayout l;
   float* maps;
   int2* slots;
+  uint32_t* counts;
   int64_t* boff;
   Filed* filed;
   int64_t* partial;
@@ -623,6 +733,7 @@ sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_param
   char* base = static_cast<char*>(ws);
   c->maps = reinterpret_cast<float*>(base + c->l.maps);
   c->slots = reinterpret_cast<int2*>(base + c->l.slots);
+  c->counts = reinterpret_cast<uint32_t*>(base + c->l.counts);
   c->boff = reinterpret_cast<int64_t*>(base + c->l.boff);
   c->filed = reinterpret_cast<Filed*>(base + c->l.items);
   c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
@@ -665,13 +776,14 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
   const dim3 per_pixel(static_cast<unsigned>((l.n_pix + sg::kThreads - 1) / sg::kThreads));
   const dim3 per_pixel_frame(per_pixel.x, static_cast<unsigned>(l.n_j));
   const float half = 0.5f * params->l;
-  hipLaunchKernelGGL(sg::k_zero<int64_t>, dim3(sg::zero_blocks(n_bk + 1)), dim3(sg::kThreads), 0, st, c.boff,
-                     n_bk + 1);
+  hipLaunchKernelGGL(sg::k_zero<uint32_t>, dim3(sg::zero_blocks(n_bk)), dim3(sg::kThreads), 0, st, c.counts, n_bk);
   hipLaunchKernelGGL(sg::k_frustum_pose, dim3(1), dim3(64), 0, st, clip->cam_to_world, f, l.jlo, l.n_j, clip->fx,
                      clip->fy, clip->cx, clip->cy, c.maps, sets->status);
   hipLaunchKernelGGL(sg::k_frustum_carry, per_pixel_frame, dim3(sg::kThreads), 0, st, clip->depth, c.maps,
                      clip->width, clip->height, l.jlo, l.rb, params->near_z, params->far_z, l.n_pix, l.n_buckets,
-                     c.slots, reinterpret_cast<unsigned long long*>(c.boff));
+                     c.slots, c.counts);
+  hipLaunchKernelGGL(sg::k_widen, dim3(sg::zero_blocks(n_bk + 1)), dim3(sg::kThreads), 0, st, c.counts, n_bk,
+                     c.boff);
   if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
   hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st,
                      reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.maps, clip->width, clip->height,
