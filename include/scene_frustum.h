@@ -42,8 +42,9 @@ typedef struct sg_frustum_params {
 } sg_frustum_params;
 
 /* Bytes of device workspace for output frame f: per window frame, every pixel's
- * bucket and slot (8 B) and filed record (32 B: carried position and depth, pixel
- * index, stored colour), and the bucket grid's offsets. */
+ * bucket and slot (8 B), bucket counter (4 B), filed record (32 B: carried
+ * position and depth, pixel index, stored colour) and its position again (8 B,
+ * the count pass's copy), and the bucket grid's offsets. */
 sg_status scene_frustum_workspace_size(const sg_clip* clip, int32_t f, const sg_frustum_params* params,
                                        size_t* bytes);
 

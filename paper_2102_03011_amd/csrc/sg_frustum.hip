@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include <climits>
+#include <type_traits>
 
 #include "scene_frustum.h"
 #include "sg_device.h"
@@ -52,6 +53,8 @@ struct __attribute__((aligned(32))) Filed {
   uint32_t pad[2];
 };
 static_assert(sizeof(Filed) == 32, "two 16-byte words per record");
+// The count pass reads p' only: the bucket pass also writes it to an array of its
+// own (8 B per record), so the count stages a quarter of the bytes.
 
 int bucket_radius(float l) { return static_cast<int>(ceilf(0.5f * l + 1.0f)) - 1; }
 
@@ -60,7 +63,7 @@ size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
 struct FrustumLayout {
   int jlo, n_j, rb;
   int64_t n_pix, n_buckets;  // per window frame
-  size_t maps, slots, counts, boff, items, partial, total;
+  size_t maps, slots, counts, boff, items, xy, partial, total;
 };
 
 FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_params* p) {
@@ -84,6 +87,8 @@ FrustumLayout frustum_layout(const sg_clip* c, int32_t f, const sg_frustum_param
   at += align_up((static_cast<size_t>(l.n_j) * l.n_buckets + 1) * sizeof(int64_t));
   l.items = at;
   at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(Filed));
+  l.xy = at;
+  at += align_up(static_cast<size_t>(l.n_j) * l.n_pix * sizeof(uint2));
   l.partial = at;
   at += align_up(static_cast<size_t>((scan_a > scan_b ? scan_a : scan_b) + 1) * sizeof(int64_t));
   l.total = at;
@@ -198,7 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_frustum_bucket(const uint2* __rest
                                                              int jlo, int rb, float near_z, float far_z,
                                                              const int2* __restrict__ slots,
                                                              const int64_t* __restrict__ boff, int64_t n_pix,
-                                                             int64_t n_buckets, Filed* __restrict__ filed) {
+                                                             int64_t n_buckets, Filed* __restrict__ filed,
+                                                             uint2* __restrict__ fxy) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   if (q >= n_pix) return;
   const int jn = blockIdx.y;
@@ -215,15 +221,18 @@ __global__ __launch_bounds__(kThreads) void k_frustum_bucket(const uint2* __rest
   gp<u32x4> out = reinterpret_cast<gp<u32x4>>(to_global(filed) + at);
   out[0] = u32x4{__float_as_uint(px), __float_as_uint(py), __float_as_uint(z), static_cast<uint32_t>(q)};
   out[1] = u32x4{c.x, c.y, 0u, 0u};
+  st2(to_global(fxy) + at, make_uint2(__float_as_uint(px), __float_as_uint(py)));
 }
 
 // Calls fn(q, z', k) for every q filed (at index k) within L1 distance rb of output
-// pixel (x, y) in window frame jn and passing Eq. 2.
-template <typename Fn>
-__device__ __forceinline__ void for_members(const Filed* __restrict__ filed_, const int64_t* __restrict__ boff,
-                                            int width, int rb, float half, int64_t n_buckets, int jn, int x, int y,
-                                            Fn&& fn) {
+// pixel (x, y) in window frame jn and passing Eq. 2 (kXy: positions from the p'
+// array only, fn gets q = z' = 0).
+template <bool kXy, typename Fn>
+__device__ __forceinline__ void for_members(const Filed* __restrict__ filed_, const uint2* __restrict__ fxy_,
+                                            const int64_t* __restrict__ boff, int width, int rb, float half,
+                                            int64_t n_buckets, int jn, int x, int y, Fn&& fn) {
   gp<const u32x4> filed = reinterpret_cast<gp<const u32x4>>(to_global(filed_));
+  gp<const uint2> fxy = to_global(fxy_);
   gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
   const int ew = width + 2 * rb;
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
@@ -233,7 +242,13 @@ __device__ __forceinline__ void for_members(const Filed* __restrict__ filed_, co
     // the buckets of this row are adjacent: one contiguous range of filed records
     const int64_t k0 = bj[row - span], k1 = bj[row + span + 1];
     for (int64_t k = k0; k < k1; ++k) {
-      const u32x4 w = filed[2 * k];
+      u32x4 w;
+      if (kXy) {
+        const uint2 v = ld2(fxy + k);
+        w = u32x4{v.x, v.y, 0u, 0u};
+      } else {
+        w = filed[2 * k];
+      }
       if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
         fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
     }
@@ -257,7 +272,8 @@ static_assert(kThreads == kTile * kTile, "one thread per pixel of a tile");
 // records staged per window frame (kColour: with their colours, for the scatter)
 template <bool kColour>
 struct StageLds {
-  u32x4 rec[kStageCap];                     // x, y, z', q of the staged rows, row after row
+  // x, y, z', q (scatter) or x, y (count) of the staged rows' records, row after row
+  typename std::conditional<kColour, u32x4, uint2>::type rec[kStageCap];
   uint2 col[kColour ? kStageCap : 1];       // their r, g, b, depth
   int32_t loc[kStageSide][kStageSide + 1];  // rec index of bucket (row, column); [r][ncols] = row end
   int32_t base[kStageSide + 1];             // rec index of each row's first record; [nrows] = total
@@ -301,8 +317,8 @@ __device__ __forceinline__ RowSpan row_span(gp<const int64_t> bj, int ew, const 
 // either way, and the caller puts one between its last read of the staged records
 // and the next call.
 template <bool kColour>
-__device__ bool stage_rows(gp<const u32x4> filed, gp<const int64_t> bj, int ew, const TileGeom& g, int r0, int r1,
-                           RowSpan rs, StageLds<kColour>& s) {
+__device__ bool stage_rows(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> bj, int ew,
+                           const TileGeom& g, int r0, int r1, RowSpan rs, StageLds<kColour>& s) {
   const int t = threadIdx.x;
   const int nr = r1 - r0;
   if (t < nr) {
@@ -338,7 +354,7 @@ __device__ bool stage_rows(gp<const u32x4> filed, gp<const int64_t> bj, int ew, 
   }
   constexpr int kRecPerThread = kStageCap / kThreads;
   static_assert(kRecPerThread * kThreads == kStageCap, "whole records per thread");
-  u32x4 v[kRecPerThread];
+  typename std::conditional<kColour, u32x4, uint2>::type v[kRecPerThread];
   uint2 cv[kRecPerThread];
 #pragma unroll
   for (int k = 0; k < kRecPerThread; ++k) {
@@ -350,10 +366,12 @@ __device__ bool stage_rows(gp<const u32x4> filed, gp<const int64_t> bj, int ew, 
         if (s.base[mid] <= i) lo = mid; else hi = mid - 1;
       }
       const int64_t at = s.first[lo] + (i - s.base[lo]);
-      v[k] = filed[2 * at];
-      if (kColour) {
+      if constexpr (kColour) {
+        v[k] = filed[2 * at];
         const u32x4 w = filed[2 * at + 1];
         cv[k] = make_uint2(w[0], w[1]);
+      } else {
+        v[k] = ld2(fxy + at);
       }
     }
   }
@@ -368,7 +386,7 @@ __device__ bool stage_rows(gp<const u32x4> filed, gp<const int64_t> bj, int ew, 
   for (int k = 0; k < kRecPerThread; ++k)
     if (t + k * kThreads < total) {
       s.rec[t + k * kThreads] = v[k];
-      if (kColour) s.col[t + k * kThreads] = cv[k];
+      if constexpr (kColour) s.col[t + k * kThreads] = cv[k];
     }
   __syncthreads();
   return true;
@@ -385,9 +403,14 @@ __device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, i
     const int r = ty + dy + rb - r0;
     const int k0 = s.loc[r][tx + rb - span], k1 = s.loc[r][tx + rb + span + 1];
     for (int k = k0; k < k1; ++k) {
-      const u32x4 w = s.rec[k];
-      if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
-        fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
+      if constexpr (kColour) {
+        const u32x4 w = s.rec[k];
+        if (fabsf(fx - __uint_as_float(w[0])) + fabsf(fy - __uint_as_float(w[1])) < half)
+          fn(static_cast<int32_t>(w[3]), __uint_as_float(w[2]), k);
+      } else {
+        const uint2 w = s.rec[k];
+        if (fabsf(fx - __uint_as_float(w.x)) + fabsf(fy - __uint_as_float(w.y)) < half) fn(0, 0.0f, k);
+      }
     }
   }
 }
@@ -400,10 +423,11 @@ __device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, i
 // calls it, and body runs for every thread of the workgroup (mine: the thread's
 // pixel row belongs to the current part); body may not use barriers.
 template <bool kColour, typename Body>
-__device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const int64_t> bj, int ew, int rb,
+__device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> bj,
+                                                 int ew, int rb,
                                                  int height, const TileGeom& g, int ty, RowSpan rs,
                                                  StageLds<kColour>& s, Body&& body) {
-  if (stage_rows(filed, bj, ew, g, 0, g.nrows, rs, s)) {
+  if (stage_rows(filed, fxy, bj, ew, g, 0, g.nrows, rs, s)) {
     body(true, 0, true);
     __syncthreads();
     return;
@@ -418,7 +442,7 @@ __device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const
       if ((todo & part) == 0u) continue;  // done, or no pixel rows
       const int r1 = min(g.nrows, r0 + np + 2 * rb);
       const bool mine = ty >= r0 && ty < r0 + np;
-      if (stage_rows(filed, bj, ew, g, r0, r1, row_span(bj, ew, g, r0, r1), s)) {
+      if (stage_rows(filed, fxy, bj, ew, g, r0, r1, row_span(bj, ew, g, r0, r1), s)) {
         body(true, r0, mine);
         __syncthreads();
         todo &= ~part;
@@ -431,7 +455,7 @@ __device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const
 }
 
 // grid: 16 x 16 tiles of the output frame
-__global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restrict__ filed,
+__global__ __launch_bounds__(kThreads) void k_frustum_count(const uint2* __restrict__ fxy,
                                                             const int64_t* __restrict__ boff, int width, int height,
                                                             int n_j, int rb, float half, int64_t n_buckets,
                                                             int64_t* __restrict__ counts) {
@@ -441,19 +465,19 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const Filed* __restr
   const int x = g.tx0 + tx, y = g.ty0 + ty;
   const bool in = x < width && y < height;
   const int ew = width + 2 * rb;
-  gp<const u32x4> filed4 = reinterpret_cast<gp<const u32x4>>(to_global(filed));
   int64_t n = 0;
   RowSpan next = row_span(to_global(boff), ew, g, 0, g.nrows);
   for (int jn = 0; jn < n_j; ++jn) {
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
     const RowSpan rs = next;
     if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
-    for_frame_staged(filed4, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
+    for_frame_staged(nullptr, to_global(fxy), bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
       if (!in || !mine) return;
       if (staged)
         for_members_staged(s, r0, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
       else
-        for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, [&](int32_t, float, int64_t) { ++n; });
+        for_members<true>(nullptr, fxy, boff, width, rb, half, n_buckets, jn, x, y,
+                          [&](int32_t, float, int64_t) { ++n; });
     });
   }
   if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
@@ -627,7 +651,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
     gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
     const RowSpan rs = next;
     if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
-    for_frame_staged(filed4, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
+    for_frame_staged(filed4, nullptr, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
       const bool act = live && mine;
       uint32_t keys[kSortSlots];
 #pragma unroll
@@ -684,7 +708,8 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       } else if (act) {
         const int64_t before = cur;
         emit_by_minimum(
-            id_j, [&](auto&& fn) { for_members(filed, boff, width, rb, half, n_buckets, jn, x, y, fn); },
+            id_j,
+            [&](auto&& fn) { for_members<false>(filed, nullptr, boff, width, rb, half, n_buckets, jn, x, y, fn); },
             [&](int64_t k) {
               const u32x4 c = filed4[2 * k + 1];
               return make_uint2(c[0], c[1]);
@@ -718,6 +743,7 @@ struct FrustumCall {
   uint32_t* counts;
   int64_t* boff;
   Filed* filed;
+  uint2* xy;
   int64_t* partial;
 };
 
@@ -736,6 +762,7 @@ sg_status frustum_prepare(const sg_clip* clip, int32_t f, const sg_frustum_param
   c->counts = reinterpret_cast<uint32_t*>(base + c->l.counts);
   c->boff = reinterpret_cast<int64_t*>(base + c->l.boff);
   c->filed = reinterpret_cast<Filed*>(base + c->l.items);
+  c->xy = reinterpret_cast<uint2*>(base + c->l.xy);
   c->partial = reinterpret_cast<int64_t*>(base + c->l.partial);
   return SG_OK;
 }
@@ -787,8 +814,8 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
   if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
   hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st,
                      reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.maps, clip->width, clip->height,
-                     l.jlo, l.rb, params->near_z, params->far_z, c.slots, c.boff, l.n_pix, l.n_buckets, c.filed);
-  hipLaunchKernelGGL(sg::k_frustum_count, sg::tile_grid(clip), dim3(sg::kThreads), 0, st, c.filed, c.boff,
+                     l.jlo, l.rb, params->near_z, params->far_z, c.slots, c.boff, l.n_pix, l.n_buckets, c.filed, c.xy);
+  hipLaunchKernelGGL(sg::k_frustum_count, sg::tile_grid(clip), dim3(sg::kThreads), 0, st, c.xy, c.boff,
                      clip->width, clip->height, l.n_j, l.rb, half, l.n_buckets, sets->offsets + 1);
   return hip_status(sg::launch_scan(sets->offsets, l.n_pix, c.partial, st));
 }
