@@ -287,9 +287,20 @@ struct TileGeom {
 
 __device__ __forceinline__ TileGeom tile_geom(int width, int height, int rb) {
   const int tiles_x = (width + kTile - 1) / kTile;
+  const int nt = tiles_x * ((height + kTile - 1) / kTile);
+  // whole tile rows per XCD: the dispatcher hands consecutive workgroups to the
+  // eight XCDs in turn, so workgroup b runs on XCD b % 8
+  const int bl = static_cast<int>(blockIdx.x);
+  const int full = (nt / (8 * tiles_x)) * (8 * tiles_x);
+  int tl = bl;
+  if (bl < full) {
+    const int xcd = bl & 7, i = bl >> 3;
+    const int q = i / tiles_x, p = i - q * tiles_x;
+    tl = (q * 8 + xcd) * tiles_x + p;
+  }
   TileGeom g;
-  g.tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * kTile;
-  g.ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * kTile;
+  g.tx0 = (tl % tiles_x) * kTile;
+  g.ty0 = (tl / tiles_x) * kTile;
   g.nrows = min(kTile + 2 * rb, height + 2 * rb - g.ty0);
   g.ncols = min(kTile + 2 * rb, width + 2 * rb - g.tx0);
   return g;
