@@ -278,6 +278,8 @@ struct StageLds {
   int32_t loc[kStageSide][kStageSide + 1];  // rec index of bucket (row, column); [r][ncols] = row end
   int32_t base[kStageSide + 1];             // rec index of each row's first record; [nrows] = total
   int64_t first[kStageSide];                // filed index of each row's first record
+  int32_t base_next[kStageSide + 1];        // the same for the next window frame (whole tile)
+  int64_t first_next[kStageSide];
 };
 
 struct TileGeom {
@@ -426,23 +428,17 @@ __device__ __forceinline__ void for_members_staged(const StageLds<kColour>& s, i
   }
 }
 
-// Runs body(staged, r0, mine) for one window frame over the staged records: the
-// whole tile at once or, when its reachable records outgrow the stage, halves,
-// quarters, ... of its pixel rows one after the other (pixel rows [r0, r0 + n)
-// need staged bucket rows [r0, r0 + n + 2 rb)); a single pixel row that still does
-// not fit runs body with staged = false (read from global memory). Every thread
-// calls it, and body runs for every thread of the workgroup (mine: the thread's
-// pixel row belongs to the current part); body may not use barriers.
+// A window frame whose reachable records outgrow the stage: halves, quarters, ...
+// of the tile's pixel rows one after the other (pixel rows [r0, r0 + n) need staged
+// bucket rows [r0, r0 + n + 2 rb)), body(staged, r0, mine) for each part; a single
+// pixel row that still does not fit runs body with staged = false (read from
+// global memory). Every thread calls it, and body runs for every thread of the
+// workgroup (mine: the thread's pixel row belongs to the part); body may not use
+// barriers.
 template <bool kColour, typename Body>
-__device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> bj,
-                                                 int ew, int rb,
-                                                 int height, const TileGeom& g, int ty, RowSpan rs,
-                                                 StageLds<kColour>& s, Body&& body) {
-  if (stage_rows(filed, fxy, bj, ew, g, 0, g.nrows, rs, s)) {
-    body(true, 0, true);
-    __syncthreads();
-    return;
-  }
+__device__ __forceinline__ void for_frame_split(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> bj,
+                                                int ew, int rb, int height, const TileGeom& g, int ty,
+                                                StageLds<kColour>& s, Body&& body) {
   const int prows = min(kTile, height - g.ty0);  // pixel rows of the tile inside the image
   uint32_t todo = (1u << prows) - 1u;            // pixel rows not yet done (uniform)
 #pragma unroll 1
@@ -465,6 +461,161 @@ __device__ __forceinline__ void for_frame_staged(gp<const u32x4> filed, gp<const
   }
 }
 
+// The next window frame's records, loaded into registers while the workgroup
+// works on the current one, then written to the stage.
+template <bool kColour>
+struct Prefetch {
+  using Rec = typename std::conditional<kColour, u32x4, uint2>::type;
+  static constexpr int kPer = kStageCap / kThreads;
+  int total;
+  int64_t gb[kBoundsPerThread];
+  Rec v[kPer];
+  uint2 cv[kColour ? kPer : 1];
+};
+
+// Row starts of the next frame (rs: thread t's row span, t < nrows): the rows are
+// held by wave 0, whose saturating prefix sum over them needs no barrier.
+template <bool kColour>
+__device__ __forceinline__ void plan_next(RowSpan rs, const TileGeom& g, StageLds<kColour>& s) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    static_assert(kStageSide <= 32, "the rows fit in half a wave");
+    const int c = t < g.nrows ? static_cast<int>(min(rs.e - rs.a, static_cast<int64_t>(kStageCap) + 1)) : 0;
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if (t >= off) incl = min(incl + o, kStageCap + 1);
+    }
+    if (t < g.nrows) {
+      s.first_next[t] = rs.a;
+      s.base_next[t + 1] = incl;
+    }
+    if (t == 0) s.base_next[0] = 0;
+  }
+}
+
+// Issues the loads of the next frame's bucket starts and records (after plan_next
+// and a barrier); pf.total > kStageCap: nothing issued.
+template <bool kColour>
+__device__ __forceinline__ void issue_next(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> bj, int ew,
+                                           const TileGeom& g, const StageLds<kColour>& s, Prefetch<kColour>& pf) {
+  const int t = threadIdx.x;
+  pf.total = s.base_next[g.nrows];
+  if (pf.total > kStageCap) return;  // uniform
+#pragma unroll
+  for (int k = 0; k < kBoundsPerThread; ++k) {
+    const int i = t + k * kThreads;
+    if (i < g.nrows * (g.ncols + 1)) {
+      const int r = i / (g.ncols + 1), c = i - r * (g.ncols + 1);
+      pf.gb[k] = bj[static_cast<int64_t>(g.ty0 + r) * ew + g.tx0 + c];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < Prefetch<kColour>::kPer; ++k) {
+    const int i = t + k * kThreads;
+    if (i < pf.total) {
+      int lo = 0, hi = g.nrows - 1;  // row r with base[r] <= i < base[r + 1]
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.base_next[mid] <= i) lo = mid; else hi = mid - 1;
+      }
+      const int64_t at = s.first_next[lo] + (i - s.base_next[lo]);
+      if constexpr (kColour) {
+        pf.v[k] = filed[2 * at];
+        const u32x4 w = filed[2 * at + 1];
+        pf.cv[k] = make_uint2(w[0], w[1]);
+      } else {
+        pf.v[k] = ld2(fxy + at);
+      }
+    }
+  }
+}
+
+// Writes the prefetched frame into the stage (after a barrier past the last read
+// of the current one).
+template <bool kColour>
+__device__ __forceinline__ void commit_next(const TileGeom& g, StageLds<kColour>& s, const Prefetch<kColour>& pf) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBoundsPerThread; ++k) {
+    const int i = t + k * kThreads;
+    if (i < g.nrows * (g.ncols + 1)) {
+      const int r = i / (g.ncols + 1), c = i - r * (g.ncols + 1);
+      s.loc[r][c] = s.base_next[r] + static_cast<int32_t>(pf.gb[k] - s.first_next[r]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < Prefetch<kColour>::kPer; ++k)
+    if (t + k * kThreads < pf.total) {
+      s.rec[t + k * kThreads] = pf.v[k];
+      if constexpr (kColour) s.col[t + k * kThreads] = pf.cv[k];
+    }
+}
+
+// Runs body(jn, staged, r0, mine) for every window frame jn of the tile: a frame
+// whose reachable records fit the stage is staged whole (body(jn, true, 0, true));
+// one that does not fit goes by for_frame_split. kPrefetch: a frame's records are
+// loaded into registers while the workgroup works on the frame before (the
+// scatter, whose frames take long enough to hide the loads); otherwise only the
+// row spans are loaded a frame ahead (the count, whose occupancy the registers
+// would cost more than the loads). Every thread calls it; body may not use
+// barriers.
+template <bool kPrefetch, bool kColour, typename Body>
+__device__ __forceinline__ void for_frames(gp<const u32x4> filed, gp<const uint2> fxy, gp<const int64_t> boff,
+                                           int64_t n_buckets, int n_j, int ew, int rb, int height, const TileGeom& g,
+                                           int ty, StageLds<kColour>& s, Body&& body) {
+  if constexpr (!kPrefetch) {
+    RowSpan next = row_span(boff, ew, g, 0, g.nrows);
+#pragma unroll 1
+    for (int jn = 0; jn < n_j; ++jn) {
+      gp<const int64_t> bj = boff + static_cast<int64_t>(jn) * n_buckets;
+      const RowSpan rs = next;
+      if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
+      if (stage_rows(filed, fxy, bj, ew, g, 0, g.nrows, rs, s)) {
+        body(jn, true, 0, true);
+        __syncthreads();
+      } else {
+        for_frame_split(filed, fxy, bj, ew, rb, height, g, ty, s,
+                        [&](bool staged, int r0, bool mine) { body(jn, staged, r0, mine); });
+      }
+    }
+    return;
+  }
+  Prefetch<kColour> pf;
+  RowSpan sp = row_span(boff, ew, g, 0, g.nrows);
+  plan_next(sp, g, s);
+  __syncthreads();
+  issue_next(filed, fxy, boff, ew, g, s, pf);
+  if (n_j > 1) sp = row_span(boff + n_buckets, ew, g, 0, g.nrows);
+  bool cur_ok = pf.total <= kStageCap;
+  if (cur_ok) commit_next(g, s, pf);
+  __syncthreads();
+#pragma unroll 1
+  for (int jn = 0; jn < n_j; ++jn) {
+    gp<const int64_t> bj = boff + static_cast<int64_t>(jn) * n_buckets;
+    const bool more = jn + 1 < n_j;
+    if (more) plan_next(sp, g, s);
+    __syncthreads();  // the next frame's row starts are visible
+    bool next_ok = false;
+    if (more) {
+      issue_next(filed, fxy, bj + n_buckets, ew, g, s, pf);
+      next_ok = pf.total <= kStageCap;
+    }
+    if (jn + 2 < n_j) sp = row_span(bj + 2 * n_buckets, ew, g, 0, g.nrows);
+    if (cur_ok) {
+      body(jn, true, 0, true);
+    } else {
+      for_frame_split(filed, fxy, bj, ew, rb, height, g, ty, s,
+                      [&](bool staged, int r0, bool mine) { body(jn, staged, r0, mine); });
+    }
+    __syncthreads();  // every thread is done with this frame's stage
+    if (next_ok) commit_next(g, s, pf);
+    __syncthreads();
+    cur_ok = next_ok;
+  }
+}
+
 // grid: 16 x 16 tiles of the output frame
 __global__ __launch_bounds__(kThreads) void k_frustum_count(const uint2* __restrict__ fxy,
                                                             const int64_t* __restrict__ boff, int width, int height,
@@ -477,20 +628,15 @@ __global__ __launch_bounds__(kThreads) void k_frustum_count(const uint2* __restr
   const bool in = x < width && y < height;
   const int ew = width + 2 * rb;
   int64_t n = 0;
-  RowSpan next = row_span(to_global(boff), ew, g, 0, g.nrows);
-  for (int jn = 0; jn < n_j; ++jn) {
-    gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    const RowSpan rs = next;
-    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
-    for_frame_staged(nullptr, to_global(fxy), bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
-      if (!in || !mine) return;
-      if (staged)
-        for_members_staged(s, r0, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
-      else
-        for_members<true>(nullptr, fxy, boff, width, rb, half, n_buckets, jn, x, y,
-                          [&](int32_t, float, int64_t) { ++n; });
-    });
-  }
+  for_frames<false>(nullptr, to_global(fxy), to_global(boff), n_buckets, n_j, ew, rb, height, g, ty, s,
+             [&](int jn, bool staged, int r0, bool mine) {
+               if (!in || !mine) return;
+               if (staged)
+                 for_members_staged(s, r0, rb, half, tx, ty, x, y, [&](int32_t, float, int) { ++n; });
+               else
+                 for_members<true>(nullptr, fxy, boff, width, rb, half, n_buckets, jn, x, y,
+                                   [&](int32_t, float, int64_t) { ++n; });
+             });
   if (in) to_global(counts)[static_cast<int64_t>(y) * width + x] = n;
 }
 
@@ -656,13 +802,9 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       last = best;
     }
   };
-  RowSpan next = row_span(to_global(boff), ew, g, 0, g.nrows);
-  for (int jn = 0; jn < n_j; ++jn) {
-    const uint32_t id_j = static_cast<uint32_t>(jlo + jn - f + w) << SG_ID_SHIFT;
-    gp<const int64_t> bj = to_global(boff) + static_cast<int64_t>(jn) * n_buckets;
-    const RowSpan rs = next;
-    if (jn + 1 < n_j) next = row_span(bj + n_buckets, ew, g, 0, g.nrows);
-    for_frame_staged(filed4, nullptr, bj, ew, rb, height, g, ty, rs, s, [&](bool staged, int r0, bool mine) {
+  for_frames<true>(filed4, nullptr, to_global(boff), n_buckets, n_j, ew, rb, height, g, ty, s,
+             [&](int jn, bool staged, int r0, bool mine) {
+      const uint32_t id_j = static_cast<uint32_t>(jlo + jn - f + w) << SG_ID_SHIFT;
       const bool act = live && mine;
       uint32_t keys[kSortSlots];
 #pragma unroll
@@ -728,7 +870,6 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
         found += cur - before;
       }
     });
-  }
   const int nflush = fill;
   if (__any(nflush > 0)) flush_records(nflush, cur, fill, buf, ids, crho);
   if (live && found != end - start) flag_or(status, SG_FLAG_INCONSISTENT);
