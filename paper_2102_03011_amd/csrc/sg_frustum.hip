@@ -102,13 +102,73 @@ __global__ __launch_bounds__(kThreads) void k_zero(T* __restrict__ p, int64_t n)
     p[i] = T(0);
 }
 
-// offsets[0] = 0, offsets[1 + i] = counts[i]: the 32-bit bucket counters widened for
-// the 64-bit scan
-__global__ __launch_bounds__(kThreads) void k_widen(const uint32_t* __restrict__ counts, int64_t n,
-                                                    int64_t* __restrict__ offsets) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i <= n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    offsets[i] = i == 0 ? 0 : static_cast<int64_t>(counts[i - 1]);
+// Scan of the 32-bit bucket counters into the 64-bit bucket offsets (offsets[0] =
+// 0, offsets[1 + i] = counts[0] + ... + counts[i]): block sums over kScanTile
+// counters, a scan of the block sums, then each block's scan plus its start.
+__device__ __forceinline__ int64_t block_scan_excl(int64_t v, int64_t* lds, int64_t* total) {
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const int64_t add = t >= off ? lds[t - off] : 0;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  const int64_t incl = lds[t];
+  *total = lds[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_count_sums(const uint32_t* __restrict__ counts, int64_t n,
+                                                             int64_t* __restrict__ partial) {
+  __shared__ int64_t lds[kScanThreads];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+  int64_t s = 0;
+  for (int e = threadIdx.x; e < kScanTile; e += kScanThreads) {
+    const int64_t i = base + e;
+    if (i < n) s += counts[i];
+  }
+  int64_t total;
+  block_scan_excl(s, lds, &total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_count_sums_scan(int64_t* __restrict__ partial, int64_t nb) {
+  __shared__ int64_t lds[kScanThreads];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nb ? partial[i] : 0;
+    int64_t total;
+    const int64_t ex = block_scan_excl(v, lds, &total);
+    if (i < nb) partial[i] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_count_offsets(const uint32_t* __restrict__ counts, int64_t n,
+                                                                const int64_t* __restrict__ partial,
+                                                                int64_t* __restrict__ offsets) {
+  __shared__ int64_t lds[kScanThreads];
+  constexpr int kPer = kScanTile / kScanThreads;
+  const int64_t mine = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kPer;
+  uint32_t vals[kPer];
+  int64_t s = 0;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    vals[e] = mine + e < n ? counts[mine + e] : 0u;
+    s += vals[e];
+  }
+  int64_t total;
+  int64_t run = block_scan_excl(s, lds, &total) + partial[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    run += vals[e];
+    if (mine + e < n) offsets[1 + mine + e] = run;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
 }
 
 // (C^f)^-1 C^J in float64 (rigid: the inverse rotation is the transpose), folded
@@ -961,9 +1021,15 @@ sg_status scene_frustum_count(const sg_clip* clip, int32_t f, const sg_frustum_p
   hipLaunchKernelGGL(sg::k_frustum_carry, per_pixel_frame, dim3(sg::kThreads), 0, st, clip->depth, c.maps,
                      clip->width, clip->height, l.jlo, l.rb, params->near_z, params->far_z, l.n_pix, l.n_buckets,
                      c.slots, c.counts);
-  hipLaunchKernelGGL(sg::k_widen, dim3(sg::zero_blocks(n_bk + 1)), dim3(sg::kThreads), 0, st, c.counts, n_bk,
-                     c.boff);
-  if ((s = hip_status(sg::launch_scan(c.boff, n_bk, c.partial, st))) != SG_OK) return s;
+  {
+    const int64_t nb = (n_bk + sg::kScanTile - 1) / sg::kScanTile;
+    hipLaunchKernelGGL(sg::k_count_sums, dim3(static_cast<unsigned>(nb)), dim3(sg::kScanThreads), 0, st, c.counts,
+                       n_bk, c.partial);
+    hipLaunchKernelGGL(sg::k_count_sums_scan, dim3(1), dim3(sg::kScanThreads), 0, st, c.partial, nb);
+    hipLaunchKernelGGL(sg::k_count_offsets, dim3(static_cast<unsigned>(nb)), dim3(sg::kScanThreads), 0, st,
+                       c.counts, n_bk, c.partial, c.boff);
+    if ((s = hip_status(hipGetLastError())) != SG_OK) return s;
+  }
   hipLaunchKernelGGL(sg::k_frustum_bucket, per_pixel_frame, dim3(sg::kThreads), 0, st,
                      reinterpret_cast<const uint2*>(clip->rgbd), clip->depth, c.maps, clip->width, clip->height,
                      l.jlo, l.rb, params->near_z, params->far_z, c.slots, c.boff, l.n_pix, l.n_buckets, c.filed, c.xy);
