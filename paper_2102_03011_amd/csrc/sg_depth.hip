@@ -76,10 +76,11 @@ __global__ __launch_bounds__(kThreads) void k_estimate_depth(const uint2* __rest
     gp<const uint2> rgbd = to_global(rgbd_);
     gp<const float> hyp = to_global(hyp_);
     float own[9][3];
-    gp<const uint2> cf = rgbd + static_cast<size_t>(f) * pplane + padded_index(x, y, pw);
+    uint2 blk[3][3];
+    load_block_pixels<1>(rgbd + static_cast<size_t>(f) * pplane, padded_index(x, y, pw), pw, blk);
 #pragma unroll
     for (int o = 0; o < 9; ++o) {
-      const uint2 v = ld2(cf + (o / 3 - 1) * pw + (o % 3 - 1));
+      const uint2 v = blk[o / 3][o % 3];
       own[o][0] = h2f(v.x);
       own[o][1] = h2f(v.x >> 16);
       own[o][2] = h2f(v.y);
@@ -103,11 +104,12 @@ __global__ __launch_bounds__(kThreads) void k_estimate_depth(const uint2* __rest
               ev < static_cast<float>(height - 1)))
           continue;
         const int qx = static_cast<int>(floorf(eu)), qy = static_cast<int>(floorf(ev));
-        gp<const uint2> cj = rgbd + static_cast<size_t>(jlo + jn) * pplane + padded_index(qx, qy, pw);
+        uint2 src[3][3];
+        load_block_pixels<1>(rgbd + static_cast<size_t>(jlo + jn) * pplane, padded_index(qx, qy, pw), pw, src);
         float ssd = 0.0f;
 #pragma unroll
         for (int o = 0; o < 9; ++o) {
-          const uint2 w2 = ld2(cj + (o / 3 - 1) * pw + (o % 3 - 1));
+          const uint2 w2 = src[o / 3][o % 3];
           const float e0 = own[o][0] - h2f(w2.x), e1 = own[o][1] - h2f(w2.x >> 16), e2 = own[o][2] - h2f(w2.y);
           ssd = fmaf(e0, e0, fmaf(e1, e1, fmaf(e2, e2, ssd)));
         }

@@ -67,6 +67,31 @@ __device__ __forceinline__ uint32_t padded_index(int x, int y, int pw) {
   return __umul24(static_cast<uint32_t>(y + SG_APRON), static_cast<uint32_t>(pw)) + static_cast<uint32_t>(x + SG_APRON);
 }
 
+// The block of stored (r, g, b, depth) pixels around plane entry `at`: each block
+// row is fetched as 16-byte loads of two pixels and one 8-byte load of its last
+// pixel (three load instructions per row at r = 1 instead of one per pixel; a
+// wave's load touches about as many cache lines either way, and the vector memory
+// path's cost goes with the lines each instruction touches).
+typedef uint64_t __attribute__((ext_vector_type(2))) PixelPairV;
+typedef PixelPairV __attribute__((aligned(8))) PixelPair;  // two stored pixels, 8-byte aligned
+
+template <int R>
+__device__ __forceinline__ void load_block_pixels(gp<const uint2> plane, uint32_t at, int pw,
+                                                  uint2 (&px)[2 * R + 1][2 * R + 1]) {
+  constexpr int kSide = 2 * R + 1;
+#pragma unroll
+  for (int dy = 0; dy < kSide; ++dy) {
+    gp<const uint2> row = plane + (at + static_cast<uint32_t>((dy - R) * pw - R));
+#pragma unroll
+    for (int c = 0; c + 1 < kSide; c += 2) {
+      const PixelPairV v = *reinterpret_cast<gp<const PixelPair>>(row + c);
+      px[dy][c] = make_uint2(static_cast<uint32_t>(v.x), static_cast<uint32_t>(v.x >> 32));
+      px[dy][c + 1] = make_uint2(static_cast<uint32_t>(v.y), static_cast<uint32_t>(v.y >> 32));
+    }
+    px[dy][kSide - 1] = ld2(row + (kSide - 1));
+  }
+}
+
 }  // namespace sg
 
 #endif

@@ -503,10 +503,7 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
     if (active && project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p)) {
       gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane;  // frame J's plane (uniform)
       const uint32_t at = padded_index(p.iu, p.iv, pw);
-#pragma unroll
-      for (int dy = 0; dy < kSide; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (at + static_cast<uint32_t>((dy - R) * pw + (dx - R))));
+      load_block_pixels<R>(cj, at, pw, px);
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k)
         mask |= static_cast<Mask>(accept16(px[k / kSide][k % kSide].y >> 16, p) ? 1 : 0) << k;
@@ -624,10 +621,7 @@ __global__ __launch_bounds__(256) void k_gather_filter(const uint2* __restrict__
       gp<const uint2> cj = rgbd + static_cast<size_t>(j) * pplane;  // frame J's plane (uniform)
       const uint32_t at = padded_index(p.iu, p.iv, pw);
       uint2 px[kSide][kSide];
-#pragma unroll
-      for (int dy = 0; dy < kSide; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < kSide; ++dx) px[dy][dx] = ld2(cj + (at + static_cast<uint32_t>((dy - R) * pw + (dx - R))));
+      load_block_pixels<R>(cj, at, pw, px);
       const float dj = static_cast<float>(j - f);
 #pragma unroll
       for (int k = 0; k < kSide * kSide; ++k) {
