@@ -332,7 +332,7 @@ def scene_side_m(clip, staged) -> float:
     5 %-95 % range of the scene points of every 10th frame, from the stored depths)."""
     import torch
     h, w = clip.height, clip.width
-    d = staged.depth_image()[::10].to(torch.float64)
+    d = staged.rgbd_image()[::10, ..., 3].to(torch.float64)  # the depth channel
     ys, xs = torch.meshgrid(torch.arange(h, dtype=torch.float64, device=d.device),
                             torch.arange(w, dtype=torch.float64, device=d.device), indexing="ij")
     cams = staged.cam_to_world[::10].to(d.device)

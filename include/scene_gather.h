@@ -52,9 +52,8 @@ extern "C" {
 /* Stored planes carry an apron: SG_APRON rows above and below the image and
  * SG_APRON columns on its left, SG_APRON_RIGHT columns on its right. A projection
  * is kept when its block centre lies at most r pixels outside the image, so the
- * block reaches 2r beyond it: SG_APRON >= 2 SG_MAX_RADIUS. A block row of depths
- * is read as whole 8-byte words (4 values) from its first column, so the right
- * apron holds 4 ceil((2r + 1) / 4) - 1 columns for every r <= SG_MAX_RADIUS. */
+ * block reaches 2r beyond it: SG_APRON >= 2 SG_MAX_RADIUS, and so is the right
+ * apron (one column wider than it needs to be). */
 #define SG_APRON 6
 #define SG_APRON_RIGHT 7
 #define SG_MAX_WINDOW 511
@@ -84,7 +83,11 @@ typedef enum sg_status {
  * (binary16 NaN) and zero colour.
  * rgbd : device [N][SH][SW][4] binary16 (r, g, b, z-depth); the 4th channel is the
  *        same binary16 depth as `depth`.
- * depth: device [N][SH][SW] binary16 z-depth (the membership test reads it).
+ * depth: device [N][SP][SW][2] binary16 z-depth with stored rows paired, SP =
+ *        ceil(SH / 2): entry [n][P][X][s] is stored row 2P + s, column X, so one
+ *        32-bit word holds two vertically adjacent depths (the count pass reads a
+ *        block of 2r + 1 rows as r + 1 rows of words). With SH odd the last pair's
+ *        second row is apron. The pointer must be 4-byte aligned (rgbd: 8-byte).
  * cam_to_world: device [N][4][4] float64.                                    */
 typedef struct sg_clip {
   int32_t width;
@@ -147,7 +150,8 @@ const char* sg_status_string(int32_t status);
  * depth   : device [n_frames][H][W] float32 z-depth.
  * rgbd    : device [n_frames][SH][SW][4] binary16 out: (c/255, c/255, c/255, depth),
  *           each rounded to nearest even; stored geometry and apron as at sg_clip.
- * depth16 : device [n_frames][SH][SW] binary16 out: depth (inf above 65504).
+ * depth16 : device [n_frames][SP][SW][2] binary16 out: depth (inf above 65504), stored
+ *           rows paired as at sg_clip (4-byte aligned; rgbd 8-byte aligned).
  * n_frames >= 0 (0 enqueues nothing); W, H > 0 with W * H <= SG_MAX_PIXELS_PER_FRAME. */
 sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int32_t n_frames,
                       int32_t width, int32_t height, uint16_t* rgbd, uint16_t* depth16,

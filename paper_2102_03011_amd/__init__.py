@@ -77,7 +77,8 @@ class StagedClip:
     invalid depth and zero colour: SG_APRON rows above and below, SG_APRON
     columns left and SG_APRON_RIGHT columns right of the image."""
     rgbd: torch.Tensor          # [N, H + 2A, W + A + AR, 4] float16: r, g, b (0-1), z-depth
-    depth: torch.Tensor         # [N, H + 2A, W + A + AR] float16 z-depth
+    depth: torch.Tensor         # [N, ceil((H + 2A) / 2), W + A + AR, 2] float16 z-depth, stored
+                                # rows paired: [n, P, X, s] is stored row 2P + s, column X
     cam_to_world: torch.Tensor  # [N, 4, 4] float64
     fx: float
     fy: float
@@ -101,9 +102,16 @@ class StagedClip:
         a = SG_APRON
         return self.rgbd[:, a:a + self.height, a:a + self.width, :]
 
+    def depth_rows(self) -> torch.Tensor:
+        """[N, 2 ceil((H + 2A) / 2), W + A + AR] copy of the depth planes in stored-row
+        order (the apron included; with H odd the last row is an extra apron row)."""
+        n, pr, sw, _ = self.depth.shape
+        return self.depth.permute(0, 1, 3, 2).reshape(n, 2 * pr, sw)
+
     def depth_image(self) -> torch.Tensor:
+        """[N, H, W] copy of the image pixels' depths."""
         a = SG_APRON
-        return self.depth[:, a:a + self.height, a:a + self.width]
+        return self.depth_rows()[:, a:a + self.height, a:a + self.width]
 
     def c_struct(self) -> _native.SgClip:
         return _native.SgClip(self.width, self.height, self.num_frames, 0,
@@ -169,7 +177,7 @@ def scene_stage(rgb_u8: torch.Tensor, depth: torch.Tensor, cam_to_world: torch.T
     a = SG_APRON
     sw = w + a + SG_APRON_RIGHT
     rgbd = torch.empty((n, h + 2 * a, sw, 4), dtype=torch.float16, device=rgb_u8.device)
-    d16 = torch.empty((n, h + 2 * a, sw), dtype=torch.float16, device=rgb_u8.device)
+    d16 = torch.empty((n, (h + 2 * a + 1) // 2, sw, 2), dtype=torch.float16, device=rgb_u8.device)
     _check(_lib.scene_stage(rgb_u8.data_ptr(), depth.data_ptr(), n, w, h, rgbd.data_ptr(), d16.data_ptr(),
                             _stream_handle()), "scene_stage")
     return StagedClip(rgbd, d16, cam_to_world, fx, fy, cx, cy)

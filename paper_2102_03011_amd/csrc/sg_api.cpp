@@ -126,6 +126,8 @@ sg_status scene_stage(const uint8_t* rgb_u8, const float* depth, int32_t n_frame
   if (n_frames < 0 || width <= 0 || height <= 0) return SG_E_INVALID;
   if (n_frames > 0 && (rgb_u8 == nullptr || depth == nullptr || rgbd == nullptr || depth16 == nullptr))
     return SG_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(rgbd) & 7u) != 0 || (reinterpret_cast<uintptr_t>(depth16) & 3u) != 0)
+    return SG_E_INVALID;
   if (static_cast<int64_t>(width) * height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;
   if (n_frames > 65535) return SG_E_UNSUPPORTED;
   return hip_status(sg::launch_stage(rgb_u8, depth, n_frames, width, height, rgbd, depth16,

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_xyz(
   const PixelSet p = pixel_set(rgbd, width, height, f0, n_pix, to_global(offsets_), capacity, pix);
   const bool use_xyz = xa.a_x != 0.0f;
   const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
+  const size_t dplane = depth_plane_elems(width, height);
   const int64_t frame_px = static_cast<int64_t>(width) * height;
   // the reference point: p's own stored depth
   float dp = 0.0f, px = 0.0f, py = 0.0f;
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_xyz(
     const int y = static_cast<int>(p.self / width), x = static_cast<int>(p.self - static_cast<int64_t>(y) * width);
     px = static_cast<float>(x);
     py = static_cast<float>(y);
-    dp = h2f(depth[static_cast<size_t>(p.f) * pplane + padded_index(x, y, pw)]);
+    dp = h2f(depth[static_cast<size_t>(p.f) * dplane + depth_index(x, y, pw)]);
     no_ref = use_xyz && !(dp > 0.0f && dp < INFINITY);
     relf = relf + static_cast<size_t>(p.f - f0) * (2 * w + 1) * kRelStride;
   }
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_xyz(
       int qx = qi - qy * width;
       if (qx < 0) { --qy; qx += width; }
       if (qx >= width) { ++qy; qx -= width; }
-      const float d = h2f(depth[static_cast<size_t>(j) * pplane + padded_index(qx, qy, pw)]);
+      const float d = h2f(depth[static_cast<size_t>(j) * dplane + depth_index(qx, qy, pw)]);
       gp<const float> m = relf + dj * kRelStride;
       const float y0 = fmaf(dp, fmaf(m[0], px, fmaf(m[1], py, m[2])), m[9]);
       const float y1 = fmaf(dp, fmaf(m[3], px, fmaf(m[4], py, m[5])), m[10]);
@@ -479,8 +479,8 @@ __global__ __launch_bounds__(256) void k_box_mask(const uint16_t* __restrict__ d
   const int64_t self = i - static_cast<int64_t>(j) * frame_px;
   const int y = static_cast<int>(self / width), x = static_cast<int>(self - static_cast<int64_t>(y) * width);
   const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const double d = static_cast<double>(h2f(to_global(depth_)[static_cast<size_t>(j) * pplane + padded_index(x, y, pw)]));
+  const double d = static_cast<double>(
+      h2f(to_global(depth_)[static_cast<size_t>(j) * depth_plane_elems(width, height) + depth_index(x, y, pw)]));
   uint8_t m = 0;
   if (d > 0.0 && d < INFINITY) {  // NaN fails both
     const double xc = d * ((static_cast<double>(x) - cx) / fx);

@@ -216,8 +216,7 @@ __device__ __forceinline__ int carry_point(gp<const uint16_t> depth, gp<const fl
                                            int jn_plane_frame, int x, int y, int rb, float near_z, float far_z,
                                            float& px, float& py, float& z) {
   const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float d = h2f(depth[static_cast<size_t>(jn_plane_frame) * pplane + padded_index(x, y, pw)]);
+  const float d = h2f(depth[static_cast<size_t>(jn_plane_frame) * depth_plane_elems(width, height) + depth_index(x, y, pw)]);
   px = py = z = 0.0f;
   if (!(d > 0.0f && d < INFINITY)) return -1;
   const float fx = static_cast<float>(x), fy = static_cast<float>(y);
@@ -817,9 +816,7 @@ __global__ __launch_bounds__(kThreads) void k_frustum_scatter(
       live = false;
     }
   }
-  const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float dp = live ? h2f(to_global(depth_)[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]) : 0.0f;
+  const float dp = live ? depth_at(to_global(depth_), width, height, f, x, y) : 0.0f;
   const bool has_ref = dp > 0.0f && dp < INFINITY;
   gp<uint32_t> ids = to_global(ids_);
   gp<uint2> crho = to_global(crho_);

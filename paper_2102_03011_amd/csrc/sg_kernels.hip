@@ -15,8 +15,9 @@
 // on the left, SG_APRON_RIGHT on the right) holding an invalid depth (binary16
 // NaN) and zero colour, so a block around any projection that passed the bounds
 // test can be read without per-pixel bounds checks: out-of-image block pixels
-// read the apron and fail the depth test. The wider right apron lets each block
-// row be fetched as whole 8-byte words.
+// read the apron and fail the depth test. The depth plane pairs stored rows (one
+// 32-bit word per column holds two rows), so the count pass reads a 3 x 3 block
+// of depths with two row loads.
 //
 // All kernels are compiled with -ffp-contract=off; every fused multiply-add is
 // written explicitly, so pass 1 and pass 2 make bit-identical decisions.
@@ -31,36 +32,11 @@
 
 namespace sg {
 
-// Block rows are fetched as 8-byte words (four binary16 depths) starting at the
-// row's first column: kRowWords words cover the 2R + 1 columns.
-typedef uint64_t __attribute__((aligned(2))) RowWord;  // 4 binary16 depths, 2-byte aligned
-
-template <int R>
-struct RowLoad {
-  static constexpr int kWords = (2 * R + 1 + 3) / 4;
-};
-
-// The block around plane entry `at` (32-bit offsets from the frame's plane, whose
-// address is the same for the whole wave).
-template <int R>
-__device__ __forceinline__ void load_block_depths(gp<const uint16_t> plane, uint32_t at, int pw,
-                                                  uint32_t (&d)[2 * R + 1][2 * R + 1]) {
-  constexpr int kW = RowLoad<R>::kWords;
-#pragma unroll
-  for (int dy = -R; dy <= R; ++dy) {
-    gp<const uint16_t> rowp = plane + (at + static_cast<uint32_t>(dy * pw - R));
-    uint64_t w[kW];
-#pragma unroll
-    for (int c = 0; c < kW; ++c) w[c] = *reinterpret_cast<gp<const RowWord>>(rowp + 4 * c);
-#pragma unroll
-    for (int o = 0; o <= 2 * R; ++o)
-      d[dy + R][o] = static_cast<uint32_t>(w[o / 4] >> (16 * (o % 4))) & 0xFFFFu;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // a1: staging. colour c (0-255) -> binary16(c / 255); depth -> binary16(depth).
 // One thread per stored (padded) pixel; apron pixels get NaN depth, zero colour.
+// The depth goes to its row-paired entry; with an odd number of stored rows the
+// threads of the last row also fill the unused high half of the last pair.
 
 __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
                                                const float* __restrict__ depth, int n_frames,
@@ -74,9 +50,12 @@ __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
   const int64_t r = i - n * pplane;
   const int py = static_cast<int>(r / pw), px = static_cast<int>(r - static_cast<int64_t>(py) * pw);
   const int x = px - SG_APRON, y = py - SG_APRON;
+  uint16_t* dn = depth16 + static_cast<size_t>(n) * depth_plane_elems(width, height);
+  const uint32_t di = depth_index(x, y, pw);
+  if ((ph & 1) && py == ph - 1) dn[di + 1] = static_cast<uint16_t>(kInvalidDepth16);
   if (x < 0 || x >= width || y < 0 || y >= height) {
     rgbd[i] = make_uint2(0u, kInvalidDepth16 << 16);
-    depth16[i] = static_cast<uint16_t>(kInvalidDepth16);
+    dn[di] = static_cast<uint16_t>(kInvalidDepth16);
     return;
   }
   const int64_t s = (n * height + y) * static_cast<int64_t>(width) + x;
@@ -85,7 +64,7 @@ __global__ __launch_bounds__(256) void k_stage(const uint8_t* __restrict__ rgb,
   const float cb = static_cast<float>(rgb[3 * s + 2]) / 255.0f;
   const uint32_t d = f2h(depth[s]);
   rgbd[i] = make_uint2(f2h(cr) | (f2h(cg) << 16), f2h(cb) | (d << 16));
-  depth16[i] = static_cast<uint16_t>(d);
+  dn[di] = static_cast<uint16_t>(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,14 +219,20 @@ __device__ __forceinline__ Tile tile_of_block(int tiles_x, int tiles_y) {
 // Per source frame the (2r+1)^2 depths are loaded unconditionally (apron makes
 // every address valid), so all loads of a block are in flight together.
 
+// Frame j's depth plane as pair words (dplane binary16 entries per frame, an even
+// number, so every plane starts 4-byte aligned when the first one does).
+__device__ __forceinline__ gp<const uint32_t> depth_words(gp<const uint16_t> depth, int j, size_t dplane) {
+  return reinterpret_cast<gp<const uint32_t>>(depth + static_cast<size_t>(j) * dplane);
+}
+
 // Members of output pixel (x, y) of output frame f; relf = the relative maps of f.
 template <int R>
 __device__ __forceinline__ int count_pixel(gp<const uint16_t> depth, gp<const float> relf,
                                            int width, int height, int n_frames, int f, int w, float tol,
                                            float z_near, int x, int y) {
   const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+  const size_t dplane = depth_plane_elems(width, height);
+  const float dp = h2f(depth[static_cast<size_t>(f) * dplane + depth_index(x, y, pw)]);
   int count = 0;
   if (dp > z_near && dp < INFINITY) {
     const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
@@ -257,7 +242,7 @@ __device__ __forceinline__ int count_pixel(gp<const uint16_t> depth, gp<const fl
       if (!project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p))
         continue;
       uint32_t d[2 * R + 1][2 * R + 1];
-      load_block_depths<R>(depth + static_cast<size_t>(j) * pplane, padded_index(p.iu, p.iv, pw), pw, d);
+      load_block_depths<R>(depth_words(depth, j, dplane), p.iu, p.iv, pw, d);
 #pragma unroll
       for (int dy = 0; dy <= 2 * R; ++dy)
 #pragma unroll
@@ -277,8 +262,8 @@ __device__ __forceinline__ int count_pixel_k(gp<const uint16_t> depth, gp<const 
                                              float z_near, int x, int y) {
   if (K == 1) return count_pixel<R>(depth, relf, width, height, n_frames, f, w, tol, z_near, x, y);
   const int pw = stored_pitch(width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(height);
-  const float dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+  const size_t dplane = depth_plane_elems(width, height);
+  const float dp = h2f(depth[static_cast<size_t>(f) * dplane + depth_index(x, y, pw)]);
   int count = 0;
   if (dp > z_near && dp < INFINITY) {
     const int jlo = max(0, f - w), jhi = min(n_frames - 1, f + w);
@@ -293,9 +278,8 @@ __device__ __forceinline__ int count_pixel_k(gp<const uint16_t> depth, gp<const 
         ok[k] = j <= jhi &&
                 project(relf + (j - f + w) * kRelStride, fxp, fyp, dp, z_near, tol, width, height, R, p[k]);
         // a frame past the window or a failed projection reads a valid block of frame jlo
-        const size_t plane = static_cast<size_t>(ok[k] ? j : jlo) * pplane;
-        const uint32_t at = ok[k] ? padded_index(p[k].iu, p[k].iv, pw) : padded_index(0, 0, pw);
-        load_block_depths<R>(depth + plane, at, pw, d[k]);
+        load_block_depths<R>(depth_words(depth, ok[k] ? j : jlo, dplane), ok[k] ? p[k].iu : 0, ok[k] ? p[k].iv : 0,
+                             pw, d[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -482,7 +466,7 @@ __device__ __forceinline__ void scatter_wave(gp<const uint2> rgbd, gp<const uint
     } else if (end > capacity) {
       if (end > cur) flag_or(status, SG_FLAG_CAPACITY);
     } else {
-      dp = h2f(depth[static_cast<size_t>(f) * pplane + padded_index(x, y, pw)]);
+      dp = h2f(depth[static_cast<size_t>(f) * depth_plane_elems(width, height) + depth_index(x, y, pw)]);
       active = dp > z_near && dp < INFINITY;
     }
   }

@@ -182,7 +182,7 @@ struct FeatureArgs {
   gp<const float> rel;        // relative maps of this output frame, [2w+1][kRelStride]
   gp<const uint16_t> depth;   // stored depth planes
   int width, height, n_frames, pw, w;
-  size_t pplane;
+  size_t dplane;  // binary16 entries per depth plane
   float inv_w, cx, cy;
   float inv_fx, inv_fy, inv_width;  // reciprocals, once per kernel (no division per sample)
 };
@@ -197,7 +197,7 @@ __device__ __forceinline__ FeatureArgs feature_args(gp<const uint16_t> depth, in
   fa.n_frames = n_frames;
   fa.pw = stored_pitch(width);
   fa.w = w;
-  fa.pplane = static_cast<size_t>(fa.pw) * stored_rows(height);
+  fa.dplane = depth_plane_elems(width, height);
   fa.inv_w = w > 0 ? 1.0f / static_cast<float>(w) : 0.0f;
   fa.cx = cx;
   fa.cy = cy;
@@ -248,9 +248,11 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   const float ux = ax * ra - bx * rb, uy = ay * ra - by * rb, uz = az * ra - bz * rb;
   const float one_minus_cos = 0.5f * (ux * ux + uy * uy + uz * uz);
   // depth gradient at q in J (apron neighbours read as invalid)
-  gp<const uint16_t> dq = a.depth + static_cast<size_t>(j) * a.pplane + padded_index(qx, qy, a.pw);
-  const float d0 = h2f(dq[0]);
-  const float dxp = h2f(dq[1]), dxm = h2f(dq[-1]), dyp = h2f(dq[a.pw]), dym = h2f(dq[-a.pw]);
+  gp<const uint16_t> dpl = a.depth + static_cast<size_t>(j) * a.dplane;
+  const uint32_t iq = depth_index(qx, qy, a.pw);  // row neighbours are two entries away
+  const float d0 = h2f(dpl[iq]);
+  const float dxp = h2f(dpl[iq + 2]), dxm = h2f(dpl[iq - 2]);
+  const float dyp = h2f(dpl[depth_index(qx, qy + 1, a.pw)]), dym = h2f(dpl[depth_index(qx, qy - 1, a.pw)]);
   float gx = 0.0f, gy = 0.0f;
   const bool vxp = valid_depth(dxp), vxm = valid_depth(dxm), vyp = valid_depth(dyp), vym = valid_depth(dym);
   if (vxp && vxm) gx = 0.5f * (dxp - dxm); else if (vxp) gx = dxp - d0; else if (vxm) gx = d0 - dxm;
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(256) void k_filter_learned(
       q.cref[2] = h2f(ref.y);
       q.x = static_cast<float>(x);
       q.y = static_cast<float>(y);
-      q.dp = h2f(depth[pi]);
+      q.dp = h2f(ref.y >> 16);  // the depth channel holds the depth plane's binary16
       q.s = offsets[pix];
       q.e = offsets[pix + 1];
       q.x7 = __logf(1.0f + static_cast<float>(q.e - q.s)) / log_norm;
@@ -827,8 +829,6 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
   const float b3 = ta.mb[kOffB3];
 
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
-  const int pw = stored_pitch(ta.width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
   FeatureArgs fa = feature_args(ta.depth, ta.width, ta.height, ta.n_frames, ta.w, ta.fx, ta.fy, ta.cx, ta.cy);
 
   // dW2 accumulators: tile (ti, tj), element a = dW2[32 ti + 8(a/4) + 4 hi32 + a%4][32 tj + col]
@@ -850,13 +850,12 @@ __global__ __launch_bounds__(64) void k_mlp_train_grad(TrainArgs ta_in) {
     const int fo = static_cast<int>(pix / static_cast<int64_t>(plane));
     const int64_t self = pix - static_cast<int64_t>(fo) * plane;
     const int y = static_cast<int>(self / ta.width), x = static_cast<int>(self - static_cast<int64_t>(y) * ta.width);
-    const size_t pi = static_cast<size_t>(ta.f0 + fo) * pplane + padded_index(x, y, pw);
     const int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
     if (s < 0 || e <= s || e > ta.capacity) continue;
     PixelCtx px;
     px.x = static_cast<float>(x);
     px.y = static_cast<float>(y);
-    px.dp = h2f(ta.depth[pi]);
+    px.dp = depth_at(ta.depth, ta.width, ta.height, ta.f0 + fo, x, y);
     px.f = ta.f0 + fo;
     px.x7 = __logf(1.0f + static_cast<float>(e - s)) / ta.log_norm;
     set_median<64>(ta.crho, s, e, lane, px.medr, px.medg, px.medb);
@@ -1123,8 +1122,6 @@ __global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta_in, double*
   const TrainDev ta = dev_args(ta_in);
   const int lane = threadIdx.x;
   const size_t plane = static_cast<size_t>(ta.width) * ta.height;
-  const int pw = stored_pitch(ta.width);
-  const size_t pplane = static_cast<size_t>(pw) * stored_rows(ta.height);
   FeatureArgs fa = feature_args(ta.depth, ta.width, ta.height, ta.n_frames, ta.w, ta.fx, ta.fy, ta.cx, ta.cy);
   double cnt = 0.0, sum[kNF], sq[kNF];
 #pragma unroll
@@ -1135,13 +1132,12 @@ __global__ __launch_bounds__(64) void k_feature_moments(TrainArgs ta_in, double*
     const int fo = static_cast<int>(pix / static_cast<int64_t>(plane));
     const int64_t self = pix - static_cast<int64_t>(fo) * plane;
     const int y = static_cast<int>(self / ta.width), x = static_cast<int>(self - static_cast<int64_t>(y) * ta.width);
-    const size_t pi = static_cast<size_t>(ta.f0 + fo) * pplane + padded_index(x, y, pw);
     const int64_t s = ta.offsets[pix], e = ta.offsets[pix + 1];
     if (s < 0 || e <= s || e > ta.capacity) continue;
     PixelCtx px;
     px.x = static_cast<float>(x);
     px.y = static_cast<float>(y);
-    px.dp = h2f(ta.depth[pi]);
+    px.dp = depth_at(ta.depth, ta.width, ta.height, ta.f0 + fo, x, y);
     px.f = ta.f0 + fo;
     px.x7 = __logf(1.0f + static_cast<float>(e - s)) / ta.log_norm;
     set_median<64>(ta.crho, s, e, lane, px.medr, px.medg, px.medb);

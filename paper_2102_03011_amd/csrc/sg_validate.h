@@ -18,6 +18,9 @@ inline sg_status check_clip(const sg_clip* c, bool need_depth) {
   if (c->width <= 0 || c->height <= 0 || c->num_frames <= 0) return SG_E_INVALID;
   if (c->rgbd == nullptr || c->cam_to_world == nullptr) return SG_E_INVALID;
   if (need_depth && c->depth == nullptr) return SG_E_INVALID;
+  // the gather reads rgbd as 8-byte pixels and the depth plane as 32-bit row pairs
+  if ((reinterpret_cast<uintptr_t>(c->rgbd) & 7u) != 0 || (reinterpret_cast<uintptr_t>(c->depth) & 3u) != 0)
+    return SG_E_INVALID;
   if (!isfinite(c->fx) || !isfinite(c->fy) || c->fx == 0.0 || c->fy == 0.0) return SG_E_INVALID;
   if (!isfinite(c->cx) || !isfinite(c->cy)) return SG_E_INVALID;
   if (static_cast<int64_t>(c->width) * c->height > SG_MAX_PIXELS_PER_FRAME) return SG_E_UNSUPPORTED;

@@ -91,11 +91,15 @@ def test_stage_bit_exact(small):
     # the apron: binary16 NaN depth in both planes, zero colour
     a = sg_apron = _sg().SG_APRON
     full = staged.rgbd.cpu().numpy().view(np.uint16)
-    dfull = staged.depth.cpu().numpy().view(np.uint16)
+    drows = staged.depth_rows().cpu().numpy().view(np.uint16)
+    sh = full.shape[1]
+    dfull = drows[:, :sh]
     ring = np.ones(full.shape[:3], bool)
     ring[:, a:a + clip.height, a:a + clip.width] = False
     assert full.shape[2] == clip.width + a + _sg().SG_APRON_RIGHT and full.shape[1] == clip.height + 2 * a
     assert sg_apron >= 3 and np.all(dfull[ring] == 0x7E00) and np.all(full[ring][:, 3] == 0x7E00)
+    # the depth plane pairs stored rows: an odd row count leaves one more apron row
+    assert drows.shape[1] == sh + (sh & 1) and np.all(drows[:, sh:] == 0x7E00)
     assert np.all(full[ring][:, :3] == 0)
     sg = _sg()
     allv = torch.arange(256, dtype=torch.uint8).repeat_interleave(3).reshape(1, 16, 16, 3).cuda()
@@ -106,6 +110,14 @@ def test_stage_bit_exact(small):
     assert np.array_equal(got[..., :3].reshape(256, 3), want_c.astype(np.float16).view(np.uint16))
     want_d = ostaging.depth_q(d.cpu().numpy()).astype(np.float16).view(np.uint16)
     assert np.array_equal(got[..., 3], want_d)
+    # an odd number of stored rows: the row-paired depth plane holds every stored row
+    # (equal to the depth channel) and one more apron row
+    s2 = sg.scene_stage(allv[:, :15].contiguous(), d[:, :15].contiguous(),
+                        torch.eye(4, dtype=torch.float64).reshape(1, 4, 4).cuda(), 1, 1, 0, 0)
+    r2 = s2.depth_rows().cpu().numpy().view(np.uint16)
+    c2 = s2.rgbd.cpu().numpy().view(np.uint16)[..., 3]
+    assert c2.shape[1] % 2 == 1 and r2.shape[1] == c2.shape[1] + 1
+    assert np.array_equal(r2[:, :-1], c2) and np.all(r2[:, -1] == 0x7E00)
 
 
 @pytest.mark.parametrize("f", list(range(24)))

@@ -31,7 +31,7 @@ def sg():
 def _host_clip(sg, n=3, h=8, w=10):
     a, ar = sg.SG_APRON, sg.SG_APRON_RIGHT
     return sg.StagedClip(torch.zeros((n, h + 2 * a, w + a + ar, 4), dtype=torch.float16),
-                         torch.zeros((n, h + 2 * a, w + a + ar), dtype=torch.float16),
+                         torch.zeros((n, (h + 2 * a + 1) // 2, w + a + ar, 2), dtype=torch.float16),
                          torch.eye(4, dtype=torch.float64).repeat(n, 1, 1), 50.0, 50.0, 4.5, 3.5)
 
 
