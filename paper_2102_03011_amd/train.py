@@ -135,6 +135,7 @@ def evaluate(params: sg.MLPParams, n_clips: int = 20, frames_per_clip: int = 3, 
                 learned = sg.scene_filter_learned(staged, fs.sets, fs.params, params, ws=fs.ws)[0]
                 rows[w].append((psnr(noisy, clean), psnr(plain, clean), psnr(learned, clean)))
         del clip, staged
+        log(f"eval: held-out clip {i + 1} of {n_clips} done")
     out = {"clips": n_clips, "frames": n_clips * frames_per_clip}
     for w in windows:
         r = np.array(rows[w])
@@ -205,9 +206,17 @@ def main(argv=None):
     ap.add_argument("--noise-mix", action="store_true", help="draw noise levels and movers per clip")
     ap.add_argument("--eval-windows", default="30")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--eval-only", metavar="WEIGHTS", default=None,
+                    help="no training: evaluate these weights on --eval-clips held-out clips and print the result")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("training needs a GPU")
+    if a.eval_only is not None:
+        params, _ = load_mlp(a.eval_only)
+        res = evaluate(params, a.eval_clips, log=lambda s: print(s, flush=True),
+                       windows=tuple(int(x) for x in a.eval_windows.split(",")))
+        print(json.dumps({"weights": a.eval_only, "eval": res}), flush=True)
+        return
     windows = tuple(int(x) for x in a.windows.split(","))
     params, meta = train(a.clips, a.frames_per_clip, a.steps_per_frame, a.batch, a.lr, a.lr / 10, seed=a.seed,
                          log=lambda s: print(s, flush=True), windows=windows, noise_mix=a.noise_mix)
