@@ -93,7 +93,7 @@ def test_workspace_size(native):
     ("null_clip", 1), ("f_empty", 1), ("f_past_end", 1), ("neg_window", 1), ("neg_radius", 1),
     ("big_window", 4), ("big_radius", 4), ("tol_zero", 1), ("tol_nan", 1), ("znear_neg", 1),
     ("too_many_pixels", 4), ("zero_fx", 1), ("null_sets", 1), ("null_ws", 1), ("small_ws", 1),
-    ("neg_capacity", 1), ("null_arena", 1), ("null_rgbd", 1),
+    ("neg_capacity", 1), ("null_arena", 1), ("null_rgbd", 1), ("rgbd_unaligned", 1), ("depth_unaligned", 1),
 ])
 def test_gather_rejects_bad_arguments(native, case, expect):
     mod, lib = native
@@ -138,6 +138,10 @@ def test_gather_rejects_bad_arguments(native, case, expect):
         s.ids = None
     elif case == "null_rgbd":
         c.rgbd = None
+    elif case == "rgbd_unaligned":      # 8-byte pixels
+        c.rgbd = 0x10004
+    elif case == "depth_unaligned":     # 32-bit row-pair words
+        c.depth = 0x20002
     sp = ctypes.byref(s) if s is not None else None
     for fn in (lib.scene_gather, lib.scene_gather_scatter):
         assert fn(cp, f0, f1, ctypes.byref(p), sp, ws, wsb, None) == expect, (case, fn)
@@ -408,6 +412,9 @@ def test_stage_rejects_bad_arguments(native):
     assert lib.scene_stage(0x1000, 0x1000, 2, 64, 32, None, 0x3000, None) == 1
     assert lib.scene_stage(0x1000, 0x1000, 2, 4097, 1024, 0x2000, 0x3000, None) == 4
     assert lib.scene_stage(0x1000, 0x1000, 70000, 64, 32, 0x2000, 0x3000, None) == 4
+    # stored planes must be aligned for the gather's reads: rgbd 8 bytes, depth 4
+    assert lib.scene_stage(0x1000, 0x1000, 2, 64, 32, 0x2004, 0x3000, None) == 1
+    assert lib.scene_stage(0x1000, 0x1000, 2, 64, 32, 0x2000, 0x3002, None) == 1
 
 
 def _mlp(mod):
