@@ -114,9 +114,9 @@ __device__ __forceinline__ void load_block_depths(gp<const uint32_t> plane, int 
 
 // The block of stored (r, g, b, depth) pixels around plane entry `at`: each block
 // row is fetched as 16-byte loads of two pixels and one 8-byte load of its last
-// pixel (three load instructions per row at r = 1 instead of one per pixel; a
-// wave's load touches about as many cache lines either way, and the vector memory
-// path's cost goes with the lines each instruction touches).
+// pixel (two load instructions per row at r = 1 instead of three; a wave's 16-byte
+// load touches about as many cache lines as an 8-byte one, and the vector memory
+// path's cost goes with the (instruction, cache line) pairs it serves).
 typedef uint64_t __attribute__((ext_vector_type(2))) PixelPairV;
 typedef PixelPairV __attribute__((aligned(8))) PixelPair;  // two stored pixels, 8-byte aligned
 
