@@ -247,12 +247,20 @@ __device__ __forceinline__ void sample_features(const FeatureArgs& a, const Pixe
   const float ra = rsqrtf(ax * ax + ay * ay + az * az), rb = rsqrtf(bx * bx + by * by + bz * bz);
   const float ux = ax * ra - bx * rb, uy = ay * ra - by * rb, uz = az * ra - bz * rb;
   const float one_minus_cos = 0.5f * (ux * ux + uy * uy + uz * uz);
-  // depth gradient at q in J (apron neighbours read as invalid)
-  gp<const uint16_t> dpl = a.depth + static_cast<size_t>(j) * a.dplane;
-  const uint32_t iq = depth_index(qx, qy, a.pw);  // row neighbours are two entries away
-  const float d0 = h2f(dpl[iq]);
-  const float dxp = h2f(dpl[iq + 2]), dxm = h2f(dpl[iq - 2]);
-  const float dyp = h2f(dpl[depth_index(qx, qy + 1, a.pw)]), dym = h2f(dpl[depth_index(qx, qy - 1, a.pw)]);
+  // depth gradient at q in J (apron neighbours read as invalid), from the paired
+  // depth plane: the words of columns qx - 1 .. qx + 1 in q's pair row hold q's row
+  // and one vertical neighbour; one word of the pair row above (q on the pair's
+  // first row) or below (on its second) holds the other
+  gp<const uint32_t> dw = reinterpret_cast<gp<const uint32_t>>(a.depth + static_cast<size_t>(j) * a.dplane);
+  const uint32_t row = static_cast<uint32_t>(qy + SG_APRON);
+  const uint32_t at = __umul24(row >> 1, static_cast<uint32_t>(a.pw)) + static_cast<uint32_t>(qx + SG_APRON);
+  const uint32_t wl = dw[at - 1], wc = dw[at], wr = dw[at + 1];
+  const bool second = (row & 1u) != 0u;
+  const uint32_t wo = dw[second ? at + static_cast<uint32_t>(a.pw) : at - static_cast<uint32_t>(a.pw)];
+  const uint32_t sh = second ? 16u : 0u;
+  const float d0 = h2f(wc >> sh);
+  const float dxp = h2f(wr >> sh), dxm = h2f(wl >> sh);
+  const float dyp = h2f(second ? wo : wc >> 16), dym = h2f(second ? wc : wo >> 16);
   float gx = 0.0f, gy = 0.0f;
   const bool vxp = valid_depth(dxp), vxm = valid_depth(dxm), vyp = valid_depth(dyp), vym = valid_depth(dym);
   if (vxp && vxm) gx = 0.5f * (dxp - dxm); else if (vxp) gx = dxp - d0; else if (vxm) gx = d0 - dxm;
