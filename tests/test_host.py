@@ -102,3 +102,22 @@ def test_bench_oracle_worker_reads_shared_planes_and_matches_the_oracle():
     assert got["samples"] == want.ids.size > 0
     # certain members: the oracle's members outside its float32 bands
     assert got["certain"].size == int((~want.marginal).sum())
+
+
+@pytest.mark.parametrize("h", [8, 9])
+def test_paired_depth_plane_views(sg, h):
+    """The staged depth plane pairs its stored rows ([N][ceil(SH/2)][SW][2], entry
+    [n][P][X][s] = stored row 2P + s): depth_rows() undoes the pairing and
+    depth_image() cuts the image out of it (odd SH: one extra apron row)."""
+    n, w = 2, 10
+    a, ar = sg.SG_APRON, sg.SG_APRON_RIGHT
+    sh, sw = h + 2 * a, w + a + ar
+    rows = torch.arange(n * 2 * ((sh + 1) // 2) * sw, dtype=torch.float32).reshape(n, -1, sw)
+    paired = rows.reshape(n, -1, 2, sw).permute(0, 1, 3, 2).contiguous().to(torch.float16)
+    clip = sg.StagedClip(torch.zeros((n, sh, sw, 4), dtype=torch.float16), paired,
+                         torch.eye(4, dtype=torch.float64).repeat(n, 1, 1), 50.0, 50.0, 4.5, 3.5)
+    assert clip.height == h and clip.width == w
+    assert torch.equal(clip.depth_rows(), rows.to(torch.float16))
+    assert torch.equal(clip.depth_image(), rows[:, a:a + h, a:a + w].to(torch.float16))
+    # entry (P, X, s) of frame 1 is stored row 2P + s, column X
+    assert paired[1, 3, 5, 1] == rows[1, 7, 5].to(torch.float16)
